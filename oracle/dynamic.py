@@ -1,0 +1,133 @@
+"""Static CSC and dynamic CSC (Algorithm 1 of Sec. 4.1), in FP64.
+
+Static CSC (Sec. 2.2, Step 1 with lambda_k from an eigencount dichotomy): filter d
+Gaussian signals of variance 1/d with the polynomial low-pass at lambda_k and run
+k-means on the rows.
+
+Dynamic CSC keeps, at snapshot t >= 2, a fraction p of the filtered columns of earlier
+snapshots and filters only q d = (1 - p) d fresh signals on G_t with the previous
+filter h^{t-1} (eq. features_f).  The eigencount of those fresh columns decides whether
+h^{t-1} still fits G_t; if not, lambda is refined by a dichotomy that starts from the
+previous value and the fresh columns are filtered again.  k-means then runs on the
+combined features.
+
+Readings where the paper is silent or leaves a choice
+  * snapshot 1 uses the d feature columns themselves as eigencount probes;
+  * the d columns form d / (q d) blocks used as a FIFO ring: the block filtered longest
+    ago is replaced (for p <= 1/2 the kept block always comes from G_{t-1}, as the
+    paper assumes; for p > 1/2 blocks live ceil(p / q) snapshots);
+  * acceptance |c - k| <= tau with tau = max(0.5, 2 sqrt(2 k / (q d)));
+  * refinement bisects [lambda_{t-1}, lmax] when c < k and [0, lambda_{t-1}] otherwise;
+  * random draws come from Philox4x32-10 with stream id 16 t + purpose (signals 1,
+    k-means uniforms 2), see :mod:`oracle.philox`;
+  * k-means: k-means++ seeding then a fixed number of Lloyd rounds, or a warm start
+    from the previous labels (means of the new features under the old labels).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import chebyshev, eigcount, kmeans, operator, philox
+
+SIGNALS = 1
+KMEANS = 2
+
+
+def stream_id(t: int, purpose: int) -> int:
+    return 16 * int(t) + int(purpose)
+
+
+@dataclass
+class StepResult:
+    t: int
+    lam: float
+    count: float
+    refined: bool
+    labels: np.ndarray
+    centroids: np.ndarray
+    objective: list = field(default_factory=list)
+
+
+def run_kmeans(F: np.ndarray, k: int, iters: int, seed: int, t: int, init: str,
+               prev_labels: np.ndarray | None):
+    if init == "warm" and prev_labels is not None:
+        C0, _ = kmeans.update(F, prev_labels, np.zeros((k, F.shape[1])))
+    else:
+        u = philox.uniforms(k, seed, stream_id(t, KMEANS))
+        C0 = np.asarray(F, dtype=np.float64)[kmeans.kmeanspp(F, k, u)]
+    return kmeans.lloyd(F, C0, iters)
+
+
+class DynamicCSC:
+    def __init__(self, n: int, d: int, k: int, p: float, m: int, seed: int,
+                 lmax: float = 2.0, damping: str = "jackson", n_cand: int = 16,
+                 lloyd_iters: int = 20, tau: float | None = None, init: str = "kmeans++",
+                 storage=np.float64):
+        self.n, self.d, self.k, self.p, self.m = n, d, k, p, m
+        self.qd = int(round((1.0 - p) * d))
+        if self.qd < 1 or d % self.qd != 0:
+            raise ValueError("(1 - p) d must be a positive divisor of d")
+        self.nblocks = d // self.qd
+        self.seed = seed
+        self.lmax = lmax
+        self.damping = damping
+        self.n_cand = n_cand
+        self.lloyd_iters = lloyd_iters
+        self.tau = eigcount.accept_tolerance(k, self.qd) if tau is None else tau
+        self.init = init
+        self.storage = storage
+        self.sigma = 1.0 / np.sqrt(d)
+        self.theta = np.zeros((n, d))
+        self.t = 0
+        self.lam = None
+        self.next_block = 0
+        self.labels = None
+
+    def _signals(self, w: int, t: int) -> np.ndarray:
+        R = philox.gaussian_block(self.n, w, self.sigma, self.seed, stream_id(t, SIGNALS),
+                                  dtype=self.storage)
+        return np.asarray(R, dtype=np.float64)
+
+    def step(self, g) -> StepResult:
+        """Process the next snapshot, given as a CSR weight matrix (workloads.Graph)."""
+        A, _ = operator.normalized_adjacency(g.n, g.rowptr, g.colidx, g.w)
+        self.t += 1
+        t = self.t
+        sigma2 = self.sigma ** 2
+        if t == 1:
+            R = self._signals(self.d, t)
+            mu = eigcount.moments_direct(A, self.lmax, self.m, R)
+            lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, self.lmax, self.damping,
+                                                   sigma2, self.d, self.k, self.n_cand,
+                                                   0.0, self.lmax)
+            a = chebyshev.step_coefficients(self.m, self.lmax, lam, self.damping)
+            self.theta = chebyshev.filter_recurrence(A, self.lmax, a, R)
+            refined = True
+        else:
+            R = self._signals(self.qd, t)
+            a = chebyshev.step_coefficients(self.m, self.lmax, self.lam, self.damping)
+            Y = chebyshev.filter_recurrence(A, self.lmax, a, R)
+            cnt = float(np.sum(R * Y) / (sigma2 * self.qd))
+            lam = self.lam
+            refined = False
+            if abs(cnt - self.k) > self.tau:
+                mu = eigcount.moments_direct(A, self.lmax, self.m, R)
+                lo, hi = (self.lam, self.lmax) if cnt < self.k else (0.0, self.lam)
+                lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, self.lmax, self.damping,
+                                                       sigma2, self.qd, self.k, self.n_cand,
+                                                       lo, hi)
+                a = chebyshev.step_coefficients(self.m, self.lmax, lam, self.damping)
+                Y = chebyshev.filter_recurrence(A, self.lmax, a, R)
+                refined = True
+            b = self.next_block
+            self.theta[:, b * self.qd:(b + 1) * self.qd] = Y
+            self.next_block = (b + 1) % self.nblocks
+        self.lam = lam
+        lab, C, obj = run_kmeans(self.theta, self.k, self.lloyd_iters, self.seed, t,
+                                 self.init, self.labels)
+        self.labels = lab
+        return StepResult(t=t, lam=lam, count=cnt, refined=refined, labels=lab,
+                          centroids=C, objective=obj)
