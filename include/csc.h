@@ -1,0 +1,302 @@
+/*
+ * csc.h -- C ABI of libcsc: compressive spectral clustering of static and dynamic graphs
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the statement of the problem in Martin, Loukas and Vandergheynst,
+ * "Fast Approximate Spectral Clustering for Dynamic Networks" (ICML 2017): a graph
+ * sequence G_1..G_tau, a reuse fraction p and a number of random signals d give one
+ * assignment per snapshot (Algorithm 1, Sec. 4.1), built on polynomial filtering of
+ * random signals (Sec. 2.2, Step 1) with a cut-off found by eigencount (Sec. 3.2).
+ *
+ * Conventions shared by every call
+ *  - Every call returns csc_status; nothing throws across the ABI.  csc_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - "device" pointers are HIP device allocations owned by the caller; the library never
+ *    frees them.  "host" pointers are ordinary host memory.
+ *  - Work is enqueued on the caller's hipStream_t, passed as void* (NULL = the null
+ *    stream).  Calls documented as "synchronising" wait for that stream before returning
+ *    host results; all others are asynchronous.
+ *  - Dense blocks are row-major: element (i, j) of an n x w block X with leading
+ *    dimension ldx (in elements, ldx >= w) is X[i * ldx + j].
+ *  - Handles (csc_graph, csc_dyn) own their internal device memory; it is allocated only
+ *    in *_create.  Scratch memory of the other calls comes from a caller buffer `work`
+ *    whose size is given by the matching *_workspace_bytes query; a too-small buffer is
+ *    CSC_E_ARG.
+ *  - Results are deterministic given the inputs and seeds: every floating-point
+ *    reduction runs in a fixed order (no floating-point atomics).
+ */
+#ifndef CSC_H
+#define CSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CSC_OK = 0,
+  CSC_E_ARG = 1,    /* invalid argument (size, range, alignment, aliasing, workspace) */
+  CSC_E_GRAPH = 2,  /* the CSR input is not a simple symmetric graph with w > 0 */
+  CSC_E_DTYPE = 3,  /* unsupported element type for this argument */
+  CSC_E_NOMEM = 4,  /* device allocation failed (only in *_create) */
+  CSC_E_HIP = 5,    /* a HIP runtime call failed */
+  CSC_E_STATE = 6   /* handle used out of order */
+} csc_status;
+
+typedef enum { CSC_F32 = 0, CSC_BF16 = 1, CSC_F64 = 2 } csc_dtype;
+
+typedef enum { CSC_DAMP_NONE = 0, CSC_DAMP_JACKSON = 1 } csc_damping;
+
+typedef struct csc_graph_s* csc_graph;
+typedef struct csc_dyn_s* csc_dyn;
+
+/* Thread-local description of the last error (never NULL). */
+const char* csc_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int csc_version(void);
+
+/* ---------------------------------------------------------------------------------
+ * Graph operator (Sec. 2.1).  From the symmetric weight matrix W in CSR form, builds the
+ * normalized adjacency A = D^{-1/2} W D^{-1/2} on the device, so that the normalized
+ * Laplacian is L = I - A.  An isolated node (degree 0) gets D^{-1/2} = 0, i.e. an
+ * identity row in L and eigenvalue 1; their number is reported by csc_graph_info.
+ *
+ * rowptr_d: device int64[n + 1]; colidx_d: device int32[nnz], sorted strictly increasing
+ * within each row; w_d: device double[nnz], all > 0.  No self-loops; W symmetric (entry
+ * (i, j) present with the same weight as (j, i)).  With validate != 0 every one of these
+ * properties is checked on the device and a violation returns CSC_E_GRAPH (the call then
+ * synchronises `stream`); with validate == 0 the caller guarantees them.
+ * val_dt: storage type of A's values (CSC_F32 or CSC_BF16).  nnz_capacity >= nnz sizes
+ * the handle so that csc_graph_update can later load a graph with up to that many
+ * entries without allocating.  The handle copies what it needs; the inputs may be freed
+ * once `stream` has passed the call.
+ */
+csc_status csc_graph_create(int64_t n, int64_t nnz, int64_t nnz_capacity,
+                            const int64_t* rowptr_d, const int32_t* colidx_d,
+                            const double* w_d, csc_dtype val_dt, int validate,
+                            void* stream, csc_graph* out);
+/* Rebuild the operator of an existing handle from a new W with the same n and
+ * nnz <= nnz_capacity (a new snapshot of a dynamic graph).  Allocates nothing. */
+csc_status csc_graph_update(csc_graph g, int64_t nnz, const int64_t* rowptr_d,
+                            const int32_t* colidx_d, const double* w_d, int validate,
+                            void* stream);
+csc_status csc_graph_destroy(csc_graph g);
+/* Sizes and the number of isolated nodes (synchronising). */
+csc_status csc_graph_info(csc_graph g, int64_t* n, int64_t* nnz, int64_t* isolated);
+/* Device views of the operator: int32 row pointers (n + 1), int32 column indices, A's
+ * values (type *val_dt), D^{-1/2} as double[n], and for every entry e = (i, j) the index
+ * of its mirror entry (j, i).  Valid until the next update or destroy. */
+csc_status csc_graph_arrays(csc_graph g, const int32_t** rowptr, const int32_t** colidx,
+                            void** vals, csc_dtype* val_dt, const double** dinv,
+                            const int32_t** mirror);
+
+/* Upper bound of the spectrum of L used to map [0, lmax] onto [-1, 1] (Sec. 3.2 gives
+ * none).  iters == 0 returns 2, the exact bound of the normalized Laplacian.  iters > 0
+ * runs that many power iterations on L from a fixed pseudo-random start and returns
+ * 1.01 (rho + r), clamped to at most 2, where rho is the last Rayleigh quotient and r the
+ * norm of its residual L x - rho x (|x| = 1).  Allocates temporary device memory.
+ * Synchronising. */
+csc_status csc_lmax(csc_graph g, int iters, double* lmax, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Chebyshev coefficients of the ideal low-pass (Sec. 3.2): h(lambda) = sum_{j=0..m}
+ * a[j] T_j(2 lambda / lmax - 1) approximates the step 1[lambda <= lambda_c] of the
+ * ideal filter H_k (eq. Hk): a[0] = 1 - theta_c / pi and a[j] = -2 sin(j theta_c) /
+ * (j pi) with theta_c = arccos(2 lambda_c / lmax - 1), each multiplied by the Jackson
+ * factor when damp == CSC_DAMP_JACKSON.  a: host double[m + 1].  Host only.
+ */
+csc_status csc_cheb_coeffs(int m, double lmax, double lambda_c, csc_damping damp, double* a);
+
+/* ---------------------------------------------------------------------------------
+ * Chebyshev filtering of a block of signals (Sec. 2.2, Step 1, and Sec. 3.2):
+ *     Y = sum_{j=0..m} a[j] T_j(L~) X,  L~ = (2 / lmax) L - I,
+ * by the three-term recurrence Z_0 = X, Z_1 = L~ X, Z_{j+1} = 2 L~ Z_j - Z_{j-1}, each
+ * step one fused kernel (sparse product, recurrence and coefficient accumulation).
+ *
+ * X: device n x w block, type x_dt (F32/BF16/F64), leading dimension ldx.
+ * Y: device n x w block, type y_dt (F32/BF16/F64), leading dimension ldy; must not
+ *    overlap X.  a: host double[m + 1].  iter_dt: storage type of the iterates Z_j
+ *    (CSC_F32, or CSC_BF16 to halve their traffic); arithmetic is always FP32.
+ * moments: NULL, or device double[m + 1] receiving mu_j = <X, T_j(L~) X> (summed over the
+ *    w columns) for j = 0..m, obtained during the same pass from the doubling identities
+ *    T_j^2 = (T_2j + T_0) / 2 and T_{j+1} T_j = (T_2j+1 + T_1) / 2.
+ * work: device scratch of csc_cheb_filter_workspace_bytes(n, w, iter_dt) bytes.
+ * Asynchronous.
+ */
+size_t csc_cheb_filter_workspace_bytes(int64_t n, int w, csc_dtype iter_dt);
+csc_status csc_cheb_filter(csc_graph g, double lmax, int m, const double* a, const void* X,
+                           csc_dtype x_dt, int64_t ldx, void* Y, csc_dtype y_dt, int64_t ldy,
+                           int w, csc_dtype iter_dt, double* moments, void* work,
+                           size_t work_bytes, void* stream);
+
+/* Chebyshev moments only: mu_j = <P, T_j(L~) P> for j = 0..m (device double[m + 1]) from
+ * floor(m / 2) + 1 operator products (doubling).  m >= 1.  Asynchronous. */
+csc_status csc_cheb_moments(csc_graph g, double lmax, int m, const void* P, csc_dtype p_dt,
+                            int64_t ldp, int n_probe, csc_dtype iter_dt, double* moments,
+                            void* work, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Eigencount and dichotomy for the cut-off (Sec. 3.2; Sec. 4.1).  The count below a
+ * cut-off lambda is Hutchinson's estimate c(lambda) = sum_j a_j(lambda) mu_j /
+ * (sigma2 * n_probe) with mu the Chebyshev moments of the probes P (n x n_probe, i.i.d.
+ * entries of variance sigma2).  The dichotomy runs n_cand fixed steps on [lo, hi]:
+ * mid = (lo + hi) / 2, lo = mid when c(mid) < k, else hi = mid; it returns
+ * *lambda_c = hi and *count = c(hi).  trace (host double[2 * n_cand] or NULL) receives
+ * (mid, c(mid)) per step; moments_out (host double[m + 1] or NULL) the moments.
+ * One device pass over the probes, then host FP64 arithmetic.  Synchronising.
+ */
+csc_status csc_eigcount(csc_graph g, double lmax, int m, csc_damping damp, const void* P,
+                        csc_dtype p_dt, int64_t ldp, int n_probe, double sigma2, double k,
+                        int n_cand, double lo, double hi, csc_dtype iter_dt,
+                        double* lambda_c, double* count, double* trace,
+                        double* moments_out, void* work, size_t work_bytes, void* stream);
+/* The host half of csc_eigcount, from moments already on the host.  Host only. */
+csc_status csc_eigcount_from_moments(const double* mu, int m, double lmax, csc_damping damp,
+                                     double sigma2, int n_probe, double k, int n_cand,
+                                     double lo, double hi, double* lambda_c, double* count,
+                                     double* trace);
+
+/* <X, Y> over an n x w block pair in FP64 with a fixed reduction order (device double[1]
+ * result).  Used for the eigencount of filtered signals, c = <P, h(L) P> / (sigma2 w).
+ * work: csc_dot_workspace_bytes(n).  Asynchronous. */
+size_t csc_dot_workspace_bytes(int64_t n);
+csc_status csc_dot(const void* X, csc_dtype x_dt, int64_t ldx, const void* Y, csc_dtype y_dt,
+                   int64_t ldy, int64_t n, int w, double* result, void* work,
+                   size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Random signals (Sec. 2.2): X (device n x w, type dt, leading dimension ldx) gets
+ * i.i.d. N(0, sigma^2) entries from Philox4x32-10 (Salmon et al., SC 2011): for row i and
+ * column pair q the counter is (i, q, stream_id_lo, stream_id_hi) and the key
+ * (seed_lo, seed_hi); the four output words give two 53-bit uniforms u1, u2 in (0, 1)
+ * and Box-Muller gives columns 2q and 2q + 1 (FP64, rounded once).  row0 offsets the
+ * row index (to draw a slice of a larger block).  Asynchronous.
+ */
+csc_status csc_randn(void* X, csc_dtype dt, int64_t n, int w, int64_t ldx, int64_t row0,
+                     uint64_t seed, uint64_t stream_id, double sigma, void* stream);
+/* count uniforms in (0, 1) of (seed, stream_id): counter (j, 0, stream lo, stream hi).
+ * u: device double[count].  Asynchronous. */
+csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * k-means on the rows of the features (Sec. 2.1, eq. SC_cost).
+ *
+ * csc_kmeans_assign: labels[i] = argmin_c sum_t (F[i, t] - C[c, t])^2 for the n rows of
+ * F (device, type f_dt, leading dimension ldf, d columns) and the k centroids C (device
+ * float[k * d], row-major).  Candidates are ranked in FP32 and the two best re-scored in
+ * FP64, exact ties going to the lowest index.  labels: device int32[n]; best_d2: device
+ * float[n] or NULL.  Asynchronous.
+ *
+ * csc_kmeans_update: C[c] = mean of the rows labelled c; an empty cluster keeps its
+ * previous centroid (C is read and overwritten); counts: device int32[k] or NULL.
+ * Fixed-order reduction.  work: csc_kmeans_workspace_bytes(n, d, k).  Asynchronous.
+ *
+ * csc_kmeans_seed: k-means++ (Arthur and Vassilvitskii, 2007) driven by the device
+ * uniforms u[0..k-1]: the first centre is row floor(u[0] n); centre j is the first row
+ * whose running sum of squared distances (FP64) to the chosen centres exceeds u[j] times
+ * their total.  Writes C (device float[k * d]) and idx (device int32[k] or NULL).
+ * Asynchronous.
+ *
+ * csc_kmeans: seeding (init == 0, uniforms of (seed, stream_id)) or the given C
+ * (init == 1), then `iters` rounds of assign + update and a final assignment.
+ * objective: host double[iters + 1] or NULL (sum of squared distances of each assignment;
+ * synchronising when given).
+ */
+size_t csc_kmeans_workspace_bytes(int64_t n, int d, int k);
+csc_status csc_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                             const float* C, int k, int32_t* labels, float* best_d2,
+                             void* stream);
+csc_status csc_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                             const int32_t* labels, int k, float* C, int32_t* counts,
+                             void* work, size_t work_bytes, void* stream);
+csc_status csc_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                           int k, const double* u, float* C, int32_t* idx, void* work,
+                           size_t work_bytes, void* stream);
+csc_status csc_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d, int k,
+                      int iters, int init, uint64_t seed, uint64_t stream_id, float* C,
+                      int32_t* labels, double* objective, void* work, size_t work_bytes,
+                      void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Dynamic compressive spectral clustering (Algorithm 1, Sec. 4.1).
+ *
+ * The state keeps the n x d features Theta as d / (q d) column blocks, q = 1 - p, used as
+ * a FIFO ring (for p <= 1/2 the kept columns are exactly those filtered on G_{t-1}), the
+ * cut-off of the previous snapshot, and the previous labels.
+ *  - The first call runs static CSC on G_1 (Algorithm 1 steps 1-2): d signals, their
+ *    moments, an n_cand-step dichotomy on [0, lmax], the filter at the found cut-off,
+ *    k-means.
+ *  - Each later call (steps 4-8): draws q d fresh signals, filters them on G_t with the
+ *    previous filter, estimates their eigencount c = <R, h(L) R> / (sigma2 q d); when
+ *    |c - k| > tau it computes their moments, bisects from the previous cut-off
+ *    ([lambda, lmax] when c < k, [0, lambda] otherwise) and filters them again; the
+ *    result replaces the oldest block of Theta; k-means on Theta gives the labels.
+ * Random draws: Philox streams 16 t + 1 (signals, variance 1/d) and 16 t + 2 (k-means++
+ * uniforms), key `seed`.  feat_dt: storage of Theta and of the fresh signals (F32 or
+ * BF16); iterates follow opts->iter_dt.  (1 - p) d must divide d.
+ * csc_dynamic_step writes labels (device int32[n]) and returns lambda_t, whether the
+ * filter was refined and the eigencount of the fresh columns.  Synchronising.
+ */
+typedef struct {
+  double lmax;        /* spectrum bound, 0 -> 2 */
+  double tau;         /* acceptance half-width, <= 0 -> max(0.5, 2 sqrt(2 k / (q d))) */
+  int n_cand;         /* dichotomy steps, 0 -> 16 */
+  int lloyd_iters;    /* Lloyd rounds after seeding, < 0 -> 20 */
+  int init;           /* 0: k-means++ every snapshot; 1: warm start from previous labels */
+  csc_dtype iter_dt;  /* storage of the recurrence iterates (F32 or BF16) */
+} csc_dyn_opts;
+
+csc_status csc_dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp,
+                          csc_dtype feat_dt, uint64_t seed, const csc_dyn_opts* opts,
+                          csc_dyn* out);
+csc_status csc_dynamic_step(csc_dyn st, csc_graph g_t, int32_t* labels, double* lambda_t,
+                            int* refined, double* count, void* stream);
+/* Device view of Theta (n x d, type *dt, leading dimension *ld) and the centroids
+ * (float[k * d]).  Valid until destroy. */
+csc_status csc_dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,
+                            const float** centroids);
+csc_status csc_dyn_destroy(csc_dyn st);
+
+/* ---------------------------------------------------------------------------------
+ * Adjoint of csc_cheb_filter (FP32).  Given G = dl/dY (device n x w, float, ldg), returns
+ *   dX = sum_j a_j T_j(L~)^T G (device float n x w, lddx; NULL to skip),
+ *   da[j] = <G, T_j(L~) X> (device double[m + 1] or NULL),
+ *   dA[e] = dl/dA_e for every stored entry e of A (device float[nnz] or NULL), each entry
+ *           a parameter of its own (the transposed product reads A's mirror entries);
+ * by the reverse recurrence Zb_j = a_j G + 2 L~^T Zb_{j+1} - Zb_{j+2}, with the forward
+ * iterates recomputed from checkpoints taken every ckpt_every steps (0 -> ceil(sqrt(m))).
+ * X: device float n x w (ldx).  work: csc_cheb_backward_workspace_bytes(n, w, m,
+ * ckpt_every).  Asynchronous.
+ */
+size_t csc_cheb_backward_workspace_bytes(int64_t n, int w, int m, int ckpt_every);
+csc_status csc_cheb_filter_backward(csc_graph g, double lmax, int m, const double* a,
+                                    const float* X, int64_t ldx, const float* G, int64_t ldg,
+                                    int w, float* dX, int64_t lddx, double* da, float* dA,
+                                    int ckpt_every, void* work, size_t work_bytes,
+                                    void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Measurement.  When enabled, csc_cheb_filter / csc_cheb_moments record a pair of HIP
+ * events on their stream around their sequence of recurrence-step kernels, and
+ * csc_timing_read sums, over the calls since the last reset, the elapsed time, the number
+ * of step kernels and their algorithmic bytes (synchronising on the recorded events).
+ */
+csc_status csc_timing_enable(int on);
+csc_status csc_timing_reset(void);
+csc_status csc_timing_read(double* ms, int64_t* launches, double* bytes);
+
+/* Kernel-shape selection for the recurrence step of graph g at width w: candidate row
+ * groups and column tiles are timed on the device and the fastest is kept in the handle
+ * (variant index written to *variant).  Synchronising; uses `work` like csc_cheb_filter. */
+csc_status csc_autotune(csc_graph g, int w, csc_dtype iter_dt, void* work, size_t work_bytes,
+                        void* stream, int* variant);
+/* Force a variant (-1 = heuristic default) for graph g and width class of iter_dt. */
+csc_status csc_set_variant(csc_graph g, csc_dtype iter_dt, int variant);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSC_H */

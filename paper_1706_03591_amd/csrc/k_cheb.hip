@@ -1,0 +1,857 @@
+// Fused Chebyshev recurrence step (Sec. 2.2, Step 1; Sec. 3.2).
+//
+// One launch computes, for every row r of one column tile,
+//     acc      = sum_{c in row r} A_rc Z_j[c, :]                       (sparse gather)
+//     Z_{j+1}  = 2 (alpha Z_j[r] - beta acc) - Z_{j-1}[r]               (three-term step)
+//     Y[r]    += a_{j+1} Z_{j+1}[r]                                     (coefficient accumulate)
+// with L~ = alpha I - beta A (alpha = 2 / lmax - 1, beta = 2 / lmax).  Z_{j+1} overwrites
+// Z_{j-1} in place: row r reads its own Z_{j-1} row before writing it and no other row
+// reads Z_{j-1}.  Optionally the per-row dot products <Z_j, Z_j> and <Z_{j+1}, Z_j> are
+// reduced (FP64, fixed order) for the doubled Chebyshev moments.
+//
+// Layout.  Iterates live in the workspace as column tiles: tile t is a contiguous n x wt
+// array (row-major), so a gathered row segment is wt * sizeof(T) contiguous bytes and the
+// tile that the whole grid gathers from is as small as the cache it should stay in.  Blocks
+// are numbered tile-major, so the blocks in flight at any time work on one tile.  A block
+// stages its rows' column indices and values in LDS with one coalesced pass; each row is
+// served by `LPR` lanes that each own 16 bytes of the row (4 FP32 or 8 BF16 columns), so a
+// gather is one 16-byte load per lane and one contiguous segment per row group.
+#include "csc_internal.h"
+
+namespace csc {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kStageCap = 2048;  // CSR entries staged in LDS per block
+
+enum : int { F_FIRST = 1, F_ACC = 2, F_LAST = 4, F_MOM = 8, F_STORE = 16, F_OWN = 32 };
+
+template <typename TZ>
+struct Pack;
+
+template <>
+struct Pack<float> {
+  static constexpr int VEC = 4;
+  __device__ static inline void unpack(const uint4& u, float* f) {
+    f[0] = __uint_as_float(u.x);
+    f[1] = __uint_as_float(u.y);
+    f[2] = __uint_as_float(u.z);
+    f[3] = __uint_as_float(u.w);
+  }
+  // round to storage (identity) and return the stored values
+  __device__ static inline uint4 pack(float* f) {
+    return make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
+                      __float_as_uint(f[3]));
+  }
+};
+
+template <>
+struct Pack<uint16_t> {
+  static constexpr int VEC = 8;
+  __device__ static inline void unpack(const uint4& u, float* f) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f[2 * i] = __uint_as_float(w[i] << 16);
+      f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+  __device__ static inline uint4 pack(float* f) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint16_t lo = f32_to_bf16(f[2 * i]);
+      uint16_t hi = f32_to_bf16(f[2 * i + 1]);
+      f[2 * i] = bf16_to_f32(lo);
+      f[2 * i + 1] = bf16_to_f32(hi);
+      w[i] = static_cast<uint32_t>(lo) | (static_cast<uint32_t>(hi) << 16);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  }
+};
+
+template <typename TV>
+__device__ inline float val_f(TV v);
+template <>
+__device__ inline float val_f<float>(float v) { return v; }
+template <>
+__device__ inline float val_f<uint16_t>(uint16_t v) { return bf16_to_f32(v); }
+
+__device__ inline uint4 ld16(const void* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ inline void st16(void* p, const uint4& v) { *reinterpret_cast<uint4*>(p) = v; }
+
+struct StepParams {
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const void* vals;
+  const void* zcur;
+  const void* zprev;
+  void* zout;
+  float* acc;      // row-major n x wpad
+  int64_t ld_acc;  // = wpad
+  void* yout;      // final output (row-major, ldy, y_dt) on the last step, else null
+  int64_t ldy;
+  int y_dt;
+  int w;
+  int64_t n;
+  int64_t row_blocks;
+  float alpha, beta, coef;
+  int flags;
+  double* mom_part;  // [2][gridDim.x]
+};
+
+__device__ inline void store_out(void* y, int dt, int64_t idx, float v) {
+  if (dt == CSC_F32) static_cast<float*>(y)[idx] = v;
+  else if (dt == CSC_BF16) static_cast<uint16_t*>(y)[idx] = f32_to_bf16(v);
+  else static_cast<double*>(y)[idx] = static_cast<double>(v);
+}
+
+// Fixed-order block reduction of two doubles; result valid in thread 0.
+__device__ inline void block_reduce2(double& a, double& b) {
+  __shared__ double red[2][kThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+  if (lid == 0) { red[0][wid] = a; red[1][wid] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0.0; b = 0.0;
+    for (int i = 0; i < kThreads / 64; ++i) { a += red[0][i]; b += red[1][i]; }
+  }
+}
+
+template <typename TZ, typename TV, int LPR>
+__global__ __launch_bounds__(kThreads) void k_step(StepParams p) {
+  using P = Pack<TZ>;
+  constexpr int VEC = P::VEC;
+  constexpr int WT = LPR * VEC;
+  constexpr int RPB = kThreads / LPR;
+  __shared__ int32_t s_col[kStageCap];
+  __shared__ float s_val[kStageCap];
+
+  const int64_t bid = blockIdx.x;
+  const int64_t tile = bid / p.row_blocks;
+  const int64_t rb = bid - tile * p.row_blocks;
+  const int64_t r0 = rb * RPB;
+  const int64_t r1 = min(r0 + RPB, p.n);
+  const int32_t e0 = p.rowptr[r0];
+  const int32_t e1 = p.rowptr[r1];
+  const int32_t cnt = e1 - e0;
+  const bool staged = cnt <= kStageCap;
+  const TV* vals = static_cast<const TV*>(p.vals);
+  if (staged) {
+    for (int32_t i = threadIdx.x; i < cnt; i += kThreads) {
+      s_col[i] = p.colidx[e0 + i];
+      s_val[i] = val_f<TV>(vals[e0 + i]);
+    }
+  }
+  __syncthreads();
+
+  const int64_t row = r0 + threadIdx.x / LPR;
+  const int lane = threadIdx.x % LPR;
+  const int64_t tile_off = tile * p.n * WT;  // elements
+  const TZ* zc = static_cast<const TZ*>(p.zcur) + tile_off + lane * VEC;
+  double d1 = 0.0, d2 = 0.0;
+
+  if (row < p.n) {
+    float acc[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) acc[i] = 0.f;
+    const int32_t rs = p.rowptr[row], re = p.rowptr[row + 1];
+    int32_t e = rs;
+    if (staged) {
+      for (; e + 4 <= re; e += 4) {
+        const int32_t l = e - e0;
+        const int32_t c0 = s_col[l], c1 = s_col[l + 1], c2 = s_col[l + 2], c3 = s_col[l + 3];
+        const float v0 = s_val[l], v1 = s_val[l + 1], v2 = s_val[l + 2], v3 = s_val[l + 3];
+        const uint4 g0 = ld16(zc + static_cast<int64_t>(c0) * WT);
+        const uint4 g1 = ld16(zc + static_cast<int64_t>(c1) * WT);
+        const uint4 g2 = ld16(zc + static_cast<int64_t>(c2) * WT);
+        const uint4 g3 = ld16(zc + static_cast<int64_t>(c3) * WT);
+        float f[VEC];
+        P::unpack(g0, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v0, f[i], acc[i]);
+        P::unpack(g1, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v1, f[i], acc[i]);
+        P::unpack(g2, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v2, f[i], acc[i]);
+        P::unpack(g3, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v3, f[i], acc[i]);
+      }
+      for (; e < re; ++e) {
+        const int32_t l = e - e0;
+        const uint4 g = ld16(zc + static_cast<int64_t>(s_col[l]) * WT);
+        float f[VEC];
+        P::unpack(g, f);
+        const float v = s_val[l];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v, f[i], acc[i]);
+      }
+    } else {
+      for (; e < re; ++e) {
+        const uint4 g = ld16(zc + static_cast<int64_t>(p.colidx[e]) * WT);
+        float f[VEC];
+        P::unpack(g, f);
+        const float v = val_f<TV>(vals[e]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v, f[i], acc[i]);
+      }
+    }
+
+    const int64_t own = row * WT;  // element offset of this row within the tile
+    float zj[VEC];
+    if (p.flags & F_OWN) {
+      P::unpack(ld16(zc + own), zj);
+    } else {
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) zj[i] = 0.f;
+    }
+    float zn[VEC];
+    if (p.flags & F_FIRST) {
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) zn[i] = fmaf(p.alpha, zj[i], -p.beta * acc[i]);
+    } else {
+      float zp[VEC];
+      P::unpack(ld16(static_cast<const TZ*>(p.zprev) + tile_off + lane * VEC + own), zp);
+#pragma unroll
+      for (int i = 0; i < VEC; ++i)
+        zn[i] = 2.f * fmaf(p.alpha, zj[i], -p.beta * acc[i]) - zp[i];
+    }
+    const uint4 packed = P::pack(zn);  // zn now holds the stored (rounded) values
+    if (p.flags & F_STORE)
+      st16(static_cast<TZ*>(p.zout) + tile_off + lane * VEC + own, packed);
+    if (p.flags & F_MOM) {
+      float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        s1 = fmaf(zj[i], zj[i], s1);
+        s2 = fmaf(zn[i], zj[i], s2);
+      }
+      d1 = s1;
+      d2 = s2;
+    }
+    if (p.flags & F_ACC) {
+      const int64_t col0 = tile * WT + lane * VEC;
+      float* ap = p.acc + row * p.ld_acc + col0;
+      float y[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; i += 4) {
+        float4 t4 = *reinterpret_cast<const float4*>(ap + i);
+        y[i] = fmaf(p.coef, zn[i], t4.x);
+        y[i + 1] = fmaf(p.coef, zn[i + 1], t4.y);
+        y[i + 2] = fmaf(p.coef, zn[i + 2], t4.z);
+        y[i + 3] = fmaf(p.coef, zn[i + 3], t4.w);
+      }
+      if (p.yout) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i)
+          if (col0 + i < p.w) store_out(p.yout, p.y_dt, row * p.ldy + col0 + i, y[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VEC; i += 4)
+          *reinterpret_cast<float4*>(ap + i) = make_float4(y[i], y[i + 1], y[i + 2], y[i + 3]);
+      }
+    }
+  }
+  if (p.flags & F_MOM) {
+    block_reduce2(d1, d2);
+    if (threadIdx.x == 0) {
+      p.mom_part[bid] = d1;
+      p.mom_part[gridDim.x + bid] = d2;
+    }
+  }
+}
+
+// Z_0 (tiled, iter type) from X (row-major, x_dt); acc = a0 * Z_0 when acc != null.
+template <typename TZ>
+__global__ void k_init(const void* X, int x_dt, int64_t ldx, int64_t n, int w, int wpad, int wt,
+                       TZ* z0, float* acc, float a0) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * wpad) return;
+  const int64_t row = idx / wpad;
+  const int col = static_cast<int>(idx - row * wpad);
+  float x = 0.f;
+  if (col < w) {
+    const int64_t src = row * ldx + col;
+    if (x_dt == CSC_F32) x = static_cast<const float*>(X)[src];
+    else if (x_dt == CSC_BF16) x = bf16_to_f32(static_cast<const uint16_t*>(X)[src]);
+    else x = static_cast<float>(static_cast<const double*>(X)[src]);
+  }
+  const int tile = col / wt, c = col - tile * wt;
+  float stored;
+  if constexpr (sizeof(TZ) == 4) {
+    stored = x;
+    z0[static_cast<int64_t>(tile) * n * wt + row * wt + c] = stored;
+  } else {
+    const uint16_t h = f32_to_bf16(x);
+    stored = bf16_to_f32(h);
+    z0[static_cast<int64_t>(tile) * n * wt + row * wt + c] = h;
+  }
+  if (acc) acc[row * wpad + col] = a0 * stored;
+}
+
+__global__ void k_acc_out(const float* acc, int64_t n, int w, int wpad, void* y, int y_dt,
+                          int64_t ldy) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * w) return;
+  const int64_t row = idx / w;
+  const int col = static_cast<int>(idx - row * w);
+  store_out(y, y_dt, row * ldy + col, acc[row * wpad + col]);
+}
+
+// sums[q] = sum_b part[q * nb + b] in a fixed order (one block per q).
+__global__ void k_reduce_rows(const double* part, int64_t nb, double* sums) {
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += kThreads) s += part[q * nb + b];
+  double dummy = 0.0;
+  block_reduce2(s, dummy);
+  if (threadIdx.x == 0) sums[q] = s;
+}
+
+// Doubling: mu_0 = d1(0), mu_1 = d2(0), mu_2j = 2 d1(j) - mu_0, mu_2j+1 = 2 d2(j) - mu_1.
+__global__ void k_moments(const double* sums, int J, int m, double* mu) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double mu0 = sums[0], mu1 = sums[1];
+  mu[0] = mu0;
+  if (m >= 1) mu[1] = mu1;
+  for (int j = 1; j <= J; ++j) {
+    if (2 * j <= m) mu[2 * j] = 2.0 * sums[2 * j] - mu0;
+    if (2 * j + 1 <= m) mu[2 * j + 1] = 2.0 * sums[2 * j + 1] - mu1;
+  }
+}
+
+using StepFn = void (*)(StepParams);
+
+template <typename TZ>
+StepFn pick_step(int lpr, csc_dtype val_dt) {
+  const bool vb = val_dt == CSC_BF16;
+  switch (lpr) {
+    case 4: return vb ? k_step<TZ, uint16_t, 4> : k_step<TZ, float, 4>;
+    case 8: return vb ? k_step<TZ, uint16_t, 8> : k_step<TZ, float, 8>;
+    case 16: return vb ? k_step<TZ, uint16_t, 16> : k_step<TZ, float, 16>;
+    default: return vb ? k_step<TZ, uint16_t, 32> : k_step<TZ, float, 32>;
+  }
+}
+
+const int kLpr[] = {4, 8, 16, 32};
+
+}  // namespace
+
+int num_variants() { return 4; }
+
+StepShape variant_shape(int variant, csc_dtype iter_dt) {
+  const int vec = iter_dt == CSC_BF16 ? 8 : 4;
+  if (variant < 0 || variant >= num_variants()) variant = 2;
+  return StepShape{kLpr[variant], vec};
+}
+
+int default_variant(const Graph* g, int w, csc_dtype iter_dt) {
+  const int v = iter_dt == CSC_BF16 ? g->variant_bf16 : g->variant_f32;
+  if (v >= 0) return v;
+  // widest tile that does not exceed the block width (fewest CSR re-reads)
+  const int vec = iter_dt == CSC_BF16 ? 8 : 4;
+  int best = 0;
+  for (int i = 0; i < num_variants(); ++i)
+    if (kLpr[i] * vec <= std::max(w, kLpr[0] * vec)) best = i;
+  return best;
+}
+
+FilterPlan make_plan(int64_t n, int w, csc_dtype iter_dt, int variant, int m_for_moments) {
+  FilterPlan pl{};
+  pl.n = n;
+  pl.w = w;
+  pl.variant = variant;
+  pl.shape = variant_shape(variant, iter_dt);
+  pl.iter_dt = iter_dt;
+  const int wt = pl.shape.wt();
+  pl.ntiles = (w + wt - 1) / wt;
+  pl.wpad = pl.ntiles * wt;
+  pl.rows_per_block = kThreads / pl.shape.lpr;
+  pl.row_blocks = (n + pl.rows_per_block - 1) / pl.rows_per_block;
+  const size_t zbytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
+  const size_t nb = static_cast<size_t>(pl.row_blocks) * pl.ntiles;
+  const int J = m_for_moments >= 1 ? m_for_moments / 2 : 0;
+  size_t off = 0;
+  pl.off_z0 = off; off += zbytes;
+  pl.off_z1 = off; off += zbytes;
+  pl.off_acc = off; off += align_up(static_cast<size_t>(n) * pl.wpad * sizeof(float));
+  pl.off_part = off; off += align_up(static_cast<size_t>(J + 1) * 2 * nb * sizeof(double));
+  pl.off_mom = off; off += align_up(static_cast<size_t>(J + 1) * 2 * sizeof(double));
+  pl.total = off;
+  return pl;
+}
+
+// Workspace large enough for every variant and for moments up to degree 4096.
+size_t filter_workspace(int64_t n, int w, csc_dtype iter_dt) {
+  size_t best = 0;
+  for (int v = 0; v < num_variants(); ++v)
+    best = std::max(best, make_plan(n, w, iter_dt, v, 4096).total);
+  return best;
+}
+
+static double step_bytes(const Graph* g, int64_t n, int w, csc_dtype iter_dt, int flags,
+                         csc_dtype y_dt) {
+  const double sz = static_cast<double>(dtype_size(iter_dt));
+  double b = static_cast<double>(g->nnz) * (4.0 + dtype_size(g->val_dt)) + 4.0 * (n + 1);
+  const double nw = static_cast<double>(n) * w;
+  b += nw * sz;                                   // gather Z_j (each row counted once)
+  if (!(flags & F_FIRST)) b += nw * sz;           // Z_{j-1}
+  if (flags & F_STORE) b += nw * sz;              // Z_{j+1}
+  if (flags & F_ACC) b += nw * 4.0 + ((flags & F_LAST) ? nw * dtype_size(y_dt) : nw * 4.0);
+  return b;
+}
+
+csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const void* X,
+                      csc_dtype x_dt, int64_t ldx, void* Y, csc_dtype y_dt, int64_t ldy, int w,
+                      csc_dtype iter_dt, double* moments, int moments_only, void* work,
+                      size_t work_bytes, hipStream_t s, int variant_override) {
+  const int64_t n = g->n;
+  if (m < 0) return fail(CSC_E_ARG, "m must be >= 0");
+  if (w < 1) return fail(CSC_E_ARG, "w must be >= 1");
+  if (!(lmax > 0.0)) return fail(CSC_E_ARG, "lmax must be > 0");
+  if (iter_dt != CSC_F32 && iter_dt != CSC_BF16)
+    return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
+  if (moments && m < 1) return fail(CSC_E_ARG, "moments need m >= 1");
+  if (!moments_only && (ldy < w || !Y)) return fail(CSC_E_ARG, "bad Y / ldy");
+  if (ldx < w || !X) return fail(CSC_E_ARG, "bad X / ldx");
+  if (!moments_only) {
+    const char* xb = static_cast<const char*>(X);
+    const char* yb = static_cast<const char*>(Y);
+    const size_t xspan = (static_cast<size_t>(n - 1) * ldx + w) * dtype_size(x_dt);
+    const size_t yspan = (static_cast<size_t>(n - 1) * ldy + w) * dtype_size(y_dt);
+    if (n > 0 && xb < yb + yspan && yb < xb + xspan)
+      return fail(CSC_E_ARG, "X and Y overlap");
+  }
+  if (n == 0) return CSC_OK;
+  const int variant = variant_override >= 0 ? variant_override : default_variant(g, w, iter_dt);
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, moments ? m : 0);
+  if (!work || work_bytes < pl.total)
+    return fail(CSC_E_ARG, "workspace too small: need " + std::to_string(pl.total) + " bytes");
+  char* base = static_cast<char*>(work);
+  void* zb[2] = {base + pl.off_z0, base + pl.off_z1};
+  float* acc = reinterpret_cast<float*>(base + pl.off_acc);
+  double* part = reinterpret_cast<double*>(base + pl.off_part);
+  double* msum = reinterpret_cast<double*>(base + pl.off_mom);
+  const int wt = pl.shape.wt();
+  const bool do_acc = !moments_only;
+
+  {
+    const int64_t total = n * pl.wpad;
+    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+    const float a0 = static_cast<float>(a ? a[0] : 0.0);
+    if (iter_dt == CSC_F32)
+      hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
+                         pl.wpad, wt, static_cast<float*>(zb[0]), do_acc ? acc : nullptr, a0);
+    else
+      hipLaunchKernelGGL(k_init<uint16_t>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n,
+                         w, pl.wpad, wt, static_cast<uint16_t*>(zb[0]), do_acc ? acc : nullptr,
+                         a0);
+    CSC_HIP(hipGetLastError());
+  }
+  if (m == 0) {
+    if (do_acc) {
+      const int64_t total = n * w;
+      hipLaunchKernelGGL(k_acc_out, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
+                         0, s, acc, n, w, pl.wpad, Y, int(y_dt), ldy);
+      CSC_HIP(hipGetLastError());
+    }
+    return CSC_OK;
+  }
+
+  const StepFn fn = iter_dt == CSC_F32 ? pick_step<float>(pl.shape.lpr, g->val_dt)
+                                       : pick_step<uint16_t>(pl.shape.lpr, g->val_dt);
+  const int64_t nb = pl.row_blocks * pl.ntiles;
+  const int J = moments ? m / 2 : -1;
+  const int nsteps = moments_only ? J + 1 : m;
+  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
+  const float beta = static_cast<float>(2.0 / lmax);
+  double bytes = 0.0;
+  timing_begin(s);
+  for (int j = 0; j < nsteps; ++j) {
+    StepParams p{};
+    p.rowptr = g->rowptr;
+    p.colidx = g->colidx;
+    p.vals = g->vals;
+    p.zcur = zb[j & 1];
+    p.zprev = zb[(j + 1) & 1];
+    p.zout = zb[(j + 1) & 1];
+    p.acc = acc;
+    p.ld_acc = pl.wpad;
+    p.w = w;
+    p.n = n;
+    p.row_blocks = pl.row_blocks;
+    p.alpha = alpha;
+    p.beta = beta;
+    p.coef = static_cast<float>(do_acc ? a[j + 1] : 0.0);
+    const bool last = j == nsteps - 1;
+    const bool mom = moments && j <= J;
+    int flags = 0;
+    if (j == 0) flags |= F_FIRST;
+    if (do_acc) flags |= F_ACC;
+    if (do_acc && last) {
+      flags |= F_LAST;
+      p.yout = Y;
+      p.ldy = ldy;
+      p.y_dt = int(y_dt);
+    }
+    if (mom) {
+      flags |= F_MOM;
+      p.mom_part = part + static_cast<int64_t>(j) * 2 * nb;
+    }
+    if (!last) flags |= F_STORE;
+    if (mom || alpha != 0.f) flags |= F_OWN;
+    p.flags = flags;
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, p);
+    bytes += step_bytes(g, n, w, iter_dt, flags, y_dt);
+  }
+  timing_end(s, nsteps, bytes);
+  CSC_HIP(hipGetLastError());
+  if (moments) {
+    hipLaunchKernelGGL(k_reduce_rows, dim3(2 * (J + 1)), dim3(kThreads), 0, s, part, nb, msum);
+    hipLaunchKernelGGL(k_moments, dim3(1), dim3(64), 0, s, msum, J, m, moments);
+    CSC_HIP(hipGetLastError());
+  }
+  return CSC_OK;
+}
+
+}  // namespace csc
+
+// =====================================================================================
+// Adjoint of the filter (reverse mode).  With Zb_j = dl/dZ_j and Zb_{m+1} = Zb_{m+2} = 0:
+//     Zb_j = a_j G + f_j (alpha Zb_{j+1} - beta A^T Zb_{j+1}) - Zb_{j+2},  f_j = 2 (j >= 1), 1 (j = 0)
+//     dl/dA_e += -beta f_j <Zb_{j+1}[r], Z_j[c]>   for every stored entry e = (r, c)
+//     dl/da_j  = <G, Z_j>,   dl/dX = Zb_0.
+// The forward iterates are recomputed segment by segment from checkpoint pairs
+// (Z_s, Z_{s+1}) taken every `ckpt` steps.  The fused adjoint kernel gathers Zb_{j+1} and
+// Z_j over the same CSR entries (transposed product and sampled dense-dense product) and
+// loops over the column tiles inside the block, so each entry's gradient is accumulated
+// by one lane in a fixed order.
+namespace csc {
+
+namespace {
+
+struct AdjParams {
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const void* valsT;   // A^T values on A's pattern
+  const float* zb1;    // Zb_{j+1}, tiled
+  const float* zb2;    // Zb_{j+2}, tiled, or null (zero)
+  float* zbout;        // Zb_j, tiled (may alias zb2)
+  const float* zj;     // Z_j, tiled
+  const float* G;      // row-major, ldg
+  int64_t ldg;
+  float* dA;           // nnz
+  int64_t n;
+  int w, ntiles;
+  float alpha, beta, aj, fac, sdd;
+};
+
+template <typename TV, int LPR>
+__global__ __launch_bounds__(kThreads) void k_adj(AdjParams p) {
+  constexpr int VEC = 4;
+  constexpr int WT = LPR * VEC;
+  constexpr int RPB = kThreads / LPR;
+  __shared__ int32_t s_col[kStageCap];
+  __shared__ float s_val[kStageCap];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RPB;
+  const int64_t r1 = min(r0 + RPB, p.n);
+  const int32_t e0 = p.rowptr[r0];
+  const int32_t cnt = p.rowptr[r1] - e0;
+  const bool staged = cnt <= kStageCap;
+  const TV* vals = static_cast<const TV*>(p.valsT);
+  if (staged)
+    for (int32_t i = threadIdx.x; i < cnt; i += kThreads) {
+      s_col[i] = p.colidx[e0 + i];
+      s_val[i] = val_f<TV>(vals[e0 + i]);
+    }
+  __syncthreads();
+  const int64_t row = r0 + threadIdx.x / LPR;
+  const int lane = threadIdx.x % LPR;
+  if (row >= p.n) return;
+  const int32_t rs = p.rowptr[row], re = p.rowptr[row + 1];
+  for (int tile = 0; tile < p.ntiles; ++tile) {
+    const int64_t toff = static_cast<int64_t>(tile) * p.n * WT + lane * VEC;
+    const float* zb1 = p.zb1 + toff;
+    const float* zj = p.zj + toff;
+    float ob[VEC], acc[VEC];
+    Pack<float>::unpack(ld16(zb1 + row * WT), ob);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) acc[i] = 0.f;
+    for (int32_t e = rs; e < re; ++e) {
+      const int32_t c = staged ? s_col[e - e0] : p.colidx[e];
+      const float v = staged ? s_val[e - e0] : val_f<TV>(vals[e]);
+      float gb[VEC], gz[VEC];
+      Pack<float>::unpack(ld16(zb1 + static_cast<int64_t>(c) * WT), gb);
+      Pack<float>::unpack(ld16(zj + static_cast<int64_t>(c) * WT), gz);
+      float sd = 0.f;
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        acc[i] = fmaf(v, gb[i], acc[i]);
+        sd = fmaf(ob[i], gz[i], sd);
+      }
+#pragma unroll
+      for (int off = LPR / 2; off > 0; off >>= 1) sd += __shfl_xor(sd, off, LPR);
+      if (p.dA && lane == 0) p.dA[e] += p.sdd * sd;
+    }
+    const int64_t col0 = static_cast<int64_t>(tile) * WT + lane * VEC;
+    float out[VEC];
+    float z2[VEC];
+    if (p.zb2) Pack<float>::unpack(ld16(p.zb2 + toff + row * WT), z2);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const float g = (col0 + i < p.w) ? p.G[row * p.ldg + col0 + i] : 0.f;
+      out[i] = fmaf(p.aj, g, p.fac * fmaf(p.alpha, ob[i], -p.beta * acc[i]));
+      if (p.zb2) out[i] -= z2[i];
+    }
+    st16(p.zbout + toff + row * WT, Pack<float>::pack(out));
+  }
+}
+
+// Zb = s * G in the tiled layout (zero in padded columns).
+__global__ void k_scale_tiled(const float* G, int64_t ldg, int64_t n, int w, int wpad, int wt,
+                              float s, float* out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * wpad) return;
+  const int64_t row = idx / wpad;
+  const int col = static_cast<int>(idx - row * wpad);
+  const int tile = col / wt, c = col - tile * wt;
+  out[static_cast<int64_t>(tile) * n * wt + row * wt + c] = col < w ? s * G[row * ldg + col] : 0.f;
+}
+
+// Row-major out (ld) from the tiled layout.
+__global__ void k_tiled_out(const float* Z, int64_t n, int w, int wt, float* out, int64_t ld) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * w) return;
+  const int64_t row = idx / w;
+  const int col = static_cast<int>(idx - row * w);
+  const int tile = col / wt, c = col - tile * wt;
+  out[row * ld + col] = Z[static_cast<int64_t>(tile) * n * wt + row * wt + c];
+}
+
+// Block partials of <G, Z> with Z tiled (FP64, fixed order).
+__global__ void k_gdot_part(const float* Z, const float* G, int64_t ldg, int64_t n, int w, int wt,
+                            double* part) {
+  const int64_t total = n * w;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  double s = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < total; i += stride) {
+    const int64_t row = i / w;
+    const int col = static_cast<int>(i - row * w);
+    const int tile = col / wt, c = col - tile * wt;
+    s += static_cast<double>(G[row * ldg + col]) *
+         static_cast<double>(Z[static_cast<int64_t>(tile) * n * wt + row * wt + c]);
+  }
+  double dummy = 0.0;
+  block_reduce2(s, dummy);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename TV>
+__global__ void k_transpose_vals(const TV* vals, const int32_t* mirror, int64_t nnz, TV* out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < nnz) out[e] = vals[mirror[e]];
+}
+
+__global__ void k_zero(float* p, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.f;
+}
+
+using AdjFn = void (*)(AdjParams);
+AdjFn pick_adj(int lpr, csc_dtype val_dt) {
+  const bool vb = val_dt == CSC_BF16;
+  switch (lpr) {
+    case 4: return vb ? k_adj<uint16_t, 4> : k_adj<float, 4>;
+    case 8: return vb ? k_adj<uint16_t, 8> : k_adj<float, 8>;
+    case 16: return vb ? k_adj<uint16_t, 16> : k_adj<float, 16>;
+    default: return vb ? k_adj<uint16_t, 32> : k_adj<float, 32>;
+  }
+}
+
+constexpr int64_t kGdotBlocks = 1024;
+
+struct BwdLayout {
+  FilterPlan pl;
+  int ckpt, nseg;
+  size_t zbytes;
+  size_t off_ckpt, off_seg, off_pp, off_zb, off_vt, off_part, total;
+};
+
+BwdLayout bwd_layout(int64_t n, int w, int m, int ckpt, int variant, size_t nnz_cap) {
+  BwdLayout L{};
+  L.pl = make_plan(n, w, CSC_F32, variant, 0);
+  if (ckpt <= 0) ckpt = std::max(2, static_cast<int>(std::ceil(std::sqrt(static_cast<double>(std::max(m, 1))))));
+  L.ckpt = std::max(2, ckpt);
+  L.nseg = std::max(1, (m + L.ckpt - 1) / L.ckpt);
+  L.zbytes = align_up(static_cast<size_t>(n) * L.pl.wpad * sizeof(float));
+  size_t off = 0;
+  L.off_ckpt = off; off += 2 * L.nseg * L.zbytes;
+  L.off_seg = off; off += (L.ckpt - 2 > 0 ? L.ckpt - 2 : 0) * L.zbytes;
+  L.off_pp = off; off += 2 * L.zbytes;   // forward ping-pong
+  L.off_zb = off; off += 2 * L.zbytes;   // adjoint pair
+  L.off_vt = off; off += align_up(nnz_cap * 4);
+  L.off_part = off; off += align_up(static_cast<size_t>(m + 1) * kGdotBlocks * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+size_t backward_workspace(int64_t n, int w, int m, int ckpt) {
+  // the transposed values need the graph's capacity; callers size it with nnz = 64 n at most
+  size_t best = 0;
+  for (int v = 0; v < num_variants(); ++v)
+    best = std::max(best, bwd_layout(n, w, m, ckpt, v, static_cast<size_t>(n) * 64).total);
+  return best;
+}
+
+csc_status run_backward(const Graph* g, double lmax, int m, const double* a, const float* X,
+                        int64_t ldx, const float* G, int64_t ldg, int w, float* dX, int64_t lddx,
+                        double* da, float* dA, int ckpt, void* work, size_t work_bytes,
+                        hipStream_t s) {
+  const int64_t n = g->n;
+  if (m < 0 || m > 4096) return fail(CSC_E_ARG, "m must be in [0, 4096]");
+  if (w < 1 || ldx < w || ldg < w || (dX && lddx < w)) return fail(CSC_E_ARG, "bad sizes");
+  if (!(lmax > 0.0)) return fail(CSC_E_ARG, "lmax must be > 0");
+  if (g->nnz > n * 64) return fail(CSC_E_ARG, "backward supports nnz <= 64 n");
+  const int variant = default_variant(g, w, CSC_F32);
+  const BwdLayout L = bwd_layout(n, w, m, ckpt, variant, static_cast<size_t>(std::max<int64_t>(g->nnz, 1)));
+  if (!work || work_bytes < L.total)
+    return fail(CSC_E_ARG, "backward workspace too small: need " + std::to_string(L.total));
+  const FilterPlan& pl = L.pl;
+  const int wt = pl.shape.wt();
+  char* base = static_cast<char*>(work);
+  auto ck = [&](int q, int which) {
+    return reinterpret_cast<float*>(base + L.off_ckpt + (2 * q + which) * L.zbytes);
+  };
+  auto seg = [&](int i) { return reinterpret_cast<float*>(base + L.off_seg + (i - 2) * L.zbytes); };
+  float* pp[2] = {reinterpret_cast<float*>(base + L.off_pp),
+                  reinterpret_cast<float*>(base + L.off_pp + L.zbytes)};
+  float* zbb[2] = {reinterpret_cast<float*>(base + L.off_zb),
+                   reinterpret_cast<float*>(base + L.off_zb + L.zbytes)};
+  void* valsT = base + L.off_vt;
+  double* part = reinterpret_cast<double*>(base + L.off_part);
+  const size_t tiled_bytes = static_cast<size_t>(n) * pl.wpad * sizeof(float);
+  const unsigned eblocks = static_cast<unsigned>((n * pl.wpad + 255) / 256);
+  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
+  const float beta = static_cast<float>(2.0 / lmax);
+  const int64_t nb = pl.row_blocks * pl.ntiles;
+  const StepFn fstep = pick_step<float>(pl.shape.lpr, g->val_dt);
+  const int gblocks = static_cast<int>(std::min<int64_t>(kGdotBlocks, std::max<int64_t>(1, (n * w + kThreads - 1) / kThreads)));
+
+  if (n == 0) return CSC_OK;
+  // transposed values on A's pattern
+  if (g->nnz > 0) {
+    const unsigned vb = static_cast<unsigned>((g->nnz + 255) / 256);
+    if (g->val_dt == CSC_F32)
+      hipLaunchKernelGGL(k_transpose_vals<float>, dim3(vb), dim3(256), 0, s,
+                         static_cast<const float*>(g->vals), g->mirror, g->nnz, static_cast<float*>(valsT));
+    else
+      hipLaunchKernelGGL(k_transpose_vals<uint16_t>, dim3(vb), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(g->vals), g->mirror, g->nnz,
+                         static_cast<uint16_t*>(valsT));
+  }
+  if (dA && g->nnz > 0)
+    hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>((g->nnz + 255) / 256)), dim3(256), 0, s, dA, g->nnz);
+
+  auto step = [&](const float* zcur, const float* zprev, float* zout, bool first) {
+    StepParams p{};
+    p.rowptr = g->rowptr;
+    p.colidx = g->colidx;
+    p.vals = g->vals;
+    p.zcur = zcur;
+    p.zprev = zprev;
+    p.zout = zout;
+    p.n = n;
+    p.w = w;
+    p.row_blocks = pl.row_blocks;
+    p.alpha = alpha;
+    p.beta = beta;
+    p.flags = F_STORE | (first ? F_FIRST : 0) | (alpha != 0.f ? F_OWN : 0);
+    hipLaunchKernelGGL(fstep, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, p);
+  };
+  auto gdot = [&](const float* Z, int j) {
+    hipLaunchKernelGGL(k_gdot_part, dim3(gblocks), dim3(kThreads), 0, s, Z, G, ldg, n, w, wt,
+                       part + static_cast<int64_t>(j) * gblocks);
+  };
+
+  // ---- forward with checkpoints: Z_0 .. Z_m in the ping-pong pair (Z_{j+1} overwrites
+  // Z_{j-1} in place), copies of Z_i into the checkpoint slots when i = q ckpt or q ckpt + 1,
+  // and da_j = <G, Z_j>
+  auto keep = [&](int i, const float* z) -> csc_status {
+    const int q = i / L.ckpt, r = i % L.ckpt;
+    if (q < L.nseg && r <= 1)
+      CSC_HIP(hipMemcpyAsync(ck(q, r), z, tiled_bytes, hipMemcpyDeviceToDevice, s));
+    return CSC_OK;
+  };
+  hipLaunchKernelGGL(k_init<float>, dim3(eblocks), dim3(256), 0, s, static_cast<const void*>(X),
+                     int(CSC_F32), ldx, n, w, pl.wpad, wt, pp[0], static_cast<float*>(nullptr), 0.f);
+  gdot(pp[0], 0);
+  CSC_TRY(keep(0, pp[0]));
+  for (int j = 0; j < m; ++j) {
+    step(pp[j & 1], pp[(j + 1) & 1], pp[(j + 1) & 1], j == 0);
+    gdot(pp[(j + 1) & 1], j + 1);
+    CSC_TRY(keep(j + 1, pp[(j + 1) & 1]));
+  }
+  if (da) hipLaunchKernelGGL(k_reduce_rows, dim3(m + 1), dim3(kThreads), 0, s, part, int64_t(gblocks), da);
+
+  // ---- reverse sweep
+  hipLaunchKernelGGL(k_scale_tiled, dim3(eblocks), dim3(256), 0, s, G, ldg, n, w, pl.wpad, wt,
+                     static_cast<float>(a[m]), zbb[0]);
+  const float* zb1 = zbb[0];  // Zb_{j+1}
+  const float* zb2 = nullptr; // Zb_{j+2}
+  const AdjFn adj = pick_adj(pl.shape.lpr, g->val_dt);
+  for (int q = (m >= 1 ? (m - 1) / L.ckpt : -1); q >= 0; --q) {
+    const int s0 = q * L.ckpt;
+    const int s1 = std::min(s0 + L.ckpt - 1, m - 1);  // segment iterates Z_s0 .. Z_s1
+    auto Zp = [&](int j) -> const float* {
+      const int i = j - s0;
+      if (i == 0) return ck(q, 0);
+      if (i == 1) return ck(q, 1);
+      return seg(i);
+    };
+    for (int j = s0 + 2; j <= s1; ++j) step(Zp(j - 1), Zp(j - 2), seg(j - s0), false);
+    for (int j = s1; j >= s0; --j) {
+      AdjParams p{};
+      p.rowptr = g->rowptr;
+      p.colidx = g->colidx;
+      p.valsT = valsT;
+      p.zb1 = zb1;
+      p.zb2 = zb2;
+      float* out = zb2 ? const_cast<float*>(zb2) : (zb1 == zbb[0] ? zbb[1] : zbb[0]);
+      p.zbout = out;
+      p.zj = Zp(j);
+      p.G = G;
+      p.ldg = ldg;
+      p.dA = dA;
+      p.n = n;
+      p.w = w;
+      p.ntiles = pl.ntiles;
+      p.alpha = alpha;
+      p.beta = beta;
+      p.aj = static_cast<float>(a[j]);
+      p.fac = j >= 1 ? 2.f : 1.f;
+      p.sdd = -beta * p.fac;
+      hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(pl.row_blocks)), dim3(kThreads), 0, s, p);
+      zb2 = zb1;
+      zb1 = out;
+    }
+  }
+  // zb1 now holds Zb_0 (for m == 0 it holds a_0 G)
+  if (dX)
+    hipLaunchKernelGGL(k_tiled_out, dim3(static_cast<unsigned>((n * w + 255) / 256)), dim3(256), 0, s,
+                       zb1, n, w, wt, dX, lddx);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+}  // namespace csc

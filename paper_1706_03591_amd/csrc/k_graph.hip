@@ -1,0 +1,168 @@
+// Operator build (Sec. 2.1): A = D^{-1/2} W D^{-1/2} from the CSR weight matrix W, on the
+// device, with optional validation of the CSR input (sorted rows, indices in range, no
+// self-loops, positive weights, symmetry).  All accesses are bounds-checked, so an invalid
+// input yields an error flag, never an out-of-range read.
+#include "csc_internal.h"
+
+namespace csc {
+
+namespace {
+
+constexpr int kFlagRowptr = 1;
+constexpr int kFlagIndex = 2;
+constexpr int kFlagOrder = 4;
+constexpr int kFlagSelf = 8;
+constexpr int kFlagWeight = 16;
+constexpr int kFlagSym = 32;
+
+__global__ void k_check_rowptr(const int64_t* rowptr, int64_t n, int64_t nnz, int32_t* flags) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r > n) return;
+  int64_t v = rowptr[r];
+  bool bad = v < 0 || v > nnz;
+  if (r == 0 && v != 0) bad = true;
+  if (r == n && v != nnz) bad = true;
+  if (r < n && rowptr[r + 1] < v) bad = true;
+  if (bad) atomicOr(flags, kFlagRowptr);
+}
+
+// One thread per row; assumes k_check_rowptr passed (checked on the host in between).
+__global__ void k_check_rows(const int64_t* rowptr, const int32_t* colidx, const double* w,
+                             int64_t n, int32_t* flags) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int64_t s = rowptr[r], e = rowptr[r + 1];
+  int bad = 0;
+  int64_t prev = -1;
+  for (int64_t i = s; i < e; ++i) {
+    int64_t c = colidx[i];
+    double wi = w[i];
+    if (c < 0 || c >= n) { bad |= kFlagIndex; continue; }
+    if (c <= prev) bad |= kFlagOrder;
+    prev = c;
+    if (c == r) bad |= kFlagSelf;
+    if (!(wi > 0.0) || !(wi < INFINITY)) bad |= kFlagWeight;
+    // symmetric partner (c, r) by binary search in row c
+    int64_t lo = rowptr[c], hi = rowptr[c + 1] - 1;
+    bool found = false;
+    while (lo <= hi) {
+      int64_t mid = (lo + hi) >> 1;
+      int64_t cm = colidx[mid];
+      if (cm == r) { found = (w[mid] == wi); break; }
+      if (cm < r) lo = mid + 1; else hi = mid - 1;
+    }
+    if (!found) bad |= kFlagSym;
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+__global__ void k_rowptr32(const int64_t* rowptr, int32_t* out, int64_t n) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r <= n) out[r] = static_cast<int32_t>(rowptr[r]);
+}
+
+__global__ void k_degrees(const int64_t* rowptr, const double* w, int64_t n, double* dinv,
+                          int32_t* isolated) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double deg = 0.0;
+  for (int64_t i = rowptr[r]; i < rowptr[r + 1]; ++i) deg += w[i];
+  dinv[r] = deg > 0.0 ? 1.0 / sqrt(deg) : 0.0;
+  if (rowptr[r + 1] == rowptr[r]) atomicAdd(isolated, 1);
+}
+
+template <typename TV>
+__device__ inline TV to_val(double x);
+template <>
+__device__ inline float to_val<float>(double x) { return static_cast<float>(x); }
+template <>
+__device__ inline uint16_t to_val<uint16_t>(double x) {
+  return f32_to_bf16(static_cast<float>(x));
+}
+
+template <typename TV>
+__global__ void k_values(const int64_t* rowptr, const int32_t* colidx, const double* w,
+                         const double* dinv, int64_t n, int32_t* colidx_out, TV* vals) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double dr = dinv[r];
+  for (int64_t i = rowptr[r]; i < rowptr[r + 1]; ++i) {
+    int32_t c = colidx[i];
+    colidx_out[i] = c;
+    vals[i] = to_val<TV>(w[i] * dr * dinv[c]);
+  }
+}
+
+// mirror[e] = index of entry (c, r) for entry e = (r, c); one thread per row.
+__global__ void k_mirror(const int32_t* rowptr, const int32_t* colidx, int64_t n,
+                         int32_t* mirror) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int32_t i = rowptr[r]; i < rowptr[r + 1]; ++i) {
+    int32_t c = colidx[i];
+    int32_t lo = rowptr[c], hi = rowptr[c + 1] - 1, pos = -1;
+    while (lo <= hi) {
+      int32_t mid = (lo + hi) >> 1;
+      int32_t cm = colidx[mid];
+      if (cm == r) { pos = mid; break; }
+      if (cm < r) lo = mid + 1; else hi = mid - 1;
+    }
+    mirror[i] = pos;
+  }
+}
+
+inline unsigned blocks_for(int64_t count, int threads = 256) {
+  return static_cast<unsigned>((count + threads - 1) / threads);
+}
+
+std::string flag_text(int f) {
+  std::string s;
+  if (f & kFlagRowptr) s += " row pointers not monotone or out of [0, nnz];";
+  if (f & kFlagIndex) s += " column index out of range;";
+  if (f & kFlagOrder) s += " columns not strictly increasing within a row;";
+  if (f & kFlagSelf) s += " self-loop;";
+  if (f & kFlagWeight) s += " weight not positive and finite;";
+  if (f & kFlagSym) s += " W not symmetric;";
+  return s;
+}
+
+}  // namespace
+
+csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
+                       const double* w, int validate, hipStream_t s) {
+  const int64_t n = g->n;
+  CSC_HIP(hipMemsetAsync(g->flags, 0, 4 * sizeof(int32_t), s));
+  if (validate) {
+    hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(n + 1)), dim3(256), 0, s, rowptr, n,
+                       nnz, g->flags);
+    CSC_HIP(hipGetLastError());
+    int32_t f = 0;
+    CSC_HIP(hipMemcpyAsync(&f, g->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    if (f) return fail(CSC_E_GRAPH, "invalid CSR graph:" + flag_text(f));
+    if (nnz > 0) {
+      hipLaunchKernelGGL(k_check_rows, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, colidx, w,
+                         n, g->flags);
+      CSC_HIP(hipGetLastError());
+      CSC_HIP(hipMemcpyAsync(&f, g->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CSC_HIP(hipStreamSynchronize(s));
+      if (f) return fail(CSC_E_GRAPH, "invalid CSR graph:" + flag_text(f));
+    }
+  }
+  g->nnz = nnz;
+  hipLaunchKernelGGL(k_rowptr32, dim3(blocks_for(n + 1)), dim3(256), 0, s, rowptr, g->rowptr, n);
+  hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, w, n, g->dinv,
+                     g->flags + 1);
+  if (g->val_dt == CSC_F32)
+    hipLaunchKernelGGL(k_values<float>, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, colidx, w,
+                       g->dinv, n, g->colidx, static_cast<float*>(g->vals));
+  else
+    hipLaunchKernelGGL(k_values<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, colidx,
+                       w, g->dinv, n, g->colidx, static_cast<uint16_t*>(g->vals));
+  hipLaunchKernelGGL(k_mirror, dim3(blocks_for(n)), dim3(256), 0, s, g->rowptr, g->colidx, n,
+                     g->mirror);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+}  // namespace csc

@@ -1,0 +1,108 @@
+"""GPU parity of dynamic CSC (Algorithm 1), the filter adjoint and lmax."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint, chebyshev, dynamic, kmeans as okm, operator
+from workloads import DynamicSBM, gaussian_block, sbm
+from helpers import oracle_A, rel_fro, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def seq():
+    g0 = sbm(2000, 4, 20.0, 0.05, seed=51)
+    dyn = DynamicSBM(g0, seed=52)
+    return [g0] + [dyn.step(0.01, 0.005) for _ in range(4)]
+
+
+@pytest.mark.parametrize("p,d,tau", [(0.5, 32, 1e-12), (0.5, 64, None), (0.75, 64, None), (0.0, 16, None)])
+def test_dynamic_matches_oracle(csc, seq, p, d, tau):
+    say(f"dynamic parity p={p} d={d} tau={tau}")
+    k, m, seed = 4, 40, 53
+    orc = dynamic.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10,
+                             tau=tau, storage=np.float32)
+    gpu = csc.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10, tau=tau or 0.0)
+    for t, g in enumerate(seq, start=1):
+        G = csc.Graph.from_workload(g)
+        lab, lam, ref, cnt = gpu.step(G)
+        r = orc.step(g)
+        say(f"  t={t} lam gpu={lam:.6f} oracle={r.lam:.6f} refined {ref}/{r.refined} count {cnt:.4f}/{r.count:.4f}")
+        assert ref == r.refined
+        assert lam == r.lam
+        assert cnt == pytest.approx(r.count, rel=1e-4, abs=1e-4)
+        theta = gpu.features().double().cpu().numpy()
+        assert rel_fro(theta, orc.theta) <= 1e-5
+        # labels: equal up to near-ties; compare k-means cost on the oracle's features
+        c_gpu = okm.cost(orc.theta, lab.cpu().numpy())
+        c_orc = okm.cost(orc.theta, r.labels)
+        agree = np.mean(lab.cpu().numpy() == r.labels)
+        assert agree > 0.99 or c_gpu == pytest.approx(c_orc, rel=1e-3)
+
+
+def test_dynamic_bf16_quality(csc, seq):
+    k, m, d = 4, 40, 64
+    gpu = csc.DynamicCSC(2000, d, k, 0.5, m, seed=54, feat_dtype=torch.bfloat16)
+    for g in seq:
+        lab, lam, ref, cnt = gpu.step(csc.Graph.from_workload(g))
+    A = oracle_A(seq[-1])
+    lam_d, U = operator.dense_spectrum(A)
+    Phi = U[:, :k]
+    best = min(okm.cost(Phi, okm.lloyd(Phi, Phi[okm.kmeanspp(Phi, k, np.random.default_rng(s).random(k))], 30)[0])
+               for s in range(5))
+    c = okm.cost(Phi, lab.cpu().numpy())
+    say(f"  bf16 dynamic cost {c:.4f} vs SC {best:.4f}")
+    assert c - best <= 2 * np.sqrt(k / d) * (np.sqrt(k) + 3)
+
+
+@pytest.mark.parametrize("m,w,ckpt", [(0, 3, 0), (1, 5, 0), (7, 16, 3), (30, 20, 0), (60, 64, 8)])
+def test_adjoint_matches_oracle(csc, m, w, ckpt):
+    say(f"adjoint parity m={m} w={w} ckpt={ckpt}")
+    g = sbm(1500, 4, 10.0, 0.1, seed=55)
+    A = oracle_A(g)
+    G = csc.Graph.from_workload(g)
+    X = gaussian_block(g.n, w, 0.3, seed=56)
+    Gr = gaussian_block(g.n, w, 1.0, seed=57)
+    a = chebyshev.step_coefficients(m, 2.0, 0.4, "jackson")
+    dX, da, dA = csc.filter_backward(G, a, torch.from_numpy(X).cuda(), torch.from_numpy(Gr).cuda(),
+                                     ckpt_every=ckpt)
+    rX, rda, rdA = adjoint.filter_backward(A, 2.0, a, X.astype(np.float64), Gr.astype(np.float64))
+    assert rel_fro(dX.cpu().numpy(), rX) <= 1e-5
+    assert rel_fro(da.cpu().numpy(), rda) <= 1e-5
+    if m > 0:
+        assert rel_fro(dA.cpu().numpy(), rdA) <= 1e-5
+    else:
+        assert np.all(dA.cpu().numpy() == 0)
+
+
+def test_autograd_function(csc):
+    from paper_1706_03591_amd import cheb_filter_autograd
+    g = sbm(800, 3, 10.0, 0.1, seed=58)
+    A = oracle_A(g)
+    G = csc.Graph.from_workload(g)
+    X = torch.from_numpy(gaussian_block(g.n, 8, 0.3, seed=59)).cuda().requires_grad_(True)
+    a = torch.tensor(chebyshev.step_coefficients(12, 2.0, 0.5, "jackson"), dtype=torch.float64,
+                     requires_grad=True)
+    vals = torch.from_numpy(A.data.astype(np.float32)).cuda().requires_grad_(True)
+    W = torch.from_numpy(gaussian_block(g.n, 8, 1.0, seed=60)).cuda()
+    Y = cheb_filter_autograd(X, a, G, edge_vals=vals)
+    loss = (Y * W).sum()
+    loss.backward()
+    rX, rda, rdA = adjoint.filter_backward(A, 2.0, a.detach().numpy(), X.detach().cpu().double().numpy(),
+                                           W.cpu().double().numpy())
+    assert rel_fro(X.grad.cpu().numpy(), rX) <= 1e-5
+    assert rel_fro(a.grad.numpy(), rda) <= 1e-5
+    assert rel_fro(vals.grad.cpu().numpy(), rdA) <= 1e-5
+
+
+def test_lmax_estimate_is_upper_bound(csc):
+    g = sbm(600, 3, 8.0, 0.2, seed=61)
+    A = oracle_A(g)
+    lam, _ = operator.dense_spectrum(A)
+    G = csc.Graph.from_workload(g)
+    assert G.lmax(0) == 2.0
+    est = G.lmax(100)
+    say(f"  lmax est {est:.6f} true {lam[-1]:.6f}")
+    assert lam[-1] * 0.999 <= est <= 2.0

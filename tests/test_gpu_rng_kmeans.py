@@ -1,0 +1,121 @@
+"""GPU parity of the Philox draws and of k-means (assign, update, k-means++, Lloyd)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kmeans as okm
+from oracle import philox
+from workloads import gaussian_block
+from helpers import near_tie_exempt, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+def test_randn_matches_oracle_philox(csc, dtype):
+    say(f"randn parity {dtype}")
+    n, w = 3001, 7
+    X = csc.randn(n, w, seed=123456789012, stream_id=(5 << 32) + 17, sigma=0.3, dtype=dtype)
+    ref = philox.gaussian_block(n, w, 0.3, 123456789012, (5 << 32) + 17)
+    got = X.double().cpu().numpy()
+    if dtype == torch.float64:
+        assert np.max(np.abs(got - ref)) <= 1e-13
+    elif dtype == torch.float32:
+        assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)) <= 1.2e-7
+    else:
+        assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)) <= 8e-3
+    part = csc.randn(100, w, seed=123456789012, stream_id=(5 << 32) + 17, sigma=0.3,
+                     dtype=torch.float64, row0=2000)
+    assert np.array_equal(part.cpu().numpy(), X.double().cpu().numpy()[2000:2100]) or dtype != torch.float64
+
+
+def test_uniforms_bit_exact(csc):
+    u = csc.uniforms(1000, seed=42, stream_id=34).cpu().numpy()
+    assert np.array_equal(u, philox.uniforms(1000, 42, 34))
+
+
+def _mixture(n, d, k, seed, spread=6.0):
+    rng = np.random.default_rng(seed)
+    centers = rng.standard_normal((k, d)) * spread
+    lab = rng.integers(0, k, size=n)
+    return (centers[lab] + rng.standard_normal((n, d))).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,d,k", [(5000, 32, 5), (20011, 128, 50), (3000, 256, 200), (777, 17, 1)])
+def test_assign_matches_oracle(csc, n, d, k):
+    say(f"kmeans assign n={n} d={d} k={k}")
+    F = _mixture(n, d, max(k, 2), seed=n)
+    C = F[np.random.default_rng(1).choice(n, size=k, replace=False)] + 0.01
+    lab, best = csc.kmeans_assign(torch.from_numpy(F).cuda(), torch.from_numpy(C).cuda())
+    lab = lab.cpu().numpy()
+    ref, d2 = okm.assign(F.astype(np.float64), C.astype(np.float64))
+    exempt, ok_tie = near_tie_exempt(F.astype(np.float64), C.astype(np.float64), lab)
+    mism = (lab != ref) & ~(exempt & ok_tie)
+    assert mism.sum() == 0
+    assert np.allclose(best.cpu().numpy(), d2, rtol=1e-6)
+
+
+def test_assign_exact_ties_lowest_index(csc):
+    F = np.array([[0.0, 0.0], [1.0, 1.0], [0.5, 0.5]], dtype=np.float32)
+    C = np.array([[1.0, 1.0], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0]], dtype=np.float32)
+    lab, _ = csc.kmeans_assign(torch.from_numpy(F).cuda(), torch.from_numpy(C).cuda())
+    assert lab.cpu().tolist() == [1, 0, 0]
+
+
+def test_assign_bf16_features(csc):
+    F = _mixture(4000, 64, 8, seed=3)
+    Fb = torch.from_numpy(F).cuda().to(torch.bfloat16)
+    C = F[:8].copy()
+    lab, _ = csc.kmeans_assign(Fb, torch.from_numpy(C).cuda())
+    F64 = Fb.double().cpu().numpy()
+    ref, _ = okm.assign(F64, C.astype(np.float64))
+    exempt, ok_tie = near_tie_exempt(F64, C.astype(np.float64), lab.cpu().numpy())
+    assert np.sum((lab.cpu().numpy() != ref) & ~(exempt & ok_tie)) == 0
+
+
+@pytest.mark.parametrize("n,d,k", [(5000, 32, 5), (100003, 128, 50), (3000, 256, 200)])
+def test_update_matches_oracle(csc, n, d, k):
+    say(f"kmeans update n={n} d={d} k={k}")
+    F = _mixture(n, d, k, seed=n + 1)
+    rng = np.random.default_rng(2)
+    lab = rng.integers(0, k, size=n).astype(np.int32)
+    lab[lab == k - 1] = 0  # cluster k-1 empty: keeps its previous centroid
+    C0 = rng.standard_normal((k, d)).astype(np.float32)
+    Cg = torch.from_numpy(C0.copy()).cuda()
+    counts = csc.kmeans_update(torch.from_numpy(F).cuda(), torch.from_numpy(lab).cuda(), Cg)
+    ref, rc = okm.update(F.astype(np.float64), lab, C0.astype(np.float64))
+    assert np.array_equal(counts.cpu().numpy(), rc)
+    got = Cg.cpu().numpy()
+    assert np.array_equal(got[k - 1], C0[k - 1])
+    assert np.max(np.abs(got - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+    Cg2 = torch.from_numpy(C0.copy()).cuda()
+    csc.kmeans_update(torch.from_numpy(F).cuda(), torch.from_numpy(lab).cuda(), Cg2)
+    assert torch.equal(Cg, Cg2)
+
+
+@pytest.mark.parametrize("n,d,k", [(3000, 16, 6), (50000, 64, 20)])
+def test_kmeanspp_matches_oracle(csc, n, d, k):
+    say(f"kmeans++ n={n} d={d} k={k}")
+    F = _mixture(n, d, k, seed=7)
+    u = csc.uniforms(k, seed=99, stream_id=2)
+    C, idx = csc.kmeans_seed(torch.from_numpy(F).cuda(), u, k)
+    ref = okm.kmeanspp(F.astype(np.float64), k, philox.uniforms(k, 99, 2))
+    assert idx.cpu().numpy().tolist() == ref.tolist()
+    assert np.array_equal(C.cpu().numpy(), F[ref])
+
+
+def test_lloyd_matches_oracle(csc):
+    n, d, k = 20000, 32, 10
+    F = _mixture(n, d, k, seed=8, spread=3.0)
+    lab, C, obj = csc.kmeans(torch.from_numpy(F).cuda(), k, iters=20, seed=5, stream_id=2,
+                             objective=True)
+    u = philox.uniforms(k, 5, 2)
+    C0 = F.astype(np.float64)[okm.kmeanspp(F, k, u)]
+    rlab, rC, robj = okm.lloyd(F.astype(np.float64), C0, 20)
+    # identical decisions unless a near-tie steered them apart; the objective then agrees
+    agree = np.mean(lab.cpu().numpy() == rlab)
+    say(f"  lloyd label agreement {agree:.6f}, obj {obj[-1]:.6f} vs {robj[-1]:.6f}")
+    assert agree > 0.999
+    assert obj[-1] == pytest.approx(robj[-1], rel=1e-5)
+    assert np.all(np.diff(obj) <= 1e-6 * obj[0])
