@@ -247,6 +247,9 @@ typedef struct {
   int lloyd_iters;    /* Lloyd rounds after seeding, < 0 -> 20 */
   int init;           /* 0: k-means++ every snapshot; 1: warm start from previous labels */
   csc_dtype iter_dt;  /* storage of the recurrence iterates (F32 or BF16) */
+  int keep_iterates;  /* -1: keep all m + 1 iterates of the fresh block when they fit in free
+                         device memory (a refinement then recombines them instead of running
+                         the recurrence again); 0: never; 1: always (CSC_E_NOMEM otherwise) */
 } csc_dyn_opts;
 
 csc_status csc_dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp,

@@ -31,6 +31,11 @@ struct csc_dyn_s {
   size_t kwork_bytes = 0;
   void* dwork = nullptr;
   size_t dwork_bytes = 0;
+  void* basis = nullptr;      // (m + 1) iterate slots of the fresh block, or null
+  size_t basis_bytes = 0;
+  void* aux = nullptr;
+  size_t aux_bytes = 0;
+  int variant = 0;
   int t = 0;
   double lam = 0.0;
   int next_block = 0;
@@ -47,7 +52,7 @@ uint64_t stream_id(int t, uint64_t purpose) { return 16ull * static_cast<uint64_
 void free_dyn(csc_dyn st) {
   if (!st) return;
   for (void* p : {st->theta, st->sig, static_cast<void*>(st->C), static_cast<void*>(st->prev),
-                  static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork})
+                  static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork, st->basis, st->aux})
     if (p) (void)hipFree(p);
   delete st;
 }
@@ -109,6 +114,31 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     free_dyn(st);
     return fail(CSC_E_NOMEM, "device allocation failed in csc_dyn_create");
   }
+  // Keep all m + 1 iterates of the fresh block when they fit: a refinement of the cut-off is
+  // then a new linear combination of stored iterates instead of a second recurrence.
+  const int keep = opts ? opts->keep_iterates : -1;
+  if (keep != 0 && m + 1 <= 512) {
+    Graph probe{};
+    probe.variant_f32 = probe.variant_bf16 = -1;
+    st->variant = default_variant(&probe, qd, st->iter_dt);
+    st->basis_bytes = basis_bytes(n, qd, m, st->iter_dt, st->variant);
+    st->aux_bytes = basis_aux_bytes(n, m);
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    const size_t margin = size_t(4) << 30;
+    if (keep == 1 || st->basis_bytes + st->aux_bytes + margin <= free_b) {
+      if (hipMalloc(&st->basis, st->basis_bytes) != hipSuccess ||
+          hipMalloc(&st->aux, st->aux_bytes) != hipSuccess) {
+        if (keep == 1) {
+          free_dyn(st);
+          return fail(CSC_E_NOMEM, "cannot keep the iterates: allocation failed");
+        }
+        if (st->basis) (void)hipFree(st->basis);
+        if (st->aux) (void)hipFree(st->aux);
+        st->basis = st->aux = nullptr;
+      }
+    }
+  }
   *out = st;
   return CSC_OK;
 }
@@ -151,18 +181,31 @@ csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t,
     CSC_TRY(launch_randn(st->sig, st->feat_dt, st->n, st->qd, st->qd, 0, st->seed,
                          stream_id(t, kSignals), sigma, s));
     cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
-    CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->qd, blk,
-                       st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
-                       st->fwork_bytes, s));
-    CSC_TRY(launch_dot(st->sig, st->feat_dt, st->qd, blk, st->feat_dt, st->d, st->n, st->qd,
-                       st->scal, st->dwork, st->dwork_bytes, s));
+    const bool kept = st->basis != nullptr;
+    if (kept) {
+      CSC_TRY(run_basis(g, st->lmax, st->m, st->sig, st->feat_dt, st->qd, st->qd, st->iter_dt,
+                        st->variant, st->basis, st->basis_bytes, s));
+      CSC_TRY(run_combine(st->basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
+                          st->feat_dt, st->d, st->sig, st->feat_dt, st->qd, st->scal, st->aux,
+                          st->aux_bytes, s));
+    } else {
+      CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->qd, blk,
+                         st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
+                         st->fwork_bytes, s));
+      CSC_TRY(launch_dot(st->sig, st->feat_dt, st->qd, blk, st->feat_dt, st->d, st->n, st->qd,
+                         st->scal, st->dwork, st->dwork_bytes, s));
+    }
     double dot = 0.0;
     CSC_HIP(hipMemcpyAsync(&dot, st->scal, sizeof(double), hipMemcpyDeviceToHost, s));
     CSC_HIP(hipStreamSynchronize(s));
     cnt = dot / (sigma2 * st->qd);
     if (std::fabs(cnt - st->k) > st->tau) {
-      CSC_TRY(run_filter(g, st->lmax, st->m, nullptr, st->sig, st->feat_dt, st->qd, nullptr,
-                         CSC_F32, 0, st->qd, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
+      if (kept)
+        CSC_TRY(run_basis_moments(st->basis, st->n, st->qd, st->m, st->iter_dt, st->variant, mu_d,
+                                  st->aux, st->aux_bytes, s));
+      else
+        CSC_TRY(run_filter(g, st->lmax, st->m, nullptr, st->sig, st->feat_dt, st->qd, nullptr,
+                           CSC_F32, 0, st->qd, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
       CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
       CSC_HIP(hipStreamSynchronize(s));
       const double lo = cnt < st->k ? st->lam : 0.0;
@@ -170,9 +213,14 @@ csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t,
       bisect_moments(mu.data(), st->m, st->lmax, st->damp, sigma2, st->qd, st->k, st->n_cand, lo,
                      hi, &st->lam, &cnt, nullptr);
       cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
-      CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->qd, blk,
-                         st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
-                         st->fwork_bytes, s));
+      if (kept)
+        CSC_TRY(run_combine(st->basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
+                            st->feat_dt, st->d, nullptr, st->feat_dt, 0, nullptr, st->aux,
+                            st->aux_bytes, s));
+      else
+        CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->qd, blk,
+                           st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
+                           st->fwork_bytes, s));
       ref = 1;
     }
     st->next_block = (b + 1) % st->nblocks;

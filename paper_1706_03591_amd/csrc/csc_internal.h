@@ -119,6 +119,19 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
                       int w, csc_dtype iter_dt, double* moments, int moments_only, void* work,
                       size_t work_bytes, hipStream_t s, int variant_override = -2);
 
+// Stored basis Z_0..Z_m (tiled, one slot per j) and its uses.
+size_t basis_bytes(int64_t n, int w, int m, csc_dtype iter_dt, int variant);
+size_t basis_aux_bytes(int64_t n, int m);
+csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtype x_dt, int64_t ldx,
+                     int w, csc_dtype iter_dt, int variant, void* basis, size_t bytes, hipStream_t s);
+csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype iter_dt, int variant,
+                       const double* a, void* Y, csc_dtype y_dt, int64_t ldy, const void* P,
+                       csc_dtype p_dt, int64_t ldp, double* dot, void* aux, size_t aux_bytes,
+                       hipStream_t s);
+csc_status run_basis_moments(const void* basis, int64_t n, int w, int m, csc_dtype iter_dt,
+                             int variant, double* moments, void* aux, size_t aux_bytes,
+                             hipStream_t s);
+
 // ------------------------------------------------------------------------------------
 // reductions, RNG
 

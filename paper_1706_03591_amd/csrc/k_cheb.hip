@@ -855,3 +855,244 @@ csc_status run_backward(const Graph* g, double lmax, int m, const double* a, con
 }
 
 }  // namespace csc
+
+// =====================================================================================
+// Stored basis.  The iterates Z_j = T_j(L~) X, j = 0..m, of one block are all kept (tiled
+// layout, one slot per j), so the filter at any cut-off is the linear combination
+// Y = sum_j a_j Z_j and the Chebyshev moments follow from dot products of stored iterates;
+// a change of cut-off then costs one streaming pass instead of a new recurrence.
+namespace csc {
+
+namespace {
+
+constexpr int kMaxCombine = 512;
+
+struct CombineParams {
+  const void* basis;   // (m + 1) slots of n x wpad (tiled)
+  int64_t slot;        // elements per slot
+  int64_t n;
+  int w, wt, wpad, m;
+  void* Y;
+  int y_dt;
+  int64_t ldy;
+  const void* P;       // optional: <P, Y> partials
+  int p_dt;
+  int64_t ldp;
+  double* part;        // per block
+  float coef[kMaxCombine];
+};
+
+__device__ inline float load_any(const void* p, int dt, int64_t i) {
+  if (dt == CSC_F32) return static_cast<const float*>(p)[i];
+  if (dt == CSC_BF16) return bf16_to_f32(static_cast<const uint16_t*>(p)[i]);
+  return static_cast<float>(static_cast<const double*>(p)[i]);
+}
+
+// One thread per (row, VEC columns of a tile): Y = sum_j a_j Z_j accumulated in FP32 in the
+// order j = 0..m, the same arithmetic as the fused recurrence's accumulator.
+template <typename TZ>
+__global__ __launch_bounds__(kThreads) void k_combine(CombineParams p) {
+  constexpr int VEC = Pack<TZ>::VEC;
+  const int lanes_per_row = p.wpad / VEC;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  double dot = 0.0;
+  if (t < p.n * lanes_per_row) {
+    const int64_t row = t / lanes_per_row;
+    const int q = static_cast<int>(t - row * lanes_per_row);
+    const int col0 = q * VEC;
+    const int tile = col0 / p.wt, c = col0 - tile * p.wt;
+    const TZ* z = static_cast<const TZ*>(p.basis) + static_cast<int64_t>(tile) * p.n * p.wt +
+                  row * p.wt + c;
+    float y[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) y[i] = 0.f;
+    for (int j = 0; j <= p.m; ++j) {
+      float f[VEC];
+      Pack<TZ>::unpack(ld16(z + static_cast<int64_t>(j) * p.slot), f);
+      const float a = p.coef[j];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) y[i] = fmaf(a, f[i], y[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const int col = col0 + i;
+      if (col < p.w) {
+        float yv = y[i];
+        if (p.y_dt == CSC_BF16) yv = bf16_to_f32(f32_to_bf16(yv));
+        store_out(p.Y, p.y_dt, row * p.ldy + col, y[i]);
+        if (p.P) dot += static_cast<double>(load_any(p.P, p.p_dt, row * p.ldp + col)) * static_cast<double>(yv);
+      }
+    }
+  }
+  if (p.part) {
+    double dummy = 0.0;
+    block_reduce2(dot, dummy);
+    if (threadIdx.x == 0) p.part[blockIdx.x] = dot;
+  }
+}
+
+// Partials of <Z_j, Z_j> and <Z_{j+1}, Z_j> for the doubled moments (tiled layout; padded
+// columns are zero).
+template <typename TZ>
+__global__ __launch_bounds__(kThreads) void k_pair_dots(const TZ* zj, const TZ* zj1, int64_t count,
+                                                        double* part) {
+  constexpr int VEC = Pack<TZ>::VEC;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  double d1 = 0.0, d2 = 0.0;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t * VEC < count; t += stride) {
+    float a[VEC], b[VEC];
+    Pack<TZ>::unpack(ld16(zj + t * VEC), a);
+    Pack<TZ>::unpack(ld16(zj1 + t * VEC), b);
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      s1 = fmaf(a[i], a[i], s1);
+      s2 = fmaf(b[i], a[i], s2);
+    }
+    d1 += s1;
+    d2 += s2;
+  }
+  block_reduce2(d1, d2);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = d1;
+    part[gridDim.x + blockIdx.x] = d2;
+  }
+}
+
+constexpr int kPairBlocks = 1024;
+
+}  // namespace
+
+size_t basis_bytes(int64_t n, int w, int m, csc_dtype iter_dt, int variant) {
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
+  return static_cast<size_t>(m + 1) * align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
+}
+
+size_t basis_aux_bytes(int64_t n, int m) {
+  const int J = m / 2;
+  return align_up(static_cast<size_t>(J + 1) * 2 * kPairBlocks * sizeof(double)) +
+         align_up(static_cast<size_t>(J + 1) * 2 * sizeof(double)) +
+         align_up(static_cast<size_t>((n * 256 + kThreads - 1) / kThreads + 1) * sizeof(double));
+}
+
+csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtype x_dt, int64_t ldx,
+                     int w, csc_dtype iter_dt, int variant, void* basis, size_t bytes, hipStream_t s) {
+  const int64_t n = g->n;
+  if (m < 1 || w < 1 || ldx < w || !X) return fail(CSC_E_ARG, "bad basis arguments");
+  if (iter_dt != CSC_F32 && iter_dt != CSC_BF16) return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
+  const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
+  if (!basis || bytes < static_cast<size_t>(m + 1) * slot_bytes) return fail(CSC_E_ARG, "basis buffer too small");
+  char* b = static_cast<char*>(basis);
+  const int wt = pl.shape.wt();
+  {
+    const int64_t total = n * pl.wpad;
+    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+    if (iter_dt == CSC_F32)
+      hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w, pl.wpad,
+                         wt, reinterpret_cast<float*>(b), static_cast<float*>(nullptr), 0.f);
+    else
+      hipLaunchKernelGGL(k_init<uint16_t>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
+                         pl.wpad, wt, reinterpret_cast<uint16_t*>(b), static_cast<float*>(nullptr), 0.f);
+  }
+  const StepFn fn = iter_dt == CSC_F32 ? pick_step<float>(pl.shape.lpr, g->val_dt)
+                                       : pick_step<uint16_t>(pl.shape.lpr, g->val_dt);
+  const int64_t nb = pl.row_blocks * pl.ntiles;
+  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
+  const float beta = static_cast<float>(2.0 / lmax);
+  double bytes_alg = 0.0;
+  timing_begin(s);
+  for (int j = 0; j < m; ++j) {
+    StepParams p{};
+    p.rowptr = g->rowptr;
+    p.colidx = g->colidx;
+    p.vals = g->vals;
+    p.zcur = b + static_cast<size_t>(j) * slot_bytes;
+    p.zprev = j > 0 ? b + static_cast<size_t>(j - 1) * slot_bytes : nullptr;
+    p.zout = b + static_cast<size_t>(j + 1) * slot_bytes;
+    p.w = w;
+    p.n = n;
+    p.row_blocks = pl.row_blocks;
+    p.alpha = alpha;
+    p.beta = beta;
+    p.flags = F_STORE | (j == 0 ? F_FIRST : 0) | (alpha != 0.f ? F_OWN : 0);
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, p);
+    bytes_alg += step_bytes(g, n, w, iter_dt, p.flags, CSC_F32);
+  }
+  timing_end(s, m, bytes_alg);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+// Y = sum_j a_j Z_j from the stored basis; when P is given, *dot (device) = <P, Y> with Y as
+// stored (rounded to y_dt).
+csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype iter_dt, int variant,
+                       const double* a, void* Y, csc_dtype y_dt, int64_t ldy, const void* P,
+                       csc_dtype p_dt, int64_t ldp, double* dot, void* aux, size_t aux_bytes,
+                       hipStream_t s) {
+  if (m + 1 > kMaxCombine) return fail(CSC_E_ARG, "combine supports m < 512");
+  if (!Y || ldy < w) return fail(CSC_E_ARG, "bad Y");
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
+  const int VEC = iter_dt == CSC_F32 ? 4 : 8;
+  const int64_t threads = n * (pl.wpad / VEC);
+  const unsigned blocks = static_cast<unsigned>((threads + kThreads - 1) / kThreads);
+  if (dot && aux_bytes < align_up((blocks + 1) * sizeof(double))) return fail(CSC_E_ARG, "aux too small");
+  CombineParams p{};
+  p.basis = basis;
+  p.slot = static_cast<int64_t>(align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt)) / dtype_size(iter_dt));
+  p.n = n;
+  p.w = w;
+  p.wt = pl.shape.wt();
+  p.wpad = pl.wpad;
+  p.m = m;
+  p.Y = Y;
+  p.y_dt = int(y_dt);
+  p.ldy = ldy;
+  p.P = dot ? P : nullptr;
+  p.p_dt = int(p_dt);
+  p.ldp = ldp;
+  p.part = dot ? static_cast<double*>(aux) : nullptr;
+  for (int j = 0; j <= m; ++j) p.coef[j] = static_cast<float>(a[j]);
+  if (iter_dt == CSC_F32)
+    hipLaunchKernelGGL(k_combine<float>, dim3(blocks), dim3(kThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL(k_combine<uint16_t>, dim3(blocks), dim3(kThreads), 0, s, p);
+  if (dot) hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kThreads), 0, s, static_cast<double*>(aux),
+                              static_cast<int64_t>(blocks), dot);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+// mu_0..mu_m (device) from the stored basis by the doubling identities.
+csc_status run_basis_moments(const void* basis, int64_t n, int w, int m, csc_dtype iter_dt,
+                             int variant, double* moments, void* aux, size_t aux_bytes,
+                             hipStream_t s) {
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
+  const int J = m / 2;
+  const size_t part_bytes = align_up(static_cast<size_t>(J + 1) * 2 * kPairBlocks * sizeof(double));
+  if (aux_bytes < part_bytes + align_up(static_cast<size_t>(J + 1) * 2 * sizeof(double)))
+    return fail(CSC_E_ARG, "aux too small");
+  double* part = static_cast<double*>(aux);
+  double* sums = reinterpret_cast<double*>(static_cast<char*>(aux) + part_bytes);
+  const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
+  const int64_t count = n * pl.wpad;
+  const char* b = static_cast<const char*>(basis);
+  for (int j = 0; j <= J; ++j) {
+    const void* zj = b + static_cast<size_t>(j) * slot_bytes;
+    const void* zj1 = b + static_cast<size_t>(j + 1) * slot_bytes;
+    double* pj = part + static_cast<int64_t>(j) * 2 * kPairBlocks;
+    if (iter_dt == CSC_F32)
+      hipLaunchKernelGGL(k_pair_dots<float>, dim3(kPairBlocks), dim3(kThreads), 0, s,
+                         static_cast<const float*>(zj), static_cast<const float*>(zj1), count, pj);
+    else
+      hipLaunchKernelGGL(k_pair_dots<uint16_t>, dim3(kPairBlocks), dim3(kThreads), 0, s,
+                         static_cast<const uint16_t*>(zj), static_cast<const uint16_t*>(zj1), count, pj);
+  }
+  hipLaunchKernelGGL(k_reduce_rows, dim3(2 * (J + 1)), dim3(kThreads), 0, s, part,
+                     static_cast<int64_t>(kPairBlocks), sums);
+  hipLaunchKernelGGL(k_moments, dim3(1), dim3(64), 0, s, sums, J, m, moments);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+}  // namespace csc

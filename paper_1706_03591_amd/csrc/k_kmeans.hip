@@ -1,11 +1,26 @@
 // k-means on the rows of the spectral features (Sec. 2.1, eq. SC_cost): assignment,
-// Lloyd update and k-means++ seeding, all with fixed-order reductions.
+// Lloyd update and k-means++ seeding.
 //
-// Rows are served by groups of kG = 16 lanes; lane l of a group holds columns l, l + 16,
-// l + 32, ... of its row, so a row load is coalesced and the centroid reads from LDS are
-// broadcasts across the rows of a wave.  Distances to every centroid are ranked in FP32
-// (direct form sum (f - mu)^2, so no cancellation), and the two best are re-scored in FP64
-// so that the chosen label is the exact FP64 argmin of the two (ties to the lowest index).
+// Rows are served by groups of G lanes.  When a row is a whole number of 16-byte chunks
+// (d * sizeof(elem) a multiple of 16 and G = d / VEC a power of two), lane l owns the VEC
+// contiguous columns l * VEC .. l * VEC + VEC - 1 and loads them with one vector load;
+// otherwise lane l owns columns l, l + 16, l + 32, ... (G = 16).
+//
+// Assignment: centroids are staged in LDS once per block and the block walks many rows.
+// Distances are ranked in FP32 in the direct form sum (f - mu)^2 (no cancellation) and the
+// two best candidates are re-scored in FP64, so the chosen label is the exact FP64 argmin
+// of the two, ties going to the lowest index.
+//
+// Update: sums of the rows of each cluster in 64-bit fixed point (scale 2^S chosen from
+// max |F| and n so that no sum can overflow), accumulated with integer atomics in LDS and
+// then in global memory.  Integer addition is associative, so the sums do not depend on
+// the order of the atomics and the update is bit-reproducible; the quantisation step
+// 2^-S is far below FP32 resolution.
+//
+// k-means++: FP64 squared distances to the newest centre, block sums over contiguous row
+// ranges, and a one-block pick of the first row whose running sum exceeds u_j * total.
+#include <cmath>
+
 #include "csc_internal.h"
 
 namespace csc {
@@ -13,24 +28,67 @@ namespace csc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kG = 16;             // lanes per row
-constexpr int kMaxV = 16;          // columns per lane -> d <= 256
-constexpr int kRowsPB = kThreads / kG;
-constexpr int kLdsFloats = 12288;  // 48 KB of centroids per chunk
+constexpr int kScalarG = 16;
+constexpr int kScalarNV = 16;         // scalar path: d <= 256
+constexpr int kLdsCentroids = 15360;  // floats of centroids staged per block (60 KB)
+constexpr int kPPIters = 8;           // row iterations per k-means++ block
 
-__device__ inline float ld_f(const void* F, int dt, int64_t i) {
-  return dt == CSC_F32 ? static_cast<const float*>(F)[i]
-                       : bf16_to_f32(static_cast<const uint16_t*>(F)[i]);
+template <typename TF>
+__device__ inline float to_f(TF v);
+template <>
+__device__ inline float to_f<float>(float v) { return v; }
+template <>
+__device__ inline float to_f<uint16_t>(uint16_t v) { return bf16_to_f32(v); }
+
+// Load the NV values a lane owns in one row (zeros when invalid or past d).
+template <typename TF, int G, int NV, bool VECL>
+__device__ inline void load_row(const TF* F, int64_t row, int64_t ldf, int lane, int d, bool valid,
+                                float* f) {
+  if constexpr (VECL) {
+    static_assert(NV * sizeof(TF) == 16, "one 16-byte chunk per lane");
+    if (valid) {
+      const uint4 u = *reinterpret_cast<const uint4*>(F + row * ldf + lane * NV);
+      if constexpr (sizeof(TF) == 4) {
+        f[0] = __uint_as_float(u.x);
+        f[1] = __uint_as_float(u.y);
+        f[2] = __uint_as_float(u.z);
+        f[3] = __uint_as_float(u.w);
+      } else {
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          f[2 * i] = __uint_as_float(w[i] << 16);
+          f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) f[i] = 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int col = lane + i * G;
+      f[i] = (valid && col < d) ? to_f<TF>(F[row * ldf + col]) : 0.f;
+    }
+  }
 }
 
+template <int G, int NV, bool VECL>
+__device__ inline int col_of(int lane, int i) {
+  return VECL ? lane * NV + i : lane + i * G;
+}
+
+template <int G>
 __device__ inline float grp_sum(float v) {
 #pragma unroll
-  for (int off = kG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kG);
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
   return v;
 }
+template <int G>
 __device__ inline double grp_sum(double v) {
 #pragma unroll
-  for (int off = kG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kG);
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
   return v;
 }
 
@@ -42,26 +100,92 @@ __device__ inline double block_sum(double v) {
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < kThreads / 64; ++i) s += red[i];
+    for (int i = 0; i < static_cast<int>(blockDim.x / 64); ++i) s += red[i];
   __syncthreads();
   return s;
 }
 
-__global__ __launch_bounds__(kThreads) void k_assign(const void* F, int f_dt, int64_t ldf,
-                                                     int64_t n, int d, const float* C, int k,
-                                                     int kc, int32_t* labels, float* best_d2,
-                                                     double* obj_part) {
-  __shared__ float s_c[kLdsFloats];
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPB + threadIdx.x / kG;
-  const int lane = threadIdx.x % kG;
-  const bool valid = row < n;
-  const int nv = (d + kG - 1) / kG;
-  float f[kMaxV];
+// ---------------- assignment ----------------
+
+template <typename TF, int G, int NV, bool VECL>
+__global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, int64_t n, int d,
+                                                     const float* C, int k, int32_t* labels,
+                                                     float* best_d2, double* obj_part) {
+  extern __shared__ float s_c[];  // k * d
+  constexpr int RPI = kThreads / G;
+  for (int t = threadIdx.x; t < k * d; t += kThreads) s_c[t] = C[t];
+  __syncthreads();
+  const int lane = threadIdx.x % G;
+  double objsum = 0.0;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * RPI; base < n;
+       base += static_cast<int64_t>(gridDim.x) * RPI) {
+    const int64_t row = base + threadIdx.x / G;
+    const bool valid = row < n;
+    float f[NV];
+    load_row<TF, G, NV, VECL>(F, row, ldf, lane, d, valid, f);
+    float b1 = INFINITY, b2 = INFINITY;
+    int i1 = 0, i2 = -1;
+    for (int c = 0; c < k; ++c) {
+      const float* cc = s_c + c * d;
+      float s = 0.f;
 #pragma unroll
-  for (int i = 0; i < kMaxV; ++i) {
-    const int col = lane + i * kG;
-    f[i] = (valid && i < nv && col < d) ? ld_f(F, f_dt, row * ldf + col) : 0.f;
+      for (int i = 0; i < NV; ++i) {
+        const int col = col_of<G, NV, VECL>(lane, i);
+        if (VECL || col < d) {
+          const float t = f[i] - cc[col];
+          s = fmaf(t, t, s);
+        }
+      }
+      s = grp_sum<G>(s);
+      if (s < b1) { b2 = b1; i2 = i1; b1 = s; i1 = c; }
+      else if (s < b2) { b2 = s; i2 = c; }
+    }
+    double e1 = 0.0, e2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int col = col_of<G, NV, VECL>(lane, i);
+      if (VECL || col < d) {
+        const double t1 = static_cast<double>(f[i]) - static_cast<double>(s_c[i1 * d + col]);
+        e1 += t1 * t1;
+        if (i2 >= 0) {
+          const double t2 = static_cast<double>(f[i]) - static_cast<double>(s_c[i2 * d + col]);
+          e2 += t2 * t2;
+        }
+      }
+    }
+    e1 = grp_sum<G>(e1);
+    e2 = grp_sum<G>(e2);
+    int lab = i1;
+    double best = e1;
+    if (i2 >= 0 && (e2 < e1 || (e2 == e1 && i2 < i1))) { lab = i2; best = e2; }
+    if (valid && lane == 0) {
+      labels[row] = lab;
+      if (best_d2) best_d2[row] = static_cast<float>(best);
+      objsum += best;
+    }
   }
+  if (obj_part) {
+    const double s = block_sum(objsum);
+    if (threadIdx.x == 0) obj_part[blockIdx.x] = s;
+  }
+}
+
+// Fallback when the centroids do not fit in LDS: one row group per row, centroids staged in
+// chunks for every block of rows.
+__global__ __launch_bounds__(kThreads) void k_assign_chunked(const void* F, int f_dt, int64_t ldf,
+                                                             int64_t n, int d, const float* C,
+                                                             int k, int kc, int32_t* labels,
+                                                             float* best_d2, double* obj_part) {
+  __shared__ float s_c[12288];
+  constexpr int G = kScalarG, NV = kScalarNV;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * (kThreads / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  const bool valid = row < n;
+  float f[NV];
+  if (f_dt == CSC_F32)
+    load_row<float, G, NV, false>(static_cast<const float*>(F), row, ldf, lane, d, valid, f);
+  else
+    load_row<uint16_t, G, NV, false>(static_cast<const uint16_t*>(F), row, ldf, lane, d, valid, f);
   float b1 = INFINITY, b2 = INFINITY;
   int i1 = 0, i2 = -1;
   for (int c0 = 0; c0 < k; c0 += kc) {
@@ -70,28 +194,26 @@ __global__ __launch_bounds__(kThreads) void k_assign(const void* F, int f_dt, in
     for (int t = threadIdx.x; t < cn * d; t += kThreads) s_c[t] = C[static_cast<int64_t>(c0) * d + t];
     __syncthreads();
     for (int c = 0; c < cn; ++c) {
-      const float* cc = s_c + c * d;
       float s = 0.f;
 #pragma unroll
-      for (int i = 0; i < kMaxV; ++i) {
-        const int col = lane + i * kG;
-        if (i < nv && col < d) {
-          const float t = f[i] - cc[col];
+      for (int i = 0; i < NV; ++i) {
+        const int col = lane + i * G;
+        if (col < d) {
+          const float t = f[i] - s_c[c * d + col];
           s = fmaf(t, t, s);
         }
       }
-      s = grp_sum(s);
+      s = grp_sum<G>(s);
       const int ci = c0 + c;
       if (s < b1) { b2 = b1; i2 = i1; b1 = s; i1 = ci; }
       else if (s < b2) { b2 = s; i2 = ci; }
     }
   }
-  // FP64 re-score of the two best candidates
   double e1 = 0.0, e2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < kMaxV; ++i) {
-    const int col = lane + i * kG;
-    if (i < nv && col < d) {
+  for (int i = 0; i < NV; ++i) {
+    const int col = lane + i * G;
+    if (col < d) {
       const double t1 = static_cast<double>(f[i]) - static_cast<double>(C[static_cast<int64_t>(i1) * d + col]);
       e1 += t1 * t1;
       if (i2 >= 0) {
@@ -100,8 +222,8 @@ __global__ __launch_bounds__(kThreads) void k_assign(const void* F, int f_dt, in
       }
     }
   }
-  e1 = grp_sum(e1);
-  e2 = grp_sum(e2);
+  e1 = grp_sum<G>(e1);
+  e2 = grp_sum<G>(e2);
   int lab = i1;
   double best = e1;
   if (i2 >= 0 && (e2 < e1 || (e2 == e1 && i2 < i1))) { lab = i2; best = e2; }
@@ -110,153 +232,211 @@ __global__ __launch_bounds__(kThreads) void k_assign(const void* F, int f_dt, in
     if (best_d2) best_d2[row] = static_cast<float>(best);
   }
   if (obj_part) {
-    const double v = (valid && lane == 0) ? best : 0.0;
-    const double s = block_sum(v);
+    const double s = block_sum((valid && lane == 0) ? best : 0.0);
     if (threadIdx.x == 0) obj_part[blockIdx.x] = s;
   }
 }
 
-// Per-block partial sums for the Lloyd update.  Block (b, y) owns rows [b * rpb, ...) and
-// columns [64 y, 64 y + 64); `groups` copies of the k x 64 LDS accumulator let thread
-// groups take interleaved rows; each thread owns one column, so every sum runs in a fixed
-// order.  Counts come from column chunk 0.
-__global__ void k_update_part(const void* F, int f_dt, int64_t ldf, int64_t n, int d,
-                              const int32_t* labels, int k, int64_t rpb, int groups,
-                              float* part, int32_t* cpart) {
-  extern __shared__ float s_acc[];  // [groups][k][64] floats then [groups][k] ints
-  int32_t* s_cnt = reinterpret_cast<int32_t*>(s_acc + static_cast<size_t>(groups) * k * 64);
-  const int g = threadIdx.x / 64;
-  const int cl = threadIdx.x % 64;
-  const int col = blockIdx.y * 64 + cl;
-  for (int t = threadIdx.x; t < groups * k * 64; t += blockDim.x) s_acc[t] = 0.f;
-  for (int t = threadIdx.x; t < groups * k; t += blockDim.x) s_cnt[t] = 0;
+// ---------------- Lloyd update in fixed point ----------------
+
+// Scale exponent S: every partial or total sum of n values below 2^e stays below 2^62.
+__device__ inline int fixed_scale(float maxabs, int64_t n) {
+  int e = 0;
+  frexpf(maxabs, &e);  // maxabs < 2^e
+  int ln = 0;
+  while ((int64_t(1) << ln) < n) ++ln;
+  int S = 62 - e - ln;
+  return S < -60 ? -60 : (S > 120 ? 120 : S);
+}
+
+__global__ void k_upd_clear(unsigned long long* sums, int64_t kd, int32_t* cnt, int k,
+                            uint32_t* maxabs) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < kd) sums[t] = 0ull;
+  if (t < k) cnt[t] = 0;
+  if (t == 0) maxabs[0] = 0u;
+}
+
+template <typename TF>
+__global__ void k_maxabs(const TF* F, int64_t ldf, int64_t n, int d, uint32_t* out) {
+  const int64_t total = n * d;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  float m = 0.f;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t r = i / d;
+    const int c = static_cast<int>(i - r * d);
+    m = fmaxf(m, fabsf(to_f<TF>(F[r * ldf + c])));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+// Block (b, y): rows [b * rpb, ...), columns [y * cw, y * cw + cw).  LDS holds the k x cw
+// fixed-point sums; thread groups take interleaved rows; integer atomics make the result
+// independent of the order.
+template <typename TF>
+__global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, int64_t n, int d,
+                                                      const int32_t* labels, int k, int64_t rpb,
+                                                      int cw, const uint32_t* maxabs,
+                                                      unsigned long long* gsums, int32_t* gcnt) {
+  extern __shared__ unsigned long long s_acc[];  // k * cw, then k ints
+  int32_t* s_cnt = reinterpret_cast<int32_t*>(s_acc + static_cast<size_t>(k) * cw);
+  for (int t = threadIdx.x; t < k * cw; t += kThreads) s_acc[t] = 0ull;
+  for (int t = threadIdx.x; t < k; t += kThreads) s_cnt[t] = 0;
   __syncthreads();
+  const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
+  const int groups = kThreads / cw;
+  const int g = threadIdx.x / cw;
+  const int cl = threadIdx.x % cw;
+  const int col = blockIdx.y * cw + cl;
+  const bool colok = col < d;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rpb;
   const int64_t r1 = min(r0 + rpb, n);
-  float* acc = s_acc + static_cast<size_t>(g) * k * 64;
-  const bool colok = col < d;
+  const bool counter = cl == 0 && blockIdx.y == 0;
   int64_t r = r0 + g;
   for (; r + 3 * groups < r1; r += 4 * groups) {
-    const int la = labels[r], lb = labels[r + groups], lc = labels[r + 2 * groups],
-              le = labels[r + 3 * groups];
-    float va = 0.f, vb = 0.f, vc = 0.f, vd = 0.f;
-    if (colok) {
-      va = ld_f(F, f_dt, r * ldf + col);
-      vb = ld_f(F, f_dt, (r + groups) * ldf + col);
-      vc = ld_f(F, f_dt, (r + 2 * groups) * ldf + col);
-      vd = ld_f(F, f_dt, (r + 3 * groups) * ldf + col);
+    int lb[4];
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      lb[q] = labels[r + q * groups];
+      v[q] = colok ? to_f<TF>(F[(r + q * groups) * ldf + col]) : 0.f;
     }
-    acc[la * 64 + cl] += va;
-    acc[lb * 64 + cl] += vb;
-    acc[lc * 64 + cl] += vc;
-    acc[le * 64 + cl] += vd;
-    if (cl == 0 && blockIdx.y == 0) {
-      s_cnt[g * k + la] += 1;
-      s_cnt[g * k + lb] += 1;
-      s_cnt[g * k + lc] += 1;
-      s_cnt[g * k + le] += 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long fx = llrint(ldexp(static_cast<double>(v[q]), S));
+      atomicAdd(&s_acc[lb[q] * cw + cl], static_cast<unsigned long long>(fx));
+      if (counter) atomicAdd(&s_cnt[lb[q]], 1);
     }
   }
   for (; r < r1; r += groups) {
-    const int la = labels[r];
-    acc[la * 64 + cl] += colok ? ld_f(F, f_dt, r * ldf + col) : 0.f;
-    if (cl == 0 && blockIdx.y == 0) s_cnt[g * k + la] += 1;
+    const int lb = labels[r];
+    const float v = colok ? to_f<TF>(F[r * ldf + col]) : 0.f;
+    const long long fx = llrint(ldexp(static_cast<double>(v), S));
+    atomicAdd(&s_acc[lb * cw + cl], static_cast<unsigned long long>(fx));
+    if (counter) atomicAdd(&s_cnt[lb], 1);
   }
   __syncthreads();
-  if (colok) {
-    for (int c = g; c < k; c += groups) {
-      float s = 0.f;
-      for (int q = 0; q < groups; ++q) s += s_acc[(static_cast<size_t>(q) * k + c) * 64 + cl];
-      part[(static_cast<int64_t>(blockIdx.x) * k + c) * d + col] = s;
-    }
+  for (int t = threadIdx.x; t < k * cw; t += kThreads) {
+    const int c = t / cw, cc = t % cw;
+    const int gc = blockIdx.y * cw + cc;
+    if (gc < d && s_acc[t] != 0ull) atomicAdd(&gsums[static_cast<int64_t>(c) * d + gc], s_acc[t]);
   }
-  if (blockIdx.y == 0) {
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-      int s = 0;
-      for (int q = 0; q < groups; ++q) s += s_cnt[q * k + c];
-      cpart[static_cast<int64_t>(blockIdx.x) * k + c] = s;
-    }
-  }
+  if (blockIdx.y == 0)
+    for (int t = threadIdx.x; t < k; t += kThreads)
+      if (s_cnt[t]) atomicAdd(&gcnt[t], s_cnt[t]);
 }
 
-__global__ void k_update_final(const float* part, const int32_t* cpart, int64_t nblk, int k,
-                               int d, float* C, int32_t* counts) {
+__global__ void k_upd_final(const unsigned long long* gsums, const int32_t* gcnt,
+                            const uint32_t* maxabs, int64_t n, int k, int d, float* C,
+                            int32_t* counts) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<int64_t>(k) * d) return;
   const int c = static_cast<int>(t / d);
-  int64_t cnt = 0;
-  for (int64_t b = 0; b < nblk; ++b) cnt += cpart[b * k + c];
-  double s = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) s += static_cast<double>(part[b * k * d + t]);
-  if (cnt > 0) C[t] = static_cast<float>(s / static_cast<double>(cnt));
-  if (counts && (t % d) == 0) counts[c] = static_cast<int32_t>(cnt);
+  const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
+  const int32_t cnt = gcnt[c];
+  if (cnt > 0) {
+    const double sum = ldexp(static_cast<double>(static_cast<long long>(gsums[t])), -S);
+    C[t] = static_cast<float>(sum / static_cast<double>(cnt));
+  }
+  if (counts && (t % d) == 0) counts[c] = cnt;
 }
 
 // ---------------- k-means++ ----------------
 
-__global__ void k_pp_first(const void* F, int f_dt, int64_t ldf, int64_t n, int d,
-                           const double* u, float* C, int32_t* idx, int32_t* sel) {
+template <typename TF>
+__global__ void k_pp_first(const TF* F, int64_t ldf, int64_t n, int d, const double* u, float* C,
+                           int32_t* idx, int32_t* sel) {
   int64_t i = static_cast<int64_t>(floor(u[0] * static_cast<double>(n)));
-  if (i > n - 1) i = n - 1;
-  if (i < 0) i = 0;
+  i = i > n - 1 ? n - 1 : (i < 0 ? 0 : i);
   if (threadIdx.x == 0) {
     sel[0] = static_cast<int32_t>(i);
     if (idx) idx[0] = static_cast<int32_t>(i);
   }
-  for (int t = threadIdx.x; t < d; t += blockDim.x) C[t] = ld_f(F, f_dt, i * ldf + t);
+  for (int t = threadIdx.x; t < d; t += blockDim.x) C[t] = to_f<TF>(F[i * ldf + t]);
 }
 
-// d2[i] = min(d2[i], ||f_i - C[j]||^2) in FP64 (first round: the distance itself); block
-// sums of d2 in a fixed order.
-__global__ __launch_bounds__(kThreads) void k_pp_dist(const void* F, int f_dt, int64_t ldf,
-                                                      int64_t n, int d, const float* Cj, int first,
-                                                      double* d2, double* bsum) {
-  __shared__ double s_d[kRowsPB];
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPB + threadIdx.x / kG;
-  const int lane = threadIdx.x % kG;
-  double s = 0.0;
-  if (row < n) {
-    for (int col = lane; col < d; col += kG) {
-      const double t = static_cast<double>(ld_f(F, f_dt, row * ldf + col)) - static_cast<double>(Cj[col]);
+// d2[i] = min(d2[i], ||f_i - Cj||^2) in FP64 (first round: the distance itself) for the
+// contiguous rows [b * RPI * kPPIters, ...) of block b; bsum[b] = their sum (fixed tree).
+template <typename TF, int G, int NV, bool VECL>
+__global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, int64_t n, int d,
+                                                      const float* Cj, int first, double* d2,
+                                                      double* bsum) {
+  constexpr int RPI = kThreads / G;
+  constexpr int R = RPI * kPPIters;
+  __shared__ double s_d[R];
+  const int lane = threadIdx.x % G;
+  float cj[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int col = col_of<G, NV, VECL>(lane, i);
+    cj[i] = (VECL || col < d) ? Cj[col] : 0.f;
+  }
+  const int64_t rbase = static_cast<int64_t>(blockIdx.x) * R;
+  for (int it = 0; it < kPPIters; ++it) {
+    const int loc = it * RPI + threadIdx.x / G;
+    const int64_t row = rbase + loc;
+    const bool valid = row < n;
+    float f[NV];
+    load_row<TF, G, NV, VECL>(F, row, ldf, lane, d, valid, f);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double t = static_cast<double>(f[i]) - static_cast<double>(cj[i]);
       s += t * t;
     }
-  }
-  s = grp_sum(s);
-  if (lane == 0) {
-    double v = 0.0;
-    if (row < n) {
-      v = first ? s : fmin(d2[row], s);
-      d2[row] = v;
+    s = grp_sum<G>(s);
+    if (lane == 0) {
+      double v = 0.0;
+      if (valid) {
+        v = first ? s : fmin(d2[row], s);
+        d2[row] = v;
+      }
+      s_d[loc] = v;
     }
-    s_d[threadIdx.x / kG] = v;
+  }
+  __syncthreads();
+  for (int w = R / 2; w > 0; w >>= 1) {
+    for (int t = threadIdx.x; t < w; t += kThreads) s_d[t] += s_d[t + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s_d[0];
+}
+
+// Pick centre j (1024 threads): chunk sums of the block sums, the chunk and block where the
+// running sum passes u_j * total, then the row inside that block (running sum in row order).
+template <typename TF>
+__global__ __launch_bounds__(1024) void k_pp_pick(const TF* F, int64_t ldf, int64_t n, int d,
+                                                  const double* d2, const double* bsum,
+                                                  int64_t nblk, int64_t rows_per_blk,
+                                                  const double* u, int j, float* C, int32_t* idx,
+                                                  int32_t* sel) {
+  __shared__ double s_chunk[1024];
+  __shared__ int64_t s_pick;
+  const int64_t chunk = (nblk + 1023) / 1024;
+  {
+    double s = 0.0;
+    const int64_t b0 = static_cast<int64_t>(threadIdx.x) * chunk;
+    for (int64_t b = b0; b < min(b0 + chunk, nblk); ++b) s += bsum[b];
+    s_chunk[threadIdx.x] = s;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double b = 0.0;
-    for (int i = 0; i < kRowsPB; ++i) b += s_d[i];
-    bsum[blockIdx.x] = b;
-  }
-}
-
-// Pick centre j: the first row whose running sum of d2 exceeds u[j] * total (running sum
-// over the blocks' sums in block order, then over the rows of the crossing block in row
-// order, the same order that formed each block sum).  One thread does the scan.
-__global__ void k_pp_pick(const void* F, int f_dt, int64_t ldf, int64_t n, int d,
-                          const double* d2, const double* bsum, int64_t nblk, const double* u,
-                          int j, float* C, int32_t* idx, int32_t* sel) {
-  __shared__ int64_t s_pick;
-  if (threadIdx.x == 0) {
     double total = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) total += bsum[b];
+    for (int i = 0; i < 1024; ++i) total += s_chunk[i];
     int64_t pick = sel[0];  // all distances zero: repeat the previous centre
     if (total > 0.0) {
       const double thr = u[j] * total;
       double run = 0.0;
-      int64_t b = 0;
-      while (b < nblk && run + bsum[b] <= thr) { run += bsum[b]; ++b; }
-      if (b == nblk) { b = nblk - 1; run -= bsum[b]; }
-      int64_t r = b * kRowsPB;
-      const int64_t rend = min(r + kRowsPB, n);
+      int c = 0;
+      while (c < 1023 && run + s_chunk[c] <= thr) run += s_chunk[c++];
+      int64_t b = static_cast<int64_t>(c) * chunk;
+      const int64_t bend = min(b + chunk, nblk);
+      while (b < bend - 1 && run + bsum[b] <= thr) run += bsum[b++];
+      if (b >= nblk) b = nblk - 1;
+      int64_t r = b * rows_per_blk;
+      const int64_t rend = min(r + rows_per_blk, n);
       pick = rend - 1;
       for (; r < rend; ++r) {
         run += d2[r];
@@ -270,7 +450,7 @@ __global__ void k_pp_pick(const void* F, int f_dt, int64_t ldf, int64_t n, int d
   __syncthreads();
   const int64_t pick = s_pick;
   for (int t = threadIdx.x; t < d; t += blockDim.x)
-    C[static_cast<int64_t>(j) * d + t] = ld_f(F, f_dt, pick * ldf + t);
+    C[static_cast<int64_t>(j) * d + t] = to_f<TF>(F[pick * ldf + t]);
 }
 
 __global__ void k_sum_into(const double* part, int64_t nb, double* out) {
@@ -280,32 +460,93 @@ __global__ void k_sum_into(const double* part, int64_t nb, double* out) {
   if (threadIdx.x == 0) out[0] = s;
 }
 
+// ---------------- dispatch ----------------
+
+// Row-group shape for (d, element size, pointer, ld): vectorised when possible.
+struct RowShape {
+  bool vec;
+  int G;  // lanes per row
+};
+
+RowShape row_shape(const void* F, csc_dtype f_dt, int64_t ldf, int d) {
+  const int es = static_cast<int>(dtype_size(f_dt));
+  const int vecn = 16 / es;
+  const bool aligned = (reinterpret_cast<uintptr_t>(F) % 16 == 0) && ((ldf * es) % 16 == 0);
+  if (aligned && d % vecn == 0) {
+    const int G = d / vecn;
+    if (G >= 2 && G <= 64 && (G & (G - 1)) == 0) return RowShape{true, G};
+  }
+  return RowShape{false, kScalarG};
+}
+
+template <typename TF, int NV>
+csc_status launch_assign_vec(int G, const TF* F, int64_t ldf, int64_t n, int d, const float* C,
+                             int k, int32_t* labels, float* best_d2, double* obj_part,
+                             unsigned blocks, size_t lds, hipStream_t s) {
+#define CSC_ASSIGN_CASE(GG)                                                                   \
+  case GG:                                                                                    \
+    hipLaunchKernelGGL((k_assign<TF, GG, NV, true>), dim3(blocks), dim3(kThreads), lds, s, F, \
+                       ldf, n, d, C, k, labels, best_d2, obj_part);                           \
+    break;
+  switch (G) {
+    CSC_ASSIGN_CASE(2)
+    CSC_ASSIGN_CASE(4)
+    CSC_ASSIGN_CASE(8)
+    CSC_ASSIGN_CASE(16)
+    CSC_ASSIGN_CASE(32)
+    CSC_ASSIGN_CASE(64)
+    default: return fail(CSC_E_ARG, "bad row group");
+  }
+#undef CSC_ASSIGN_CASE
+  return CSC_OK;
+}
+
+template <typename TF, int NV>
+csc_status launch_ppdist_vec(int G, const TF* F, int64_t ldf, int64_t n, int d, const float* Cj,
+                             int first, double* d2, double* bsum, hipStream_t s) {
+  const int64_t R = static_cast<int64_t>(kThreads / G) * kPPIters;
+  const unsigned blocks = static_cast<unsigned>((n + R - 1) / R);
+#define CSC_PP_CASE(GG)                                                                          \
+  case GG:                                                                                       \
+    hipLaunchKernelGGL((k_pp_dist<TF, GG, NV, true>), dim3(blocks), dim3(kThreads), 0, s, F, ldf, \
+                       n, d, Cj, first, d2, bsum);                                               \
+    break;
+  switch (G) {
+    CSC_PP_CASE(2)
+    CSC_PP_CASE(4)
+    CSC_PP_CASE(8)
+    CSC_PP_CASE(16)
+    CSC_PP_CASE(32)
+    CSC_PP_CASE(64)
+    default: return fail(CSC_E_ARG, "bad row group");
+  }
+#undef CSC_PP_CASE
+  return CSC_OK;
+}
+
+int64_t assign_grid(int64_t n, int G) {
+  const int64_t rpi = kThreads / G;
+  return std::max<int64_t>(1, std::min<int64_t>(2048, (n + rpi - 1) / rpi));
+}
+
 struct KmLayout {
-  int64_t nblk_upd, rpb, assign_blocks, pp_blocks;
-  int groups;
-  size_t off_u, off_d2, off_bsum, off_part, off_cpart, off_obj, off_objv, off_sel, total;
+  size_t off_u, off_d2, off_bsum, off_sums, off_cnt, off_max, off_obj, off_objv, off_sel, total;
 };
 
 KmLayout km_layout(int64_t n, int d, int k) {
   KmLayout L{};
-  L.assign_blocks = (n + kRowsPB - 1) / kRowsPB;
-  L.pp_blocks = L.assign_blocks;
-  const int64_t dch = (d + 63) / 64;
-  (void)dch;
-  int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(2048, (n + 255) / 256));
-  while (nblk > 64 && static_cast<double>(nblk) * k * d * 4.0 > 256.0 * 1024 * 1024) nblk /= 2;
-  L.nblk_upd = nblk;
-  L.rpb = (n + nblk - 1) / nblk;
-  int groups = 4;
-  while (groups > 1 && static_cast<size_t>(groups) * k * (64 * 4 + 4) > 60 * 1024) groups /= 2;
-  L.groups = groups;
+  // k-means++ blocks cover at least 32 rows (G = 64); the chunked assignment writes one
+  // objective partial per 16 rows
+  const int64_t pp_blocks = (n + 31) / 32;
+  const int64_t obj_parts = std::max<int64_t>(2048, (n + 15) / 16);
   size_t off = 0;
   L.off_u = off; off += align_up(static_cast<size_t>(k) * 8);
   L.off_d2 = off; off += align_up(static_cast<size_t>(n) * 8);
-  L.off_bsum = off; off += align_up(static_cast<size_t>(L.pp_blocks) * 8);
-  L.off_part = off; off += align_up(static_cast<size_t>(nblk) * k * d * 4);
-  L.off_cpart = off; off += align_up(static_cast<size_t>(nblk) * k * 4);
-  L.off_obj = off; off += align_up(static_cast<size_t>(L.assign_blocks) * 8);
+  L.off_bsum = off; off += align_up(static_cast<size_t>(pp_blocks) * 8);
+  L.off_sums = off; off += align_up(static_cast<size_t>(k) * d * 8);
+  L.off_cnt = off; off += align_up(static_cast<size_t>(k) * 4);
+  L.off_max = off; off += 256;
+  L.off_obj = off; off += align_up(static_cast<size_t>(obj_parts) * 8);
   L.off_objv = off; off += align_up(static_cast<size_t>(1024 + 1) * 8);
   L.off_sel = off; off += 256;
   L.total = off;
@@ -316,11 +557,20 @@ csc_status check_f(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                    bool need_k_le_n = false) {
   if (!F || n < 1 || d < 1 || ldf < d) return fail(CSC_E_ARG, "bad feature block");
   if (f_dt != CSC_F32 && f_dt != CSC_BF16) return fail(CSC_E_DTYPE, "features must be F32 or BF16");
-  if (d > kG * kMaxV) return fail(CSC_E_ARG, "d must be <= 256");
+  if (d > kScalarG * kScalarNV) return fail(CSC_E_ARG, "d must be <= 256");
   if (k < 1) return fail(CSC_E_ARG, "need k >= 1");
   if (need_k_le_n && k > n) return fail(CSC_E_ARG, "seeding needs k <= n");
-  if (static_cast<size_t>(k) * (64 * 4 + 4) > 60 * 1024) return fail(CSC_E_ARG, "k too large (<= 235)");
+  if (static_cast<size_t>(k) * (32 * 8 + 4) > 62 * 1024) return fail(CSC_E_ARG, "k must be <= 240");
   return CSC_OK;
+}
+
+// number of objective partials the assignment writes
+int64_t assign_partials(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d, int k) {
+  if (static_cast<int64_t>(k) * d <= kLdsCentroids) {
+    const RowShape rs = row_shape(F, f_dt, ldf, d);
+    return assign_grid(n, rs.vec ? rs.G : kScalarG);
+  }
+  return (n + kThreads / kScalarG - 1) / (kThreads / kScalarG);
 }
 
 }  // namespace
@@ -332,10 +582,34 @@ csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int6
                                 double* obj_part, hipStream_t s) {
   CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
   if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
-  const int kc = std::max(1, std::min(k, kLdsFloats / d));
-  const int64_t blocks = (n + kRowsPB - 1) / kRowsPB;
-  hipLaunchKernelGGL(k_assign, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, F,
-                     int(f_dt), ldf, n, d, C, k, kc, labels, best_d2, obj_part);
+  const RowShape rs = row_shape(F, f_dt, ldf, d);
+  if (static_cast<int64_t>(k) * d <= kLdsCentroids) {
+    const size_t lds = static_cast<size_t>(k) * d * sizeof(float);
+    if (rs.vec) {
+      const unsigned blocks = static_cast<unsigned>(assign_grid(n, rs.G));
+      if (f_dt == CSC_F32)
+        CSC_TRY((launch_assign_vec<float, 4>(rs.G, static_cast<const float*>(F), ldf, n, d, C, k,
+                                             labels, best_d2, obj_part, blocks, lds, s)));
+      else
+        CSC_TRY((launch_assign_vec<uint16_t, 8>(rs.G, static_cast<const uint16_t*>(F), ldf, n, d,
+                                                C, k, labels, best_d2, obj_part, blocks, lds, s)));
+    } else {
+      const unsigned blocks = static_cast<unsigned>(assign_grid(n, kScalarG));
+      if (f_dt == CSC_F32)
+        hipLaunchKernelGGL((k_assign<float, kScalarG, kScalarNV, false>), dim3(blocks), dim3(kThreads),
+                           lds, s, static_cast<const float*>(F), ldf, n, d, C, k, labels, best_d2,
+                           obj_part);
+      else
+        hipLaunchKernelGGL((k_assign<uint16_t, kScalarG, kScalarNV, false>), dim3(blocks),
+                           dim3(kThreads), lds, s, static_cast<const uint16_t*>(F), ldf, n, d, C, k,
+                           labels, best_d2, obj_part);
+    }
+  } else {
+    const int kc = std::max(1, std::min(k, 12288 / d));
+    const int64_t blocks = (n + kThreads / kScalarG - 1) / (kThreads / kScalarG);
+    hipLaunchKernelGGL(k_assign_chunked, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
+                       F, int(f_dt), ldf, n, d, C, k, kc, labels, best_d2, obj_part);
+  }
   CSC_HIP(hipGetLastError());
   return CSC_OK;
 }
@@ -347,15 +621,32 @@ csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int6
   const KmLayout L = km_layout(n, d, k);
   if (!work || work_bytes < L.total) return fail(CSC_E_ARG, "k-means workspace too small");
   char* base = static_cast<char*>(work);
-  float* part = reinterpret_cast<float*>(base + L.off_part);
-  int32_t* cpart = reinterpret_cast<int32_t*>(base + L.off_cpart);
-  const size_t lds = static_cast<size_t>(L.groups) * k * 64 * 4 + static_cast<size_t>(L.groups) * k * 4;
-  hipLaunchKernelGGL(k_update_part, dim3(static_cast<unsigned>(L.nblk_upd), (d + 63) / 64),
-                     dim3(64 * L.groups), lds, s, F, int(f_dt), ldf, n, d, labels, k, L.rpb,
-                     L.groups, part, cpart);
+  auto* sums = reinterpret_cast<unsigned long long*>(base + L.off_sums);
+  auto* cnt = reinterpret_cast<int32_t*>(base + L.off_cnt);
+  auto* mx = reinterpret_cast<uint32_t*>(base + L.off_max);
   const int64_t kd = static_cast<int64_t>(k) * d;
-  hipLaunchKernelGGL(k_update_final, dim3(static_cast<unsigned>((kd + 255) / 256)), dim3(256), 0,
-                     s, part, cpart, L.nblk_upd, k, d, C, counts);
+  hipLaunchKernelGGL(k_upd_clear, dim3(static_cast<unsigned>((std::max<int64_t>(kd, k) + 255) / 256)),
+                     dim3(256), 0, s, sums, kd, cnt, k, mx);
+  const unsigned mblocks = static_cast<unsigned>(std::min<int64_t>(2048, (n * d + 255) / 256));
+  if (f_dt == CSC_F32)
+    hipLaunchKernelGGL(k_maxabs<float>, dim3(mblocks), dim3(256), 0, s, static_cast<const float*>(F),
+                       ldf, n, d, mx);
+  else
+    hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(F), ldf, n, d, mx);
+  const int cw = k <= 112 ? 64 : 32;
+  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(1024, (n + 1023) / 1024));
+  const int64_t rpb = (n + nblk - 1) / nblk;
+  const size_t lds = static_cast<size_t>(k) * cw * 8 + static_cast<size_t>(k) * 4;
+  const dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>((d + cw - 1) / cw));
+  if (f_dt == CSC_F32)
+    hipLaunchKernelGGL(k_upd_acc<float>, grid, dim3(kThreads), lds, s, static_cast<const float*>(F),
+                       ldf, n, d, labels, k, rpb, cw, mx, sums, cnt);
+  else
+    hipLaunchKernelGGL(k_upd_acc<uint16_t>, grid, dim3(kThreads), lds, s,
+                       static_cast<const uint16_t*>(F), ldf, n, d, labels, k, rpb, cw, mx, sums, cnt);
+  hipLaunchKernelGGL(k_upd_final, dim3(static_cast<unsigned>((kd + 255) / 256)), dim3(256), 0, s,
+                     sums, cnt, mx, n, k, d, C, counts);
   CSC_HIP(hipGetLastError());
   return CSC_OK;
 }
@@ -370,13 +661,42 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   double* d2 = reinterpret_cast<double*>(base + L.off_d2);
   double* bsum = reinterpret_cast<double*>(base + L.off_bsum);
   int32_t* sel = reinterpret_cast<int32_t*>(base + L.off_sel);
-  hipLaunchKernelGGL(k_pp_first, dim3(1), dim3(256), 0, s, F, int(f_dt), ldf, n, d, u, C, idx, sel);
+  const RowShape rs = row_shape(F, f_dt, ldf, d);
+  const int G = rs.vec ? rs.G : kScalarG;
+  const int64_t rows_per_blk = static_cast<int64_t>(kThreads / G) * kPPIters;
+  const int64_t nblk = (n + rows_per_blk - 1) / rows_per_blk;
+  const bool f32 = f_dt == CSC_F32;
+  if (f32)
+    hipLaunchKernelGGL(k_pp_first<float>, dim3(1), dim3(256), 0, s, static_cast<const float*>(F), ldf,
+                       n, d, u, C, idx, sel);
+  else
+    hipLaunchKernelGGL(k_pp_first<uint16_t>, dim3(1), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(F), ldf, n, d, u, C, idx, sel);
   for (int j = 1; j < k; ++j) {
-    hipLaunchKernelGGL(k_pp_dist, dim3(static_cast<unsigned>(L.pp_blocks)), dim3(kThreads), 0, s,
-                       F, int(f_dt), ldf, n, d, C + static_cast<int64_t>(j - 1) * d, j == 1 ? 1 : 0,
-                       d2, bsum);
-    hipLaunchKernelGGL(k_pp_pick, dim3(1), dim3(256), 0, s, F, int(f_dt), ldf, n, d, d2, bsum,
-                       L.pp_blocks, u, j, C, idx, sel);
+    const float* Cj = C + static_cast<int64_t>(j - 1) * d;
+    const int first = j == 1 ? 1 : 0;
+    if (rs.vec) {
+      if (f32)
+        CSC_TRY((launch_ppdist_vec<float, 4>(G, static_cast<const float*>(F), ldf, n, d, Cj, first,
+                                             d2, bsum, s)));
+      else
+        CSC_TRY((launch_ppdist_vec<uint16_t, 8>(G, static_cast<const uint16_t*>(F), ldf, n, d, Cj,
+                                                first, d2, bsum, s)));
+    } else if (f32) {
+      hipLaunchKernelGGL((k_pp_dist<float, kScalarG, kScalarNV, false>), dim3(static_cast<unsigned>(nblk)),
+                         dim3(kThreads), 0, s, static_cast<const float*>(F), ldf, n, d, Cj, first, d2, bsum);
+    } else {
+      hipLaunchKernelGGL((k_pp_dist<uint16_t, kScalarG, kScalarNV, false>),
+                         dim3(static_cast<unsigned>(nblk)), dim3(kThreads), 0, s,
+                         static_cast<const uint16_t*>(F), ldf, n, d, Cj, first, d2, bsum);
+    }
+    if (f32)
+      hipLaunchKernelGGL(k_pp_pick<float>, dim3(1), dim3(1024), 0, s, static_cast<const float*>(F), ldf,
+                         n, d, d2, bsum, nblk, rows_per_blk, u, j, C, idx, sel);
+    else
+      hipLaunchKernelGGL(k_pp_pick<uint16_t>, dim3(1), dim3(1024), 0, s,
+                         static_cast<const uint16_t*>(F), ldf, n, d, d2, bsum, nblk, rows_per_blk, u,
+                         j, C, idx, sel);
   }
   CSC_HIP(hipGetLastError());
   return CSC_OK;
@@ -398,11 +718,12 @@ csc_status run_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
     CSC_TRY(launch_uniforms(u, k, seed, stream_id, s));
     CSC_TRY(launch_kmeans_seed(F, f_dt, ldf, n, d, k, u, C, nullptr, work, work_bytes, s));
   }
+  const int64_t nparts = assign_partials(F, f_dt, ldf, n, d, k);
   for (int it = 0; it <= iters; ++it) {
     CSC_TRY(launch_kmeans_assign(F, f_dt, ldf, n, d, C, k, labels, nullptr,
                                  objective ? obj : nullptr, s));
     if (objective)
-      hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(kThreads), 0, s, obj, L.assign_blocks, objv + it);
+      hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(kThreads), 0, s, obj, nparts, objv + it);
     if (it < iters)
       CSC_TRY(launch_kmeans_update(F, f_dt, ldf, n, d, labels, k, C, nullptr, work, work_bytes, s));
   }

@@ -18,13 +18,15 @@ def seq():
     return [g0] + [dyn.step(0.01, 0.005) for _ in range(4)]
 
 
+@pytest.mark.parametrize("keep", [0, 1])
 @pytest.mark.parametrize("p,d,tau", [(0.5, 32, 1e-12), (0.5, 64, None), (0.75, 64, None), (0.0, 16, None)])
-def test_dynamic_matches_oracle(csc, seq, p, d, tau):
-    say(f"dynamic parity p={p} d={d} tau={tau}")
+def test_dynamic_matches_oracle(csc, seq, p, d, tau, keep):
+    say(f"dynamic parity p={p} d={d} tau={tau} keep_iterates={keep}")
     k, m, seed = 4, 40, 53
     orc = dynamic.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10,
                              tau=tau, storage=np.float32)
-    gpu = csc.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10, tau=tau or 0.0)
+    gpu = csc.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10, tau=tau or 0.0,
+                         keep_iterates=keep)
     for t, g in enumerate(seq, start=1):
         G = csc.Graph.from_workload(g)
         lab, lam, ref, cnt = gpu.step(G)
