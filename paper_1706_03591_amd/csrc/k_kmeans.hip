@@ -1,15 +1,11 @@
 // k-means on the rows of the spectral features (Sec. 2.1, eq. SC_cost): assignment,
 // Lloyd update and k-means++ seeding.
 //
-// Rows are served by groups of G lanes.  When a row is a whole number of 16-byte chunks
-// (d * sizeof(elem) a multiple of 16 and G = d / VEC a power of two), lane l owns the VEC
-// contiguous columns l * VEC .. l * VEC + VEC - 1 and loads them with one vector load;
-// otherwise lane l owns columns l, l + 16, l + 32, ... (G = 16).
-//
-// Assignment: centroids are staged in LDS once per block and the block walks many rows.
-// Distances are ranked in FP32 in the direct form sum (f - mu)^2 (no cancellation) and the
-// two best candidates are re-scored in FP64, so the chosen label is the exact FP64 argmin
-// of the two, ties going to the lowest index.
+// Assignment: one lane per row.  Centroids are staged 32 at a time in LDS and read as
+// broadcasts while each lane streams its row through registers 16 columns at a time, so
+// the distances need no cross-lane reduction.  Distances are ranked in FP32 in the direct
+// form sum (f - mu)^2 (no cancellation) and the two best candidates are re-scored in FP64,
+// so the chosen label is the exact FP64 argmin of the two, ties going to the lowest index.
 //
 // Update: sums of the rows of each cluster in 64-bit fixed point (scale 2^S chosen from
 // max |F| and n so that no sum can overflow), accumulated with integer atomics in LDS and
@@ -17,8 +13,9 @@
 // the order of the atomics and the update is bit-reproducible; the quantisation step
 // 2^-S is far below FP32 resolution.
 //
-// k-means++: FP64 squared distances to the newest centre, block sums over contiguous row
-// ranges, and a one-block pick of the first row whose running sum exceeds u_j * total.
+// k-means++: FP64 squared distances to the newest centre (one lane per row), block sums over
+// contiguous row ranges, and a one-block pick of the first row whose running sum exceeds
+// u_j * total.
 #include <cmath>
 
 #include "csc_internal.h"
@@ -28,10 +25,6 @@ namespace csc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kScalarG = 16;
-constexpr int kScalarNV = 16;         // scalar path: d <= 256
-constexpr int kLdsCentroids = 15360;  // floats of centroids staged per block (60 KB)
-constexpr int kPPIters = 8;           // row iterations per k-means++ block
 
 template <typename TF>
 __device__ inline float to_f(TF v);
@@ -39,58 +32,6 @@ template <>
 __device__ inline float to_f<float>(float v) { return v; }
 template <>
 __device__ inline float to_f<uint16_t>(uint16_t v) { return bf16_to_f32(v); }
-
-// Load the NV values a lane owns in one row (zeros when invalid or past d).
-template <typename TF, int G, int NV, bool VECL>
-__device__ inline void load_row(const TF* F, int64_t row, int64_t ldf, int lane, int d, bool valid,
-                                float* f) {
-  if constexpr (VECL) {
-    static_assert(NV * sizeof(TF) == 16, "one 16-byte chunk per lane");
-    if (valid) {
-      const uint4 u = *reinterpret_cast<const uint4*>(F + row * ldf + lane * NV);
-      if constexpr (sizeof(TF) == 4) {
-        f[0] = __uint_as_float(u.x);
-        f[1] = __uint_as_float(u.y);
-        f[2] = __uint_as_float(u.z);
-        f[3] = __uint_as_float(u.w);
-      } else {
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          f[2 * i] = __uint_as_float(w[i] << 16);
-          f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) f[i] = 0.f;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int col = lane + i * G;
-      f[i] = (valid && col < d) ? to_f<TF>(F[row * ldf + col]) : 0.f;
-    }
-  }
-}
-
-template <int G, int NV, bool VECL>
-__device__ inline int col_of(int lane, int i) {
-  return VECL ? lane * NV + i : lane + i * G;
-}
-
-template <int G>
-__device__ inline float grp_sum(float v) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
-  return v;
-}
-template <int G>
-__device__ inline double grp_sum(double v) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
-  return v;
-}
 
 __device__ inline double block_sum(double v) {
   __shared__ double red[kThreads / 64];
@@ -107,132 +48,127 @@ __device__ inline double block_sum(double v) {
 
 // ---------------- assignment ----------------
 
-template <typename TF, int G, int NV, bool VECL>
-__global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, int64_t n, int d,
-                                                     const float* C, int k, int32_t* labels,
-                                                     float* best_d2, double* obj_part) {
-  extern __shared__ float s_c[];  // k * d
-  constexpr int RPI = kThreads / G;
-  for (int t = threadIdx.x; t < k * d; t += kThreads) s_c[t] = C[t];
-  __syncthreads();
-  const int lane = threadIdx.x % G;
-  double objsum = 0.0;
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * RPI; base < n;
-       base += static_cast<int64_t>(gridDim.x) * RPI) {
-    const int64_t row = base + threadIdx.x / G;
-    const bool valid = row < n;
-    float f[NV];
-    load_row<TF, G, NV, VECL>(F, row, ldf, lane, d, valid, f);
-    float b1 = INFINITY, b2 = INFINITY;
-    int i1 = 0, i2 = -1;
-    for (int c = 0; c < k; ++c) {
-      const float* cc = s_c + c * d;
-      float s = 0.f;
+constexpr int kKG = 32;   // centroids per staged group
+constexpr int kCH = 16;   // columns per streamed chunk
+constexpr int kRIT = 4;   // rows per thread per block
+
+// kCH consecutive values of a row from column c0 (zeros past d).  Vector loads when the
+// whole chunk is inside the row and rows are 16-byte aligned.
+template <typename TF, bool VEC>
+__device__ inline void load_chunk(const TF* rowp, int c0, int d, float* f) {
+  if (VEC && c0 + kCH <= d) {
+    const uint4* p = reinterpret_cast<const uint4*>(rowp + c0);
+    if constexpr (sizeof(TF) == 4) {
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const int col = col_of<G, NV, VECL>(lane, i);
-        if (VECL || col < d) {
-          const float t = f[i] - cc[col];
-          s = fmaf(t, t, s);
-        }
+      for (int q = 0; q < 4; ++q) {
+        const uint4 u = p[q];
+        f[4 * q] = __uint_as_float(u.x);
+        f[4 * q + 1] = __uint_as_float(u.y);
+        f[4 * q + 2] = __uint_as_float(u.z);
+        f[4 * q + 3] = __uint_as_float(u.w);
       }
-      s = grp_sum<G>(s);
-      if (s < b1) { b2 = b1; i2 = i1; b1 = s; i1 = c; }
-      else if (s < b2) { b2 = s; i2 = c; }
-    }
-    double e1 = 0.0, e2 = 0.0;
+    } else {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int col = col_of<G, NV, VECL>(lane, i);
-      if (VECL || col < d) {
-        const double t1 = static_cast<double>(f[i]) - static_cast<double>(s_c[i1 * d + col]);
-        e1 += t1 * t1;
-        if (i2 >= 0) {
-          const double t2 = static_cast<double>(f[i]) - static_cast<double>(s_c[i2 * d + col]);
-          e2 += t2 * t2;
+      for (int q = 0; q < 2; ++q) {
+        const uint4 u = p[q];
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          f[8 * q + 2 * i] = __uint_as_float(w[i] << 16);
+          f[8 * q + 2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
         }
       }
     }
-    e1 = grp_sum<G>(e1);
-    e2 = grp_sum<G>(e2);
-    int lab = i1;
-    double best = e1;
-    if (i2 >= 0 && (e2 < e1 || (e2 == e1 && i2 < i1))) { lab = i2; best = e2; }
-    if (valid && lane == 0) {
-      labels[row] = lab;
-      if (best_d2) best_d2[row] = static_cast<float>(best);
-      objsum += best;
-    }
-  }
-  if (obj_part) {
-    const double s = block_sum(objsum);
-    if (threadIdx.x == 0) obj_part[blockIdx.x] = s;
+  } else {
+#pragma unroll
+    for (int i = 0; i < kCH; ++i) f[i] = (c0 + i < d) ? to_f<TF>(rowp[c0 + i]) : 0.f;
   }
 }
 
-// Fallback when the centroids do not fit in LDS: one row group per row, centroids staged in
-// chunks for every block of rows.
-__global__ __launch_bounds__(kThreads) void k_assign_chunked(const void* F, int f_dt, int64_t ldf,
-                                                             int64_t n, int d, const float* C,
-                                                             int k, int kc, int32_t* labels,
-                                                             float* best_d2, double* obj_part) {
-  __shared__ float s_c[12288];
-  constexpr int G = kScalarG, NV = kScalarNV;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * (kThreads / G) + threadIdx.x / G;
-  const int lane = threadIdx.x % G;
-  const bool valid = row < n;
-  float f[NV];
-  if (f_dt == CSC_F32)
-    load_row<float, G, NV, false>(static_cast<const float*>(F), row, ldf, lane, d, valid, f);
-  else
-    load_row<uint16_t, G, NV, false>(static_cast<const uint16_t*>(F), row, ldf, lane, d, valid, f);
-  float b1 = INFINITY, b2 = INFINITY;
-  int i1 = 0, i2 = -1;
-  for (int c0 = 0; c0 < k; c0 += kc) {
-    const int cn = min(kc, k - c0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < cn * d; t += kThreads) s_c[t] = C[static_cast<int64_t>(c0) * d + t];
-    __syncthreads();
-    for (int c = 0; c < cn; ++c) {
-      float s = 0.f;
+// Each lane owns whole rows (kRIT of them per block pass).  Centroids are staged kKG at a
+// time in LDS (zero-padded to dp columns) and read as broadcasts; a row is streamed through
+// registers kCH columns at a time against the kKG staged centroids, so no cross-lane
+// reduction is needed.  Top-2 in FP32 (increasing centroid index, strict <), then FP64
+// re-score of the two.
+template <typename TF, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, int64_t n, int d,
+                                                     int dp, const float* C, int k,
+                                                     int32_t* labels, float* best_d2,
+                                                     double* obj_part) {
+  __shared__ float s_c[kKG * 256];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kRIT;
+  float b1[kRIT], b2[kRIT];
+  int i1[kRIT], i2[kRIT];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const int col = lane + i * G;
-        if (col < d) {
-          const float t = f[i] - s_c[c * d + col];
-          s = fmaf(t, t, s);
+  for (int q = 0; q < kRIT; ++q) { b1[q] = INFINITY; b2[q] = INFINITY; i1[q] = 0; i2[q] = -1; }
+  for (int g0 = 0; g0 < k; g0 += kKG) {
+    const int gn = min(kKG, k - g0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kKG * dp; t += kThreads) {
+      const int c = t / dp, col = t - c * dp;
+      s_c[t] = (c < gn && col < d) ? C[static_cast<int64_t>(g0 + c) * d + col] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int q = 0; q < kRIT; ++q) {
+      const int64_t row = base + q * kThreads + threadIdx.x;
+      const bool valid = row < n;
+      const TF* rowp = F + (valid ? row : 0) * ldf;
+      float part[kKG];
+#pragma unroll
+      for (int cc = 0; cc < kKG; ++cc) part[cc] = 0.f;
+      for (int c0 = 0; c0 < dp; c0 += kCH) {
+        float f[kCH];
+        if (valid) load_chunk<TF, VEC>(rowp, c0, d, f);
+        else {
+#pragma unroll
+          for (int i = 0; i < kCH; ++i) f[i] = 0.f;
+        }
+#pragma unroll
+        for (int cc = 0; cc < kKG; ++cc) {
+          const float* cp = s_c + cc * dp + c0;
+#pragma unroll
+          for (int i = 0; i < kCH; ++i) {
+            const float t = f[i] - cp[i];
+            part[cc] = fmaf(t, t, part[cc]);
+          }
         }
       }
-      s = grp_sum<G>(s);
-      const int ci = c0 + c;
-      if (s < b1) { b2 = b1; i2 = i1; b1 = s; i1 = ci; }
-      else if (s < b2) { b2 = s; i2 = ci; }
-    }
-  }
-  double e1 = 0.0, e2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int col = lane + i * G;
-    if (col < d) {
-      const double t1 = static_cast<double>(f[i]) - static_cast<double>(C[static_cast<int64_t>(i1) * d + col]);
-      e1 += t1 * t1;
-      if (i2 >= 0) {
-        const double t2 = static_cast<double>(f[i]) - static_cast<double>(C[static_cast<int64_t>(i2) * d + col]);
-        e2 += t2 * t2;
+      for (int cc = 0; cc < kKG; ++cc) {
+        if (cc < gn) {
+          const float s = part[cc];
+          if (s < b1[q]) { b2[q] = b1[q]; i2[q] = i1[q]; b1[q] = s; i1[q] = g0 + cc; }
+          else if (s < b2[q]) { b2[q] = s; i2[q] = g0 + cc; }
+        }
       }
     }
   }
-  e1 = grp_sum<G>(e1);
-  e2 = grp_sum<G>(e2);
-  int lab = i1;
-  double best = e1;
-  if (i2 >= 0 && (e2 < e1 || (e2 == e1 && i2 < i1))) { lab = i2; best = e2; }
-  if (valid && lane == 0) {
+  double objsum = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < kRIT; ++q) {
+    const int64_t row = base + q * kThreads + threadIdx.x;
+    if (row >= n) continue;
+    const TF* rowp = F + row * ldf;
+    const float* c1 = C + static_cast<int64_t>(i1[q]) * d;
+    const float* c2 = C + static_cast<int64_t>(i2[q] >= 0 ? i2[q] : i1[q]) * d;
+    double e1 = 0.0, e2 = 0.0;
+    for (int col = 0; col < d; ++col) {
+      const double fv = static_cast<double>(to_f<TF>(rowp[col]));
+      const double t1 = fv - static_cast<double>(c1[col]);
+      const double t2 = fv - static_cast<double>(c2[col]);
+      e1 += t1 * t1;
+      e2 += t2 * t2;
+    }
+    int lab = i1[q];
+    double best = e1;
+    if (i2[q] >= 0 && (e2 < e1 || (e2 == e1 && i2[q] < i1[q]))) { lab = i2[q]; best = e2; }
     labels[row] = lab;
     if (best_d2) best_d2[row] = static_cast<float>(best);
+    objsum += best;
   }
   if (obj_part) {
-    const double s = block_sum((valid && lane == 0) ? best : 0.0);
+    const double s = block_sum(objsum);
     if (threadIdx.x == 0) obj_part[blockIdx.x] = s;
   }
 }
@@ -254,7 +190,7 @@ __global__ void k_upd_clear(unsigned long long* sums, int64_t kd, int32_t* cnt, 
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t < kd) sums[t] = 0ull;
   if (t < k) cnt[t] = 0;
-  if (t == 0) maxabs[0] = 0u;
+  if (t == 0 && maxabs) maxabs[0] = 0u;
 }
 
 template <typename TF>
@@ -357,51 +293,39 @@ __global__ void k_pp_first(const TF* F, int64_t ldf, int64_t n, int d, const dou
   for (int t = threadIdx.x; t < d; t += blockDim.x) C[t] = to_f<TF>(F[i * ldf + t]);
 }
 
-// d2[i] = min(d2[i], ||f_i - Cj||^2) in FP64 (first round: the distance itself) for the
-// contiguous rows [b * RPI * kPPIters, ...) of block b; bsum[b] = their sum (fixed tree).
-template <typename TF, int G, int NV, bool VECL>
+// d2[i] = min(d2[i], ||f_i - Cj||^2) in FP64 (first round: the distance itself); one lane
+// per row, kRIT rows per thread, so block b covers the contiguous rows
+// [b * kThreads * kRIT, ...); bsum[b] = their sum (fixed reduction order).
+template <typename TF, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, int64_t n, int d,
-                                                      const float* Cj, int first, double* d2,
-                                                      double* bsum) {
-  constexpr int RPI = kThreads / G;
-  constexpr int R = RPI * kPPIters;
-  __shared__ double s_d[R];
-  const int lane = threadIdx.x % G;
-  float cj[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int col = col_of<G, NV, VECL>(lane, i);
-    cj[i] = (VECL || col < d) ? Cj[col] : 0.f;
-  }
-  const int64_t rbase = static_cast<int64_t>(blockIdx.x) * R;
-  for (int it = 0; it < kPPIters; ++it) {
-    const int loc = it * RPI + threadIdx.x / G;
-    const int64_t row = rbase + loc;
-    const bool valid = row < n;
-    float f[NV];
-    load_row<TF, G, NV, VECL>(F, row, ldf, lane, d, valid, f);
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const double t = static_cast<double>(f[i]) - static_cast<double>(cj[i]);
-      s += t * t;
-    }
-    s = grp_sum<G>(s);
-    if (lane == 0) {
-      double v = 0.0;
-      if (valid) {
-        v = first ? s : fmin(d2[row], s);
-        d2[row] = v;
-      }
-      s_d[loc] = v;
-    }
-  }
+                                                      int dp, const float* Cj, int first,
+                                                      double* d2, double* bsum) {
+  __shared__ float s_cj[256];
+  for (int t = threadIdx.x; t < dp; t += kThreads) s_cj[t] = t < d ? Cj[t] : 0.f;
   __syncthreads();
-  for (int w = R / 2; w > 0; w >>= 1) {
-    for (int t = threadIdx.x; t < w; t += kThreads) s_d[t] += s_d[t + w];
-    __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kRIT;
+  double local = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < kRIT; ++q) {
+    const int64_t row = base + q * kThreads + threadIdx.x;
+    if (row >= n) continue;
+    const TF* rowp = F + row * ldf;
+    double s = 0.0;
+    for (int c0 = 0; c0 < dp; c0 += kCH) {
+      float f[kCH];
+      load_chunk<TF, VEC>(rowp, c0, d, f);
+#pragma unroll
+      for (int i = 0; i < kCH; ++i) {
+        const double t = static_cast<double>(f[i]) - static_cast<double>(s_cj[c0 + i]);
+        s += t * t;
+      }
+    }
+    const double v = first ? s : fmin(d2[row], s);
+    d2[row] = v;
+    local += v;
   }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = s_d[0];
+  const double tot = block_sum(local);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
 // Pick centre j (1024 threads): chunk sums of the block sums, the chunk and block where the
@@ -462,71 +386,17 @@ __global__ void k_sum_into(const double* part, int64_t nb, double* out) {
 
 // ---------------- dispatch ----------------
 
-// Row-group shape for (d, element size, pointer, ld): vectorised when possible.
-struct RowShape {
-  bool vec;
-  int G;  // lanes per row
-};
-
-RowShape row_shape(const void* F, csc_dtype f_dt, int64_t ldf, int d) {
-  const int es = static_cast<int>(dtype_size(f_dt));
-  const int vecn = 16 / es;
-  const bool aligned = (reinterpret_cast<uintptr_t>(F) % 16 == 0) && ((ldf * es) % 16 == 0);
-  if (aligned && d % vecn == 0) {
-    const int G = d / vecn;
-    if (G >= 2 && G <= 64 && (G & (G - 1)) == 0) return RowShape{true, G};
-  }
-  return RowShape{false, kScalarG};
+// Vector row loads need 16-byte aligned rows.
+bool rows_aligned(const void* F, csc_dtype f_dt, int64_t ldf) {
+  const size_t es = dtype_size(f_dt);
+  return reinterpret_cast<uintptr_t>(F) % 16 == 0 && (static_cast<size_t>(ldf) * es) % 16 == 0;
 }
 
-template <typename TF, int NV>
-csc_status launch_assign_vec(int G, const TF* F, int64_t ldf, int64_t n, int d, const float* C,
-                             int k, int32_t* labels, float* best_d2, double* obj_part,
-                             unsigned blocks, size_t lds, hipStream_t s) {
-#define CSC_ASSIGN_CASE(GG)                                                                   \
-  case GG:                                                                                    \
-    hipLaunchKernelGGL((k_assign<TF, GG, NV, true>), dim3(blocks), dim3(kThreads), lds, s, F, \
-                       ldf, n, d, C, k, labels, best_d2, obj_part);                           \
-    break;
-  switch (G) {
-    CSC_ASSIGN_CASE(2)
-    CSC_ASSIGN_CASE(4)
-    CSC_ASSIGN_CASE(8)
-    CSC_ASSIGN_CASE(16)
-    CSC_ASSIGN_CASE(32)
-    CSC_ASSIGN_CASE(64)
-    default: return fail(CSC_E_ARG, "bad row group");
-  }
-#undef CSC_ASSIGN_CASE
-  return CSC_OK;
-}
+int padded_d(int d) { return (d + kCH - 1) / kCH * kCH; }
 
-template <typename TF, int NV>
-csc_status launch_ppdist_vec(int G, const TF* F, int64_t ldf, int64_t n, int d, const float* Cj,
-                             int first, double* d2, double* bsum, hipStream_t s) {
-  const int64_t R = static_cast<int64_t>(kThreads / G) * kPPIters;
-  const unsigned blocks = static_cast<unsigned>((n + R - 1) / R);
-#define CSC_PP_CASE(GG)                                                                          \
-  case GG:                                                                                       \
-    hipLaunchKernelGGL((k_pp_dist<TF, GG, NV, true>), dim3(blocks), dim3(kThreads), 0, s, F, ldf, \
-                       n, d, Cj, first, d2, bsum);                                               \
-    break;
-  switch (G) {
-    CSC_PP_CASE(2)
-    CSC_PP_CASE(4)
-    CSC_PP_CASE(8)
-    CSC_PP_CASE(16)
-    CSC_PP_CASE(32)
-    CSC_PP_CASE(64)
-    default: return fail(CSC_E_ARG, "bad row group");
-  }
-#undef CSC_PP_CASE
-  return CSC_OK;
-}
-
-int64_t assign_grid(int64_t n, int G) {
-  const int64_t rpi = kThreads / G;
-  return std::max<int64_t>(1, std::min<int64_t>(2048, (n + rpi - 1) / rpi));
+int64_t assign_blocks(int64_t n) {
+  const int64_t per = static_cast<int64_t>(kThreads) * kRIT;
+  return std::max<int64_t>(1, (n + per - 1) / per);
 }
 
 struct KmLayout {
@@ -535,18 +405,15 @@ struct KmLayout {
 
 KmLayout km_layout(int64_t n, int d, int k) {
   KmLayout L{};
-  // k-means++ blocks cover at least 32 rows (G = 64); the chunked assignment writes one
-  // objective partial per 16 rows
-  const int64_t pp_blocks = (n + 31) / 32;
-  const int64_t obj_parts = std::max<int64_t>(2048, (n + 15) / 16);
+  const int64_t blocks = assign_blocks(n);
   size_t off = 0;
   L.off_u = off; off += align_up(static_cast<size_t>(k) * 8);
   L.off_d2 = off; off += align_up(static_cast<size_t>(n) * 8);
-  L.off_bsum = off; off += align_up(static_cast<size_t>(pp_blocks) * 8);
+  L.off_bsum = off; off += align_up(static_cast<size_t>(blocks) * 8);
   L.off_sums = off; off += align_up(static_cast<size_t>(k) * d * 8);
   L.off_cnt = off; off += align_up(static_cast<size_t>(k) * 4);
   L.off_max = off; off += 256;
-  L.off_obj = off; off += align_up(static_cast<size_t>(obj_parts) * 8);
+  L.off_obj = off; off += align_up(static_cast<size_t>(blocks) * 8);
   L.off_objv = off; off += align_up(static_cast<size_t>(1024 + 1) * 8);
   L.off_sel = off; off += 256;
   L.total = off;
@@ -557,85 +424,35 @@ csc_status check_f(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                    bool need_k_le_n = false) {
   if (!F || n < 1 || d < 1 || ldf < d) return fail(CSC_E_ARG, "bad feature block");
   if (f_dt != CSC_F32 && f_dt != CSC_BF16) return fail(CSC_E_DTYPE, "features must be F32 or BF16");
-  if (d > kScalarG * kScalarNV) return fail(CSC_E_ARG, "d must be <= 256");
+  if (d > 256) return fail(CSC_E_ARG, "d must be <= 256");
   if (k < 1) return fail(CSC_E_ARG, "need k >= 1");
   if (need_k_le_n && k > n) return fail(CSC_E_ARG, "seeding needs k <= n");
   if (static_cast<size_t>(k) * (32 * 8 + 4) > 62 * 1024) return fail(CSC_E_ARG, "k must be <= 240");
   return CSC_OK;
 }
 
-// number of objective partials the assignment writes
-int64_t assign_partials(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d, int k) {
-  if (static_cast<int64_t>(k) * d <= kLdsCentroids) {
-    const RowShape rs = row_shape(F, f_dt, ldf, d);
-    return assign_grid(n, rs.vec ? rs.G : kScalarG);
-  }
-  return (n + kThreads / kScalarG - 1) / (kThreads / kScalarG);
-}
-
-}  // namespace
-
-size_t kmeans_workspace(int64_t n, int d, int k) { return km_layout(n, d, k).total; }
-
-csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
-                                const float* C, int k, int32_t* labels, float* best_d2,
-                                double* obj_part, hipStream_t s) {
-  CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
-  if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
-  const RowShape rs = row_shape(F, f_dt, ldf, d);
-  if (static_cast<int64_t>(k) * d <= kLdsCentroids) {
-    const size_t lds = static_cast<size_t>(k) * d * sizeof(float);
-    if (rs.vec) {
-      const unsigned blocks = static_cast<unsigned>(assign_grid(n, rs.G));
-      if (f_dt == CSC_F32)
-        CSC_TRY((launch_assign_vec<float, 4>(rs.G, static_cast<const float*>(F), ldf, n, d, C, k,
-                                             labels, best_d2, obj_part, blocks, lds, s)));
-      else
-        CSC_TRY((launch_assign_vec<uint16_t, 8>(rs.G, static_cast<const uint16_t*>(F), ldf, n, d,
-                                                C, k, labels, best_d2, obj_part, blocks, lds, s)));
-    } else {
-      const unsigned blocks = static_cast<unsigned>(assign_grid(n, kScalarG));
-      if (f_dt == CSC_F32)
-        hipLaunchKernelGGL((k_assign<float, kScalarG, kScalarNV, false>), dim3(blocks), dim3(kThreads),
-                           lds, s, static_cast<const float*>(F), ldf, n, d, C, k, labels, best_d2,
-                           obj_part);
-      else
-        hipLaunchKernelGGL((k_assign<uint16_t, kScalarG, kScalarNV, false>), dim3(blocks),
-                           dim3(kThreads), lds, s, static_cast<const uint16_t*>(F), ldf, n, d, C, k,
-                           labels, best_d2, obj_part);
-    }
-  } else {
-    const int kc = std::max(1, std::min(k, 12288 / d));
-    const int64_t blocks = (n + kThreads / kScalarG - 1) / (kThreads / kScalarG);
-    hipLaunchKernelGGL(k_assign_chunked, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
-                       F, int(f_dt), ldf, n, d, C, k, kc, labels, best_d2, obj_part);
-  }
-  CSC_HIP(hipGetLastError());
-  return CSC_OK;
-}
-
-csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
-                                const int32_t* labels, int k, float* C, int32_t* counts,
-                                void* work, size_t work_bytes, hipStream_t s) {
-  CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
+csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                       const int32_t* labels, int k, float* C, int32_t* counts, void* work,
+                       bool max_ready, hipStream_t s) {
   const KmLayout L = km_layout(n, d, k);
-  if (!work || work_bytes < L.total) return fail(CSC_E_ARG, "k-means workspace too small");
   char* base = static_cast<char*>(work);
   auto* sums = reinterpret_cast<unsigned long long*>(base + L.off_sums);
   auto* cnt = reinterpret_cast<int32_t*>(base + L.off_cnt);
   auto* mx = reinterpret_cast<uint32_t*>(base + L.off_max);
   const int64_t kd = static_cast<int64_t>(k) * d;
   hipLaunchKernelGGL(k_upd_clear, dim3(static_cast<unsigned>((std::max<int64_t>(kd, k) + 255) / 256)),
-                     dim3(256), 0, s, sums, kd, cnt, k, mx);
-  const unsigned mblocks = static_cast<unsigned>(std::min<int64_t>(2048, (n * d + 255) / 256));
-  if (f_dt == CSC_F32)
-    hipLaunchKernelGGL(k_maxabs<float>, dim3(mblocks), dim3(256), 0, s, static_cast<const float*>(F),
-                       ldf, n, d, mx);
-  else
-    hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
-                       static_cast<const uint16_t*>(F), ldf, n, d, mx);
+                     dim3(256), 0, s, sums, kd, cnt, k, max_ready ? nullptr : mx);
+  if (!max_ready) {
+    const unsigned mblocks = static_cast<unsigned>(std::min<int64_t>(2048, (n * d + 255) / 256));
+    if (f_dt == CSC_F32)
+      hipLaunchKernelGGL(k_maxabs<float>, dim3(mblocks), dim3(256), 0, s, static_cast<const float*>(F),
+                         ldf, n, d, mx);
+    else
+      hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(F), ldf, n, d, mx);
+  }
   const int cw = k <= 112 ? 64 : 32;
-  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(1024, (n + 1023) / 1024));
+  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(2048, (n + 511) / 512));
   const int64_t rpb = (n + nblk - 1) / nblk;
   const size_t lds = static_cast<size_t>(k) * cw * 8 + static_cast<size_t>(k) * 4;
   const dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>((d + cw - 1) / cw));
@@ -651,6 +468,40 @@ csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int6
   return CSC_OK;
 }
 
+}  // namespace
+
+size_t kmeans_workspace(int64_t n, int d, int k) { return km_layout(n, d, k).total; }
+
+csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                                const float* C, int k, int32_t* labels, float* best_d2,
+                                double* obj_part, hipStream_t s) {
+  CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
+  if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
+  const bool vec = rows_aligned(F, f_dt, ldf);
+  const unsigned blocks = static_cast<unsigned>(assign_blocks(n));
+  const int dp = padded_d(d);
+#define CSC_ASSIGN(TF, V)                                                                         \
+  hipLaunchKernelGGL((k_assign<TF, V>), dim3(blocks), dim3(kThreads), 0, s,                       \
+                     static_cast<const TF*>(F), ldf, n, d, dp, C, k, labels, best_d2, obj_part)
+  if (f_dt == CSC_F32) {
+    if (vec) CSC_ASSIGN(float, true); else CSC_ASSIGN(float, false);
+  } else {
+    if (vec) CSC_ASSIGN(uint16_t, true); else CSC_ASSIGN(uint16_t, false);
+  }
+#undef CSC_ASSIGN
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                                const int32_t* labels, int k, float* C, int32_t* counts,
+                                void* work, size_t work_bytes, hipStream_t s) {
+  CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
+  const KmLayout L = km_layout(n, d, k);
+  if (!work || work_bytes < L.total) return fail(CSC_E_ARG, "k-means workspace too small");
+  return update_impl(F, f_dt, ldf, n, d, labels, k, C, counts, work, false, s);
+}
+
 csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d, int k,
                               const double* u, float* C, int32_t* idx, void* work,
                               size_t work_bytes, hipStream_t s) {
@@ -661,10 +512,10 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   double* d2 = reinterpret_cast<double*>(base + L.off_d2);
   double* bsum = reinterpret_cast<double*>(base + L.off_bsum);
   int32_t* sel = reinterpret_cast<int32_t*>(base + L.off_sel);
-  const RowShape rs = row_shape(F, f_dt, ldf, d);
-  const int G = rs.vec ? rs.G : kScalarG;
-  const int64_t rows_per_blk = static_cast<int64_t>(kThreads / G) * kPPIters;
-  const int64_t nblk = (n + rows_per_blk - 1) / rows_per_blk;
+  const bool vec = rows_aligned(F, f_dt, ldf);
+  const int64_t rows_per_blk = static_cast<int64_t>(kThreads) * kRIT;
+  const int64_t nblk = assign_blocks(n);
+  const int dp = padded_d(d);
   const bool f32 = f_dt == CSC_F32;
   if (f32)
     hipLaunchKernelGGL(k_pp_first<float>, dim3(1), dim3(256), 0, s, static_cast<const float*>(F), ldf,
@@ -672,32 +523,24 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   else
     hipLaunchKernelGGL(k_pp_first<uint16_t>, dim3(1), dim3(256), 0, s,
                        static_cast<const uint16_t*>(F), ldf, n, d, u, C, idx, sel);
+#define CSC_PPD(TF, V)                                                                             \
+  hipLaunchKernelGGL((k_pp_dist<TF, V>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), 0, s, \
+                     static_cast<const TF*>(F), ldf, n, d, dp, Cj, first, d2, bsum)
   for (int j = 1; j < k; ++j) {
     const float* Cj = C + static_cast<int64_t>(j - 1) * d;
     const int first = j == 1 ? 1 : 0;
-    if (rs.vec) {
-      if (f32)
-        CSC_TRY((launch_ppdist_vec<float, 4>(G, static_cast<const float*>(F), ldf, n, d, Cj, first,
-                                             d2, bsum, s)));
-      else
-        CSC_TRY((launch_ppdist_vec<uint16_t, 8>(G, static_cast<const uint16_t*>(F), ldf, n, d, Cj,
-                                                first, d2, bsum, s)));
-    } else if (f32) {
-      hipLaunchKernelGGL((k_pp_dist<float, kScalarG, kScalarNV, false>), dim3(static_cast<unsigned>(nblk)),
-                         dim3(kThreads), 0, s, static_cast<const float*>(F), ldf, n, d, Cj, first, d2, bsum);
-    } else {
-      hipLaunchKernelGGL((k_pp_dist<uint16_t, kScalarG, kScalarNV, false>),
-                         dim3(static_cast<unsigned>(nblk)), dim3(kThreads), 0, s,
-                         static_cast<const uint16_t*>(F), ldf, n, d, Cj, first, d2, bsum);
-    }
-    if (f32)
+    if (f32) {
+      if (vec) CSC_PPD(float, true); else CSC_PPD(float, false);
       hipLaunchKernelGGL(k_pp_pick<float>, dim3(1), dim3(1024), 0, s, static_cast<const float*>(F), ldf,
                          n, d, d2, bsum, nblk, rows_per_blk, u, j, C, idx, sel);
-    else
+    } else {
+      if (vec) CSC_PPD(uint16_t, true); else CSC_PPD(uint16_t, false);
       hipLaunchKernelGGL(k_pp_pick<uint16_t>, dim3(1), dim3(1024), 0, s,
                          static_cast<const uint16_t*>(F), ldf, n, d, d2, bsum, nblk, rows_per_blk, u,
                          j, C, idx, sel);
+    }
   }
+#undef CSC_PPD
   CSC_HIP(hipGetLastError());
   return CSC_OK;
 }
@@ -714,18 +557,30 @@ csc_status run_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
   double* u = reinterpret_cast<double*>(base + L.off_u);
   double* obj = reinterpret_cast<double*>(base + L.off_obj);
   double* objv = reinterpret_cast<double*>(base + L.off_objv);
+  auto* mx = reinterpret_cast<uint32_t*>(base + L.off_max);
   if (init == 0) {
     CSC_TRY(launch_uniforms(u, k, seed, stream_id, s));
     CSC_TRY(launch_kmeans_seed(F, f_dt, ldf, n, d, k, u, C, nullptr, work, work_bytes, s));
   }
-  const int64_t nparts = assign_partials(F, f_dt, ldf, n, d, k);
+  // max |F| once: the features do not change during the Lloyd rounds
+  hipLaunchKernelGGL(k_upd_clear, dim3(1), dim3(256), 0, s, static_cast<unsigned long long*>(nullptr),
+                     int64_t(0), static_cast<int32_t*>(nullptr), 0, mx);
+  {
+    const unsigned mblocks = static_cast<unsigned>(std::min<int64_t>(2048, (n * d + 255) / 256));
+    if (f_dt == CSC_F32)
+      hipLaunchKernelGGL(k_maxabs<float>, dim3(mblocks), dim3(256), 0, s, static_cast<const float*>(F),
+                         ldf, n, d, mx);
+    else
+      hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(F), ldf, n, d, mx);
+  }
+  const int64_t nparts = assign_blocks(n);
   for (int it = 0; it <= iters; ++it) {
     CSC_TRY(launch_kmeans_assign(F, f_dt, ldf, n, d, C, k, labels, nullptr,
                                  objective ? obj : nullptr, s));
     if (objective)
       hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(kThreads), 0, s, obj, nparts, objv + it);
-    if (it < iters)
-      CSC_TRY(launch_kmeans_update(F, f_dt, ldf, n, d, labels, k, C, nullptr, work, work_bytes, s));
+    if (it < iters) CSC_TRY(update_impl(F, f_dt, ldf, n, d, labels, k, C, nullptr, work, true, s));
   }
   if (objective) {
     CSC_HIP(hipMemcpyAsync(objective, objv, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost, s));
