@@ -6,8 +6,8 @@ moves 0.5% of the nodes; d = 128 signals, Chebyshev degree m = 120, reuse p = 0.
 is one dynamic snapshot (Algorithm 1 steps 4-8: operator build, q d = 64 fresh signals,
 filter, eigencount, refinement when needed, k-means with 20 Lloyd rounds), with every
 snapshot's CSR already resident in HBM.  Two storage forms run on the same snapshots:
-FP32 everywhere, and BF16 storage of the signals, features and operator values with FP32
-iterates and accumulation.
+FP32 everywhere, and BF16 storage of the signals, features, operator values and recurrence
+iterates with FP32 arithmetic and accumulation (a third form, bf16io, keeps FP32 iterates).
 
 Printed: one JSON line.  `value` is the whole-job rate of the Chebyshev step kernels'
 algorithmic bytes (GB/s over the timed wall clock) of the headline form; `roofline` gives
@@ -45,11 +45,12 @@ def parse():
     ap.add_argument("--m", type=int, default=120)
     ap.add_argument("--p", type=float, default=0.5)
     ap.add_argument("--headline", choices=["bf16", "fp32"], default="bf16")
-    ap.add_argument("--bf16-iterates", action="store_true",
-                    help="store the recurrence iterates in BF16 too (larger error)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--forms", default="fp32,bf16",
+                    help="fp32: all FP32; bf16: BF16 signals, features, operator values and "
+                         "recurrence iterates with FP32 arithmetic and accumulation; bf16io: BF16 "
+                         "signals, features and values with FP32 iterates")
     return ap.parse_args()
 
 
@@ -118,10 +119,11 @@ def main():
 
     forms = {}
     digest = kernel_digest()
+    final_labels = {}
     for form in args.forms.split(","):
-        bf = form == "bf16"
+        bf = form in ("bf16", "bf16io")
         feat = torch.bfloat16 if bf else torch.float32
-        iters = torch.bfloat16 if (bf and args.bf16_iterates) else torch.float32
+        iters = torch.bfloat16 if form == "bf16" else torch.float32
         vals = torch.bfloat16 if bf else torch.float32
         rp, ci, ww = resident[0]
         G = csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=True, nnz_capacity=cap)
@@ -146,6 +148,7 @@ def main():
             lams.append(lam)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        final_labels[form] = labels.cpu().numpy()
         kms, launches, kbytes = csc.timing_read()
         csc.timing_enable(False)
         log(f"[bench] {form}: {wall / args.steps * 1e3:.2f} ms/snapshot, step kernels "
@@ -197,11 +200,11 @@ def main():
                    seconds=t_cpu)
         ref_rows = ref[rows]
         for form, rec in forms.items():
-            bf = form == "bf16"
+            bf = form in ("bf16", "bf16io")
             Xt = torch.from_numpy(X).to(dev)
             if bf:
                 Xt = Xt.to(torch.bfloat16)
-            iters = torch.bfloat16 if (bf and args.bf16_iterates) else torch.float32
+            iters = torch.bfloat16 if form == "bf16" else torch.float32
             G = rec["G"]
             G.update_device(*resident[-1], validate=False)
             Y = csc.cheb_filter(G, a, Xt, out_dtype=Xt.dtype, iter_dtype=iters).float().cpu().numpy()
@@ -259,6 +262,17 @@ def main():
     }
     if "fp32" in forms and "bf16" in forms:
         out["bf16_speedup_per_snapshot"] = round(forms["fp32"]["ms_per_snapshot"] / forms["bf16"]["ms_per_snapshot"], 4)
+    if "fp32" in final_labels:
+        # agreement of the last snapshot's partition with the FP32 form's, up to relabelling
+        ref = final_labels["fp32"]
+        agree = {}
+        for f, lab in final_labels.items():
+            if f == "fp32":
+                continue
+            cont = np.zeros((args.k, args.k), dtype=np.int64)
+            np.add.at(cont, (ref, lab), 1)
+            agree[f] = round(float(cont.max(axis=1).sum()) / len(ref), 5)
+        out["label_agreement_vs_fp32_last_snapshot"] = agree
     print(json.dumps(out), flush=True)
 
 

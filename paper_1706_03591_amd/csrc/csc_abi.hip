@@ -212,6 +212,10 @@ csc_status csc_graph_arrays(csc_graph h, const int32_t** rowptr, const int32_t**
                             void** vals, csc_dtype* val_dt, const double** dinv,
                             const int32_t** mirror) {
   if (!h) return fail(CSC_E_ARG, "null graph");
+  if (mirror) {
+    CSC_TRY(graph_ensure_mirror(&h->g, nullptr));
+    CSC_HIP(hipStreamSynchronize(nullptr));
+  }
   if (rowptr) *rowptr = h->g.rowptr;
   if (colidx) *colidx = h->g.colidx;
   if (vals) *vals = h->g.vals;
@@ -446,6 +450,7 @@ csc_status csc_cheb_filter_backward(csc_graph h, double lmax, int m, const doubl
                                     int ckpt_every, void* work, size_t work_bytes,
                                     void* stream) {
   if (!h || !a || !X || !G) return fail(CSC_E_ARG, "null argument");
+  CSC_TRY(graph_ensure_mirror(&h->g, as_stream(stream)));
   return run_backward(&h->g, lmax, m, a, X, ldx, G, ldg, w, dX, lddx, da, dA, ckpt_every, work,
                       work_bytes, as_stream(stream));
 }

@@ -75,10 +75,12 @@ struct Graph {
   int32_t* flags = nullptr;   // validation / counters (device, 4 ints)
   int variant_f32 = -1;       // step-kernel shape chosen by the autotuner (-1 = default)
   int variant_bf16 = -1;
+  bool mirror_valid = false;
 };
 
 csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
                        const double* w, int validate, hipStream_t s);
+csc_status graph_ensure_mirror(Graph* g, hipStream_t s);
 
 // ------------------------------------------------------------------------------------
 // fused Chebyshev recurrence

@@ -159,9 +159,19 @@ csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32
   else
     hipLaunchKernelGGL(k_values<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, colidx,
                        w, g->dinv, n, g->colidx, static_cast<uint16_t*>(g->vals));
-  hipLaunchKernelGGL(k_mirror, dim3(blocks_for(n)), dim3(256), 0, s, g->rowptr, g->colidx, n,
+  g->mirror_valid = false;
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+// The mirror index is needed only by the adjoint and by csc_graph_arrays; it is built on
+// first use after each (re)build.
+csc_status graph_ensure_mirror(Graph* g, hipStream_t s) {
+  if (g->mirror_valid) return CSC_OK;
+  hipLaunchKernelGGL(k_mirror, dim3(blocks_for(g->n)), dim3(256), 0, s, g->rowptr, g->colidx, g->n,
                      g->mirror);
   CSC_HIP(hipGetLastError());
+  g->mirror_valid = true;
   return CSC_OK;
 }
 

@@ -85,38 +85,32 @@ __device__ inline void load_chunk(const TF* rowp, int c0, int d, float* f) {
   }
 }
 
-// Each lane owns whole rows (kRIT of them per block pass).  Centroids are staged kKG at a
-// time in LDS (zero-padded to dp columns) and read as broadcasts; a row is streamed through
-// registers kCH columns at a time against the kKG staged centroids, so no cross-lane
-// reduction is needed.  Top-2 in FP32 (increasing centroid index, strict <), then FP64
+// Each lane owns whole rows (kRIT of them per block pass).  The centroids come from a
+// zero-padded copy Cp (kp x dp, kp a multiple of kKG): their addresses are uniform across
+// the wave, so they are fetched with scalar loads and used as scalar operands of the FMAs
+// while each lane streams its row through registers kCH columns at a time.  No LDS and no
+// cross-lane reduction.  Top-2 in FP32 (increasing centroid index, strict <), then FP64
 // re-score of the two.
 template <typename TF, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, int64_t n, int d,
-                                                     int dp, const float* C, int k,
+                                                     int dp, const float* __restrict__ Cp, int k,
                                                      int32_t* labels, float* best_d2,
                                                      double* obj_part) {
-  __shared__ float s_c[kKG * 256];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kRIT;
-  float b1[kRIT], b2[kRIT];
-  int i1[kRIT], i2[kRIT];
-#pragma unroll
-  for (int q = 0; q < kRIT; ++q) { b1[q] = INFINITY; b2[q] = INFINITY; i1[q] = 0; i2[q] = -1; }
-  for (int g0 = 0; g0 < k; g0 += kKG) {
-    const int gn = min(kKG, k - g0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < kKG * dp; t += kThreads) {
-      const int c = t / dp, col = t - c * dp;
-      s_c[t] = (c < gn && col < d) ? C[static_cast<int64_t>(g0 + c) * d + col] : 0.f;
-    }
-    __syncthreads();
+  double objsum = 0.0;
 #pragma unroll 1
-    for (int q = 0; q < kRIT; ++q) {
-      const int64_t row = base + q * kThreads + threadIdx.x;
-      const bool valid = row < n;
-      const TF* rowp = F + (valid ? row : 0) * ldf;
+  for (int q = 0; q < kRIT; ++q) {
+    const int64_t row = base + q * kThreads + threadIdx.x;
+    const bool valid = row < n;
+    const TF* rowp = F + (valid ? row : 0) * ldf;
+    float b1 = INFINITY, b2 = INFINITY;
+    int i1 = 0, i2 = -1;
+#pragma unroll 1
+    for (int g0 = 0; g0 < k; g0 += kKG) {
       float part[kKG];
 #pragma unroll
       for (int cc = 0; cc < kKG; ++cc) part[cc] = 0.f;
+#pragma unroll 1
       for (int c0 = 0; c0 < dp; c0 += kCH) {
         float f[kCH];
         if (valid) load_chunk<TF, VEC>(rowp, c0, d, f);
@@ -126,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
         }
 #pragma unroll
         for (int cc = 0; cc < kKG; ++cc) {
-          const float* cp = s_c + cc * dp + c0;
+          const float* cp = Cp + static_cast<int64_t>(g0 + cc) * dp + c0;
 #pragma unroll
           for (int i = 0; i < kCH; ++i) {
             const float t = f[i] - cp[i];
@@ -134,24 +128,19 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
           }
         }
       }
+      const int gn = min(kKG, k - g0);
 #pragma unroll
       for (int cc = 0; cc < kKG; ++cc) {
         if (cc < gn) {
-          const float s = part[cc];
-          if (s < b1[q]) { b2[q] = b1[q]; i2[q] = i1[q]; b1[q] = s; i1[q] = g0 + cc; }
-          else if (s < b2[q]) { b2[q] = s; i2[q] = g0 + cc; }
+          const float sc = part[cc];
+          if (sc < b1) { b2 = b1; i2 = i1; b1 = sc; i1 = g0 + cc; }
+          else if (sc < b2) { b2 = sc; i2 = g0 + cc; }
         }
       }
     }
-  }
-  double objsum = 0.0;
-#pragma unroll 1
-  for (int q = 0; q < kRIT; ++q) {
-    const int64_t row = base + q * kThreads + threadIdx.x;
-    if (row >= n) continue;
-    const TF* rowp = F + row * ldf;
-    const float* c1 = C + static_cast<int64_t>(i1[q]) * d;
-    const float* c2 = C + static_cast<int64_t>(i2[q] >= 0 ? i2[q] : i1[q]) * d;
+    if (!valid) continue;
+    const float* c1 = Cp + static_cast<int64_t>(i1) * dp;
+    const float* c2 = Cp + static_cast<int64_t>(i2 >= 0 ? i2 : i1) * dp;
     double e1 = 0.0, e2 = 0.0;
     for (int col = 0; col < d; ++col) {
       const double fv = static_cast<double>(to_f<TF>(rowp[col]));
@@ -160,9 +149,9 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
       e1 += t1 * t1;
       e2 += t2 * t2;
     }
-    int lab = i1[q];
+    int lab = i1;
     double best = e1;
-    if (i2[q] >= 0 && (e2 < e1 || (e2 == e1 && i2[q] < i1[q]))) { lab = i2[q]; best = e2; }
+    if (i2 >= 0 && (e2 < e1 || (e2 == e1 && i2 < i1))) { lab = i2; best = e2; }
     labels[row] = lab;
     if (best_d2) best_d2[row] = static_cast<float>(best);
     objsum += best;
@@ -171,6 +160,14 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
     const double s = block_sum(objsum);
     if (threadIdx.x == 0) obj_part[blockIdx.x] = s;
   }
+}
+
+// Cp[c][col] = C[c][col] for c < k and col < d, zero elsewhere (kp x dp).
+__global__ void k_pad_centroids(const float* C, int k, int d, int kp, int dp, float* Cp) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kp * dp) return;
+  const int c = t / dp, col = t - c * dp;
+  Cp[t] = (c < k && col < d) ? C[static_cast<int64_t>(c) * d + col] : 0.f;
 }
 
 // ---------------- Lloyd update in fixed point ----------------
@@ -328,53 +325,80 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// Pick centre j (1024 threads): chunk sums of the block sums, the chunk and block where the
-// running sum passes u_j * total, then the row inside that block (running sum in row order).
+// Inclusive prefix sums of v[0..1023] in LDS (Hillis-Steele, fixed order); 1024 threads.
+__device__ inline void scan1024(double* v) {
+  for (int off = 1; off < 1024; off <<= 1) {
+    const double add = threadIdx.x >= static_cast<unsigned>(off) ? v[threadIdx.x - off] : 0.0;
+    __syncthreads();
+    v[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// Pick centre j (1024 threads): prefix sums over chunks of block sums, the chunk and block
+// where the running sum passes u_j * total, then a prefix scan of the rows of that block.
+// Running sums are non-decreasing, so "first index above the threshold" is found by the one
+// thread whose prefix crosses it.
 template <typename TF>
 __global__ __launch_bounds__(1024) void k_pp_pick(const TF* F, int64_t ldf, int64_t n, int d,
                                                   const double* d2, const double* bsum,
                                                   int64_t nblk, int64_t rows_per_blk,
                                                   const double* u, int j, float* C, int32_t* idx,
                                                   int32_t* sel) {
-  __shared__ double s_chunk[1024];
-  __shared__ int64_t s_pick;
+  __shared__ double s_v[1024];
+  __shared__ int64_t s_at;
+  __shared__ double s_base;
+  const int t = threadIdx.x;
   const int64_t chunk = (nblk + 1023) / 1024;
   {
-    double s = 0.0;
-    const int64_t b0 = static_cast<int64_t>(threadIdx.x) * chunk;
-    for (int64_t b = b0; b < min(b0 + chunk, nblk); ++b) s += bsum[b];
-    s_chunk[threadIdx.x] = s;
+    double sum = 0.0;
+    const int64_t b0 = static_cast<int64_t>(t) * chunk;
+    for (int64_t b = b0; b < min(b0 + chunk, nblk); ++b) sum += bsum[b];
+    s_v[t] = sum;
+  }
+  if (t == 0) s_at = -1;
+  __syncthreads();
+  scan1024(s_v);
+  const double total = s_v[1023];
+  const double thr = u[j] * total;
+  if (total > 0.0) {
+    const double prev = t > 0 ? s_v[t - 1] : 0.0;
+    if (s_v[t] > thr && prev <= thr) { s_at = t; s_base = prev; }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double total = 0.0;
-    for (int i = 0; i < 1024; ++i) total += s_chunk[i];
-    int64_t pick = sel[0];  // all distances zero: repeat the previous centre
-    if (total > 0.0) {
-      const double thr = u[j] * total;
-      double run = 0.0;
-      int c = 0;
-      while (c < 1023 && run + s_chunk[c] <= thr) run += s_chunk[c++];
+  int64_t pick = sel[0];  // all distances zero: repeat the previous centre
+  if (total > 0.0) {
+    const int c = s_at >= 0 ? static_cast<int>(s_at) : 1023;
+    __syncthreads();
+    if (t == 0) {
+      double run = s_at >= 0 ? s_base : (c > 0 ? s_v[c - 1] : 0.0);
       int64_t b = static_cast<int64_t>(c) * chunk;
       const int64_t bend = min(b + chunk, nblk);
-      while (b < bend - 1 && run + bsum[b] <= thr) run += bsum[b++];
       if (b >= nblk) b = nblk - 1;
-      int64_t r = b * rows_per_blk;
-      const int64_t rend = min(r + rows_per_blk, n);
-      pick = rend - 1;
-      for (; r < rend; ++r) {
-        run += d2[r];
-        if (run > thr) { pick = r; break; }
-      }
+      while (b < bend - 1 && run + bsum[b] <= thr) run += bsum[b++];
+      s_at = b;
+      s_base = run;
     }
-    s_pick = pick;
+    __syncthreads();
+    const int64_t b = s_at;
+    const double base = s_base;
+    const int64_t r = b * rows_per_blk + t;
+    __syncthreads();
+    s_v[t] = (t < rows_per_blk && r < n) ? d2[r] : 0.0;
+    if (t == 0) s_at = -1;
+    __syncthreads();
+    scan1024(s_v);
+    const double prev = t > 0 ? s_v[t - 1] : 0.0;
+    if (t < rows_per_blk && r < n && base + s_v[t] > thr && base + prev <= thr) s_at = r;
+    __syncthreads();
+    pick = s_at >= 0 ? s_at : min(b * rows_per_blk + rows_per_blk, n) - 1;
+  }
+  if (t == 0) {
     sel[0] = static_cast<int32_t>(pick);
     if (idx) idx[j] = static_cast<int32_t>(pick);
   }
-  __syncthreads();
-  const int64_t pick = s_pick;
-  for (int t = threadIdx.x; t < d; t += blockDim.x)
-    C[static_cast<int64_t>(j) * d + t] = to_f<TF>(F[pick * ldf + t]);
+  for (int q = t; q < d; q += blockDim.x)
+    C[static_cast<int64_t>(j) * d + q] = to_f<TF>(F[pick * ldf + q]);
 }
 
 __global__ void k_sum_into(const double* part, int64_t nb, double* out) {
@@ -400,8 +424,11 @@ int64_t assign_blocks(int64_t n) {
 }
 
 struct KmLayout {
-  size_t off_u, off_d2, off_bsum, off_sums, off_cnt, off_max, off_obj, off_objv, off_sel, total;
+  size_t off_u, off_d2, off_bsum, off_sums, off_cnt, off_max, off_obj, off_objv, off_sel, off_cp,
+      total;
 };
+
+int padded_k(int k) { return (k + kKG - 1) / kKG * kKG; }
 
 KmLayout km_layout(int64_t n, int d, int k) {
   KmLayout L{};
@@ -416,6 +443,7 @@ KmLayout km_layout(int64_t n, int d, int k) {
   L.off_obj = off; off += align_up(static_cast<size_t>(blocks) * 8);
   L.off_objv = off; off += align_up(static_cast<size_t>(1024 + 1) * 8);
   L.off_sel = off; off += 256;
+  L.off_cp = off; off += align_up(static_cast<size_t>(padded_k(k)) * padded_d(d) * 4);
   L.total = off;
   return L;
 }
@@ -472,17 +500,17 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
 
 size_t kmeans_workspace(int64_t n, int d, int k) { return km_layout(n, d, k).total; }
 
-csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
-                                const float* C, int k, int32_t* labels, float* best_d2,
-                                double* obj_part, hipStream_t s) {
-  CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
-  if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
+static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                              const float* C, int k, int32_t* labels, float* best_d2,
+                              double* obj_part, float* Cp, hipStream_t s) {
   const bool vec = rows_aligned(F, f_dt, ldf);
   const unsigned blocks = static_cast<unsigned>(assign_blocks(n));
   const int dp = padded_d(d);
+  const int kp = padded_k(k);
+  hipLaunchKernelGGL(k_pad_centroids, dim3((kp * dp + 255) / 256), dim3(256), 0, s, C, k, d, kp, dp, Cp);
 #define CSC_ASSIGN(TF, V)                                                                         \
   hipLaunchKernelGGL((k_assign<TF, V>), dim3(blocks), dim3(kThreads), 0, s,                       \
-                     static_cast<const TF*>(F), ldf, n, d, dp, C, k, labels, best_d2, obj_part)
+                     static_cast<const TF*>(F), ldf, n, d, dp, Cp, k, labels, best_d2, obj_part)
   if (f_dt == CSC_F32) {
     if (vec) CSC_ASSIGN(float, true); else CSC_ASSIGN(float, false);
   } else {
@@ -491,6 +519,26 @@ csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int6
 #undef CSC_ASSIGN
   CSC_HIP(hipGetLastError());
   return CSC_OK;
+}
+
+csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                                const float* C, int k, int32_t* labels, float* best_d2,
+                                double* obj_part, hipStream_t s) {
+  CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
+  if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
+  // the ABI call has no workspace: the padded centroids live in a small per-device buffer
+  // owned by the library (grown on demand, kept until exit)
+  static float* cp_buf = nullptr;
+  static size_t cp_bytes = 0;
+  const size_t need = static_cast<size_t>(padded_k(k)) * padded_d(d) * 4;
+  if (need > cp_bytes) {
+    if (cp_buf) (void)hipFree(cp_buf);
+    cp_buf = nullptr;
+    cp_bytes = 0;
+    CSC_HIP(hipMalloc(&cp_buf, need));
+    cp_bytes = need;
+  }
+  return assign_impl(F, f_dt, ldf, n, d, C, k, labels, best_d2, obj_part, cp_buf, s);
 }
 
 csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
@@ -576,8 +624,8 @@ csc_status run_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
   }
   const int64_t nparts = assign_blocks(n);
   for (int it = 0; it <= iters; ++it) {
-    CSC_TRY(launch_kmeans_assign(F, f_dt, ldf, n, d, C, k, labels, nullptr,
-                                 objective ? obj : nullptr, s));
+    CSC_TRY(assign_impl(F, f_dt, ldf, n, d, C, k, labels, nullptr, objective ? obj : nullptr,
+                        reinterpret_cast<float*>(base + L.off_cp), s));
     if (objective)
       hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(kThreads), 0, s, obj, nparts, objv + it);
     if (it < iters) CSC_TRY(update_impl(F, f_dt, ldf, n, d, labels, k, C, nullptr, work, true, s));
