@@ -44,14 +44,36 @@ def parse():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--m", type=int, default=120)
     ap.add_argument("--p", type=float, default=0.5)
-    ap.add_argument("--headline", choices=["bf16", "fp32"], default="bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16",
-                    help="fp32: all FP32; bf16: BF16 signals, features, operator values and "
-                         "recurrence iterates with FP32 arithmetic and accumulation; bf16io: BF16 "
-                         "signals, features and values with FP32 iterates")
-    return ap.parse_args()
+    ap.add_argument("--forms", default="fp32,bf16,bf16b",
+                    help="comma list of " + ", ".join(f"{k}: {v[5]}" for k, v in FORMS.items()))
+    ap.add_argument("--headline", default="bf16b")
+    ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3")
+    args = ap.parse_args()
+    if args.workload == "c5" and "--n" not in sys.argv:
+        args.n, args.k, args.d, args.m, args.p = 8_000_000, 200, 256, 150, 0.75
+    if args.workload == "c2" and "--n" not in sys.argv:
+        args.n, args.k, args.d, args.m = 200_000, 20, 64, 100
+    if args.workload == "c4" and "--n" not in sys.argv:
+        args.n, args.k, args.d, args.m = 200_000, 20, 64, 60
+    return args
+
+
+# name -> (features/signals, iterates, operator values, batched, hipGraph replay, description)
+FORMS = {
+    "fp32": ("float32", "float32", "float32", False, False, "FP32 everywhere"),
+    "bf16": ("bfloat16", "bfloat16", "bfloat16", False, False,
+             "BF16 signals, features, operator values and recurrence iterates; FP32 arithmetic "
+             "and accumulation"),
+    "bf16io": ("bfloat16", "float32", "bfloat16", False, False,
+               "BF16 signals, features and operator values; FP32 iterates"),
+    "bf16b": ("bfloat16", "bfloat16", "bfloat16", True, True,
+              "the bf16 form with the fresh blocks of --batch snapshots filtered in one batched "
+              "recurrence replayed from a HIP graph"),
+    "fp32g": ("float32", "float32", "float32", False, True, "FP32 with HIP-graph replay"),
+}
 
 
 def kernel_digest() -> str:
@@ -81,6 +103,17 @@ def build_sequence(args, T):
     from workloads import DynamicSBM, block_sizes_zipf, sbm, seed_for
 
     t0 = time.perf_counter()
+    if args.workload == "c5":
+        from workloads import chung_lu
+        from workloads.graphs import rewire_model_free
+
+        g = chung_lu(args.n, args.k, 20.0, 2.5, 0.1, seed=seed_for(5, "graph"))
+        log(f"[bench] snapshot 1: nnz {g.nnz} ({time.perf_counter() - t0:.1f} s)")
+        seq = [g]
+        for t in range(2, T + 1):
+            seq.append(rewire_model_free(seq[-1], 0.005, seed_for(5, "perturb") + t, 0.1))
+            log(f"[bench] snapshot {t}: nnz {seq[-1].nnz} ({time.perf_counter() - t0:.1f} s)")
+        return seq, np
     sizes = block_sizes_zipf(args.n, args.k, 1.2)
     g = sbm(args.n, args.k, 16.0, 0.1, seed=seed_for(3, "graph"), sizes=sizes)
     log(f"[bench] snapshot 1: nnz {g.nnz} ({time.perf_counter() - t0:.1f} s)")
@@ -99,6 +132,10 @@ def main():
               "across GPUs is described in DESIGN.md but not built); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    {"c3": run_dynamic, "c5": run_dynamic, "c2": run_static, "c4": run_adjoint}[args.workload](args)
+
+
+def run_dynamic(args):
     import numpy as np
     import torch
 
@@ -121,31 +158,43 @@ def main():
     digest = kernel_digest()
     final_labels = {}
     for form in args.forms.split(","):
-        bf = form in ("bf16", "bf16io")
-        feat = torch.bfloat16 if bf else torch.float32
-        iters = torch.bfloat16 if form == "bf16" else torch.float32
-        vals = torch.bfloat16 if bf else torch.float32
+        fdt, idt, vdt, batched, graph, _ = FORMS[form]
+        feat, iters, vals = (getattr(torch, x) for x in (fdt, idt, vdt))
+        bf = vals == torch.bfloat16
         rp, ci, ww = resident[0]
         G = csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=True, nnz_capacity=cap)
         dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(3, "signals"),
-                             feat_dtype=feat, iter_dtype=iters)
+                             feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
+                             use_graph=graph, keep_iterates=1 if batched else -1)
         labels = torch.empty(args.n, dtype=torch.int32, device=dev)
         _, lam, ref, cnt = dyn.step(G, labels)
         log(f"[bench] {form}: snapshot 1 lambda {lam:.5f} count {cnt:.2f}")
         for t in range(2, 2 + args.warmup):
             G.update_device(*resident[t - 1], validate=False)
             dyn.step(G, labels)
+        timed = list(range(2 + args.warmup, T + 1))
+        if batched:
+            Gs = [G] + [csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=False, nnz_capacity=cap)
+                        for _ in range(len(timed) - 1)]
+            labs = [torch.empty(args.n, dtype=torch.int32, device=dev) for _ in timed]
         torch.cuda.synchronize()
         csc.timing_reset()
         csc.timing_enable(True)
         refines = 0
         lams = []
         t0 = time.perf_counter()
-        for t in range(2 + args.warmup, T + 1):
-            G.update_device(*resident[t - 1], validate=False)
-            _, lam, ref, cnt = dyn.step(G, labels)
-            refines += int(ref)
-            lams.append(lam)
+        if batched:
+            for q, t in enumerate(timed):
+                Gs[q].update_device(*resident[t - 1], validate=False)
+            labs, lams, refs, _ = dyn.steps(Gs, labs)
+            refines = sum(refs)
+            labels = labs[-1]
+        else:
+            for t in timed:
+                G.update_device(*resident[t - 1], validate=False)
+                _, lam, ref, cnt = dyn.step(G, labels)
+                refines += int(ref)
+                lams.append(lam)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         final_labels[form] = labels.cpu().numpy()
@@ -163,12 +212,14 @@ def main():
             bytes_per_launch=kbytes / launches,
             refines=refines,
             lambda_last=lams[-1] if lams else None,
-            storage=dict(signals=str(feat).replace("torch.", ""), features=str(feat).replace("torch.", ""),
-                         values=str(vals).replace("torch.", ""), iterates=str(iters).replace("torch.", ""),
-                         accumulate="float32"),
+            storage=dict(signals=fdt, features=fdt, values=vdt, iterates=idt, accumulate="float32"),
+            batch=args.batch if batched else 1,
+            hip_graph=graph,
             G=G,
         )
         del dyn
+        if batched:
+            del Gs
 
     # error of each form's filter against the FP64 oracle on 10k sampled rows (4 columns),
     # at a fixed cut-off on the last snapshot; the oracle run doubles as the CPU baseline
@@ -200,11 +251,12 @@ def main():
                    seconds=t_cpu)
         ref_rows = ref[rows]
         for form, rec in forms.items():
-            bf = form in ("bf16", "bf16io")
+            fdt, idt, vdt = FORMS[form][:3]
+            bf = vdt == "bfloat16"
             Xt = torch.from_numpy(X).to(dev)
             if bf:
                 Xt = Xt.to(torch.bfloat16)
-            iters = torch.bfloat16 if form == "bf16" else torch.float32
+            iters = getattr(torch, idt)
             G = rec["G"]
             G.update_device(*resident[-1], validate=False)
             Y = csc.cheb_filter(G, a, Xt, out_dtype=Xt.dtype, iter_dtype=iters).float().cpu().numpy()
@@ -234,14 +286,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16-storage/f32" if args.headline == "bf16" else "f32",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
             "workload": (f"dynamic SBM N={args.n}, k={args.k} Zipf(1.2) blocks, degree 16, ratio 0.1, "
                          f"1% edges rewired + 0.5% nodes moved per snapshot; d={args.d}, m={args.m}, "
-                         f"p={args.p}; step = one dynamic snapshot"),
+                         f"p={args.p}; step = one dynamic snapshot") if args.workload == "c3" else
+                        (f"dynamic Chung-Lu N={args.n}, exponent 2.5, degree 20, {args.k} planted "
+                         f"communities, ratio 0.1, 0.5% edges rewired per snapshot; d={args.d}, "
+                         f"m={args.m}, p={args.p}; step = one dynamic snapshot"),
             "n": args.n, "nnz_max": cap, "d": args.d, "m": args.m, "p": args.p, "k": args.k,
-            "parallelism": "single GPU",
+            "storage": FORMS[args.headline][5], "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
@@ -260,8 +315,16 @@ def main():
         "cpu_baseline": None if args.no_cpu_baseline else cpu,
         "kernel_sha256_16": digest,
     }
-    if "fp32" in forms and "bf16" in forms:
-        out["bf16_speedup_per_snapshot"] = round(forms["fp32"]["ms_per_snapshot"] / forms["bf16"]["ms_per_snapshot"], 4)
+    if "fp32" in forms:
+        out["speedup_per_snapshot_vs_fp32"] = {
+            f: round(forms["fp32"]["ms_per_snapshot"] / r["ms_per_snapshot"], 4) for f, r in forms.items() if f != "fp32"}
+    planted = seq[-1].labels
+    agree_planted = {}
+    for f, lab in final_labels.items():
+        cont = np.zeros((args.k, args.k), dtype=np.int64)
+        np.add.at(cont, (planted, lab), 1)
+        agree_planted[f] = round(float(cont.max(axis=1).sum()) / len(planted), 5)
+    out["label_agreement_vs_planted_last_snapshot"] = agree_planted
     if "fp32" in final_labels:
         # agreement of the last snapshot's partition with the FP32 form's, up to relabelling
         ref = final_labels["fp32"]
@@ -274,6 +337,102 @@ def main():
             agree[f] = round(float(cont.max(axis=1).sum()) / len(ref), 5)
         out["label_agreement_vs_fp32_last_snapshot"] = agree
     print(json.dumps(out), flush=True)
+
+
+def _line(args, metric, value, unit, ms, extra):
+    out = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def run_static(args):
+    """C2: static CSC on an SBM (N=200k, k=20, degree 20): eigencount with 24 probes and a
+    16-step dichotomy (one moment pass), the filter of 64 signals at the found cut-off (m=100),
+    k-means++ and 20 Lloyd rounds.  A step is one full static CSC."""
+    import numpy as np
+    import torch
+
+    import paper_1706_03591_amd as csc
+    from workloads import gaussian_block, sbm, seed_for
+
+    g = sbm(args.n, args.k, 20.0, 0.1, seed=seed_for(2, "graph"))
+    log(f"[bench] C2 graph nnz {g.nnz}")
+    G = csc.Graph.from_workload(g)
+    R = torch.from_numpy(gaussian_block(args.n, args.d, 1 / np.sqrt(args.d), seed=seed_for(2, "signals"))).cuda()
+    P = torch.from_numpy(gaussian_block(args.n, 24, 1 / np.sqrt(args.d), seed=seed_for(2, "probes"))).cuda()
+    Y = torch.empty_like(R)
+
+    def once():
+        lam, cnt, _, _ = csc.eigcount(G, args.m, P, sigma2=1.0 / args.d, k=args.k, n_cand=16)
+        a = csc.cheb_coeffs(args.m, 2.0, lam)
+        csc.cheb_filter(G, a, R, out=Y)
+        lab, C = csc.kmeans(Y, args.k, iters=20, seed=seed_for(2, "kmeans"), stream_id=2)
+        return lam, cnt
+
+    for _ in range(args.warmup):
+        once()
+    torch.cuda.synchronize()
+    csc.timing_reset()
+    csc.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lam, cnt = once()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    kms, launches, kbytes = csc.timing_read()
+    csc.timing_enable(False)
+    _line(args, "static CSC: Chebyshev SpMM GB/s & ms per clustering", kbytes / (wall * args.steps) / 1e9,
+          "GB/s", wall * 1e3,
+          {"config": {"workload": f"static SBM N={args.n}, k={args.k}, degree 20, ratio 0.1; 24 probes, "
+                                  f"16 dichotomy steps, d={args.d}, m={args.m}, 20 Lloyd rounds",
+                      "nnz": g.nnz, "lambda": lam, "count": cnt},
+           "roofline": {"bound": "hbm", "achieved": round(kbytes / (kms * 1e-3) / 1e9, 1),
+                        "peak": PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(kbytes / (kms * 1e-3) / 1e9 / PEAK_GBPS, 4),
+                        "avg_launch_us": round(kms / launches * 1e3, 2), "traffic": None}})
+
+
+def run_adjoint(args):
+    """C4: Chebyshev filter forward (m=60, 64 signals) and its adjoint (dX, the 61 coefficient
+    gradients and one gradient per stored edge value, checkpoints every 8 iterates) on the
+    N=200k SBM.  A step is one forward plus one backward."""
+    import numpy as np
+    import torch
+
+    import paper_1706_03591_amd as csc
+    from workloads import gaussian_block, sbm, seed_for
+
+    g = sbm(args.n, args.k, 20.0, 0.1, seed=seed_for(4, "graph"))
+    G = csc.Graph.from_workload(g)
+    X = torch.from_numpy(gaussian_block(args.n, args.d, 1 / np.sqrt(args.d), seed=seed_for(4, "signals"))).cuda()
+    Gr = torch.from_numpy(gaussian_block(args.n, args.d, 1.0, seed=seed_for(4, "probes"))).cuda()
+    a = csc.cheb_coeffs(args.m, 2.0, 0.5)
+    Y = torch.empty_like(X)
+
+    def once():
+        csc.cheb_filter(G, a, X, out=Y)
+        return csc.filter_backward(G, a, X, Gr, ckpt_every=8)
+
+    for _ in range(args.warmup):
+        once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        once()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    nnz = g.nnz
+    nw = args.n * args.d
+    fwd = args.m * (nnz * 8 + 4 * (args.n + 1) + nw * 20)
+    # backward: checkpointed forward (3 streams + G read per step), segment recompute (same),
+    # adjoint steps (2 gathers + 2 streams + G read + one dA read-modify-write per entry)
+    bwd = args.m * (nnz * 8 + nw * 16) * 2 + args.m * (nnz * 16 + nw * 20)
+    _line(args, "Chebyshev filter forward+backward: algorithmic GB/s & ms per pair",
+          (fwd + bwd) / wall / 1e9, "GB/s", wall * 1e3,
+          {"config": {"workload": f"SBM N={args.n}, k={args.k}, degree 20; w={args.d}, m={args.m}, "
+                                  f"checkpoint every 8 iterates; dX, da and dA", "nnz": nnz}})
 
 
 if __name__ == "__main__":

@@ -250,6 +250,11 @@ typedef struct {
   int keep_iterates;  /* -1: keep all m + 1 iterates of the fresh block when they fit in free
                          device memory (a refinement then recombines them instead of running
                          the recurrence again); 0: never; 1: always (CSC_E_NOMEM otherwise) */
+  int batch;          /* csc_dynamic_steps: fresh blocks of up to `batch` (<= 8) snapshots are
+                         filtered together, one launch per recurrence step; needs the
+                         iterates kept (0 or 1 -> one snapshot at a time) */
+  int use_graph;      /* non-zero: the recurrence launches are captured once in a HIP graph
+                         and replayed for every snapshot (or batch) */
 } csc_dyn_opts;
 
 csc_status csc_dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp,
@@ -257,6 +262,14 @@ csc_status csc_dyn_create(int64_t n, int d, int k, double p, int m, csc_damping 
                           csc_dyn* out);
 csc_status csc_dynamic_step(csc_dyn st, csc_graph g_t, int32_t* labels, double* lambda_t,
                             int* refined, double* count, void* stream);
+/* S snapshots in order (Algorithm 1 steps 4-8 for each): the fresh signals of up to
+ * opts->batch snapshots are filtered in one batched recurrence (their graphs must share n
+ * and the value type), then each snapshot's eigencount check, refinement, ring update and
+ * k-means run in order, so the results equal S calls to csc_dynamic_step.  labels[i]:
+ * device int32[n] per snapshot; lambdas, refined, counts: host arrays of S or NULL.
+ * Synchronising. */
+csc_status csc_dynamic_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
+                             double* lambdas, int* refined, double* counts, void* stream);
 /* Device view of Theta (n x d, type *dt, leading dimension *ld) and the centroids
  * (float[k * d]).  Valid until destroy. */
 csc_status csc_dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,

@@ -44,7 +44,7 @@ pdbl, pi64, pint = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_in
 class DynOpts(C.Structure):
     _fields_ = [("lmax", C.c_double), ("tau", C.c_double), ("n_cand", C.c_int),
                 ("lloyd_iters", C.c_int), ("init", C.c_int), ("iter_dt", C.c_int),
-                ("keep_iterates", C.c_int)]
+                ("keep_iterates", C.c_int), ("batch", C.c_int), ("use_graph", C.c_int)]
 
 
 _SIGS = {
@@ -79,6 +79,7 @@ _SIGS = {
     "csc_dyn_create": ([i64, i32, i32, dbl, i32, i32, i32, u64, C.POINTER(DynOpts), C.POINTER(vp)],
                        i32),
     "csc_dynamic_step": ([vp, vp, vp, pdbl, pint, pdbl, vp], i32),
+    "csc_dynamic_steps": ([vp, C.POINTER(vp), i32, C.POINTER(vp), pdbl, pint, pdbl, vp], i32),
     "csc_dyn_features": ([vp, C.POINTER(vp), pint, pi64, C.POINTER(vp)], i32),
     "csc_dyn_destroy": ([vp], i32),
     "csc_cheb_backward_workspace_bytes": ([i64, i32, i32, i32], sz),
@@ -434,9 +435,10 @@ class DynamicCSC:
     def __init__(self, n: int, d: int, k: int, p: float, m: int, seed: int,
                  damping: int = DAMP_JACKSON, feat_dtype=torch.float32, iter_dtype=torch.float32,
                  lmax: float = 2.0, tau: float = 0.0, n_cand: int = 16, lloyd_iters: int = 20,
-                 init: int = 0, keep_iterates: int = -1):
+                 init: int = 0, keep_iterates: int = -1, batch: int = 1, use_graph: bool = False):
         opts = DynOpts(lmax=lmax, tau=tau, n_cand=n_cand, lloyd_iters=lloyd_iters, init=init,
-                       iter_dt=_TORCH_DT[iter_dtype], keep_iterates=keep_iterates)
+                       iter_dt=_TORCH_DT[iter_dtype], keep_iterates=keep_iterates, batch=batch,
+                       use_graph=int(bool(use_graph)))
         h = C.c_void_p()
         _check(lib.csc_dyn_create(int(n), int(d), int(k), float(p), int(m), int(damping),
                                   _TORCH_DT[feat_dtype], int(seed), C.byref(opts), C.byref(h)))
@@ -452,6 +454,20 @@ class DynamicCSC:
         _check(lib.csc_dynamic_step(self.h, g.h, _ptr(labels), C.byref(lam), C.byref(ref),
                                     C.byref(cnt), _stream(stream)))
         return labels, lam.value, bool(ref.value), cnt.value
+
+    def steps(self, graphs, labels=None, stream=None):
+        """Several snapshots in order (batched recurrences when the state was created with
+        batch > 1).  Returns (labels list, lambdas, refined, counts)."""
+        S = len(graphs)
+        if labels is None:
+            labels = [torch.empty(self.n, dtype=torch.int32, device="cuda") for _ in range(S)]
+        gh = (C.c_void_p * S)(*[g.h.value for g in graphs])
+        lp = (C.c_void_p * S)(*[lab.data_ptr() for lab in labels])
+        lam = (C.c_double * S)()
+        ref = (C.c_int * S)()
+        cnt = (C.c_double * S)()
+        _check(lib.csc_dynamic_steps(self.h, gh, S, lp, lam, ref, cnt, _stream(stream)))
+        return labels, list(lam), [bool(x) for x in ref], list(cnt)
 
     def features(self) -> torch.Tensor:
         th, dt, ld, cp = C.c_void_p(), C.c_int(), C.c_int64(), C.c_void_p()

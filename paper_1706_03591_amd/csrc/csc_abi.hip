@@ -116,6 +116,8 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
                       csc_dtype feat_dt, uint64_t seed, const csc_dyn_opts* opts, csc_dyn* out);
 csc_status dyn_step(csc_dyn st, csc_graph g, int32_t* labels, double* lambda_t, int* refined,
                     double* count, void* stream);
+csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
+                     double* lambdas, int* refined, double* counts, void* stream);
 csc_status dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,
                         const float** centroids);
 csc_status dyn_destroy(csc_dyn st);
@@ -428,6 +430,11 @@ csc_status csc_dyn_create(int64_t n, int d, int k, double p, int m, csc_damping 
 csc_status csc_dynamic_step(csc_dyn st, csc_graph g, int32_t* labels, double* lambda_t,
                             int* refined, double* count, void* stream) {
   return dyn_step(st, g, labels, lambda_t, refined, count, stream);
+}
+
+csc_status csc_dynamic_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
+                             double* lambdas, int* refined, double* counts, void* stream) {
+  return dyn_steps(st, graphs, S, labels, lambdas, refined, counts, stream);
 }
 
 csc_status csc_dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,

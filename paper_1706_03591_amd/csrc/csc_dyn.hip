@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -31,8 +32,13 @@ struct csc_dyn_s {
   size_t kwork_bytes = 0;
   void* dwork = nullptr;
   size_t dwork_bytes = 0;
-  void* basis = nullptr;      // (m + 1) iterate slots of the fresh block, or null
-  size_t basis_bytes = 0;
+  void* basis = nullptr;      // batch x (m + 1) iterate slots of the fresh blocks, or null
+  size_t basis_bytes = 0;     // per snapshot
+  int batch = 1;              // snapshots whose recurrences advance together
+  bool use_graph = false;     // replay the recurrence launches from a captured HIP graph
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* exec_key[9] = {};
   void* aux = nullptr;
   size_t aux_bytes = 0;
   int variant = 0;
@@ -54,6 +60,8 @@ void free_dyn(csc_dyn st) {
   for (void* p : {st->theta, st->sig, static_cast<void*>(st->C), static_cast<void*>(st->prev),
                   static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork, st->basis, st->aux})
     if (p) (void)hipFree(p);
+  if (st->exec) (void)hipGraphExecDestroy(st->exec);
+  if (st->cap) (void)hipStreamDestroy(st->cap);
   delete st;
 }
 
@@ -86,6 +94,8 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   st->feat_dt = feat_dt;
   st->seed = seed;
   if (opts) {
+    st->batch = opts->batch >= 1 ? opts->batch : 1;
+    st->use_graph = opts->use_graph != 0;
     st->lmax = opts->lmax > 0.0 ? opts->lmax : 2.0;
     st->tau = opts->tau;
     st->n_cand = opts->n_cand > 0 ? opts->n_cand : 16;
@@ -98,12 +108,16 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     delete st;
     return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
   }
+  if (st->batch > 8) {
+    delete st;
+    return fail(CSC_E_ARG, "batch must be in [1, 8]");
+  }
   const size_t es = dtype_size(feat_dt);
   st->fwork_bytes = filter_workspace(n, d, st->iter_dt);
   st->kwork_bytes = kmeans_workspace(n, d, k);
   st->dwork_bytes = dot_workspace(n);
   bool ok = hipMalloc(&st->theta, es * n * d) == hipSuccess &&
-            hipMalloc(&st->sig, es * n * d) == hipSuccess &&
+            hipMalloc(&st->sig, es * n * std::max(d, st->batch * qd)) == hipSuccess &&
             hipMalloc(&st->C, sizeof(float) * k * d) == hipSuccess &&
             hipMalloc(&st->prev, sizeof(int32_t) * n) == hipSuccess &&
             hipMalloc(&st->scal, sizeof(double) * (m + 2)) == hipSuccess &&
@@ -126,8 +140,9 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     const size_t margin = size_t(4) << 30;
-    if (keep == 1 || st->basis_bytes + st->aux_bytes + margin <= free_b) {
-      if (hipMalloc(&st->basis, st->basis_bytes) != hipSuccess ||
+    const size_t want = st->basis_bytes * st->batch;
+    if (keep == 1 || want + st->aux_bytes + margin <= free_b) {
+      if (hipMalloc(&st->basis, want) != hipSuccess ||
           hipMalloc(&st->aux, st->aux_bytes) != hipSuccess) {
         if (keep == 1) {
           free_dyn(st);
@@ -139,16 +154,89 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
       }
     }
   }
+  if (st->batch > 1 && !st->basis) {
+    free_dyn(st);
+    return fail(CSC_E_NOMEM, "a batch of snapshots needs their iterates kept on the device");
+  }
+  if (st->use_graph && hipStreamCreate(&st->cap) != hipSuccess) {
+    free_dyn(st);
+    return fail(CSC_E_HIP, "cannot create the capture stream");
+  }
   *out = st;
   return CSC_OK;
 }
 
-csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t, int* refined,
-                    double* count, void* stream) {
-  if (!st || !gh || !labels) return fail(CSC_E_ARG, "null argument");
-  const Graph* g = &gh->g;
-  if (g->n != st->n) return fail(CSC_E_ARG, "graph size differs from the state's");
-  hipStream_t s = as_stream(stream);
+namespace {
+
+// Fresh signals of snapshot t into signal slot `slot`.
+csc_status draw_signals(csc_dyn st, int t, int slot, hipStream_t s) {
+  const double sigma = 1.0 / std::sqrt(static_cast<double>(st->d));
+  char* sig = static_cast<char*>(st->sig) + dtype_size(st->feat_dt) * static_cast<size_t>(slot) * st->n * st->qd;
+  return launch_randn(sig, st->feat_dt, st->n, st->qd, st->qd, 0, st->seed, stream_id(t, kSignals), sigma, s);
+}
+
+void* sig_slot(csc_dyn st, int slot) {
+  return static_cast<char*>(st->sig) + dtype_size(st->feat_dt) * static_cast<size_t>(slot) * st->n * st->qd;
+}
+
+void* basis_slot(csc_dyn st, int slot) {
+  return static_cast<char*>(st->basis) + st->basis_bytes * static_cast<size_t>(slot);
+}
+
+// The recurrences of S snapshots (slots 0..S-1), replayed from a captured graph when enabled.
+csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s) {
+  const void* X[8];
+  void* B[8];
+  for (int i = 0; i < S; ++i) {
+    X[i] = sig_slot(st, i);
+    B[i] = basis_slot(st, i);
+  }
+  if (!st->use_graph)
+    return run_basis_batch(gs, S, st->lmax, st->m, X, st->feat_dt, st->qd, st->qd, st->iter_dt,
+                           st->variant, B, st->basis_bytes, s, true);
+  const void* key[9] = {};
+  key[0] = reinterpret_cast<const void*>(static_cast<intptr_t>(S));
+  for (int i = 0; i < S; ++i) key[1 + i] = gs[i];
+  bool same = st->exec != nullptr;
+  for (int i = 0; i < 9 && same; ++i) same = key[i] == st->exec_key[i];
+  if (!same) {
+    if (st->exec) {
+      (void)hipGraphExecDestroy(st->exec);
+      st->exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    CSC_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeRelaxed));
+    const csc_status cs = run_basis_batch(gs, S, st->lmax, st->m, X, st->feat_dt, st->qd, st->qd,
+                                          st->iter_dt, st->variant, B, st->basis_bytes, st->cap, false);
+    const hipError_t e = hipStreamEndCapture(st->cap, &graph);
+    if (cs != CSC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cs;
+    }
+    if (e != hipSuccess) return fail(CSC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t ie = hipGraphInstantiate(&st->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      st->exec = nullptr;
+      return fail(CSC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    for (int i = 0; i < 9; ++i) st->exec_key[i] = key[i];
+  }
+  timing_begin(s);
+  CSC_HIP(hipGraphLaunch(st->exec, s));
+  timing_end(s, st->m, basis_batch_bytes(gs, S, st->m, st->qd, st->iter_dt));
+  return CSC_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// One snapshot of Algorithm 1.  For t >= 2 the fresh signals and (when kept) their iterates
+// live in slot `slot`; with pre_basis the signals are drawn and the iterates computed already
+// (batched recurrence).
+csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32_t* labels,
+                     double* lambda_t, int* refined, double* count, hipStream_t s) {
   const int t = ++st->t;
   const double sigma = 1.0 / std::sqrt(static_cast<double>(st->d));
   const double sigma2 = sigma * sigma;
@@ -178,21 +266,21 @@ csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t,
     // Steps 4-7: fresh q d columns filtered with h^{t-1}, eigencount, optional refinement.
     const int b = st->next_block;
     char* blk = static_cast<char*>(st->theta) + es * static_cast<size_t>(b) * st->qd;
-    CSC_TRY(launch_randn(st->sig, st->feat_dt, st->n, st->qd, st->qd, 0, st->seed,
-                         stream_id(t, kSignals), sigma, s));
+    void* sig = sig_slot(st, slot);
+    void* basis = st->basis ? basis_slot(st, slot) : nullptr;
+    if (!pre_basis) CSC_TRY(draw_signals(st, t, slot, s));
     cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
     const bool kept = st->basis != nullptr;
     if (kept) {
-      CSC_TRY(run_basis(g, st->lmax, st->m, st->sig, st->feat_dt, st->qd, st->qd, st->iter_dt,
-                        st->variant, st->basis, st->basis_bytes, s));
-      CSC_TRY(run_combine(st->basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
-                          st->feat_dt, st->d, st->sig, st->feat_dt, st->qd, st->scal, st->aux,
+      if (!pre_basis) CSC_TRY(batch_basis(st, &g, 1, s));
+      CSC_TRY(run_combine(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
+                          st->feat_dt, st->d, sig, st->feat_dt, st->qd, st->scal, st->aux,
                           st->aux_bytes, s));
     } else {
-      CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->qd, blk,
+      CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
                          st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
                          st->fwork_bytes, s));
-      CSC_TRY(launch_dot(st->sig, st->feat_dt, st->qd, blk, st->feat_dt, st->d, st->n, st->qd,
+      CSC_TRY(launch_dot(sig, st->feat_dt, st->qd, blk, st->feat_dt, st->d, st->n, st->qd,
                          st->scal, st->dwork, st->dwork_bytes, s));
     }
     double dot = 0.0;
@@ -201,10 +289,10 @@ csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t,
     cnt = dot / (sigma2 * st->qd);
     if (std::fabs(cnt - st->k) > st->tau) {
       if (kept)
-        CSC_TRY(run_basis_moments(st->basis, st->n, st->qd, st->m, st->iter_dt, st->variant, mu_d,
+        CSC_TRY(run_basis_moments(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, mu_d,
                                   st->aux, st->aux_bytes, s));
       else
-        CSC_TRY(run_filter(g, st->lmax, st->m, nullptr, st->sig, st->feat_dt, st->qd, nullptr,
+        CSC_TRY(run_filter(g, st->lmax, st->m, nullptr, sig, st->feat_dt, st->qd, nullptr,
                            CSC_F32, 0, st->qd, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
       CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
       CSC_HIP(hipStreamSynchronize(s));
@@ -214,11 +302,11 @@ csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t,
                      hi, &st->lam, &cnt, nullptr);
       cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
       if (kept)
-        CSC_TRY(run_combine(st->basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
+        CSC_TRY(run_combine(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
                             st->feat_dt, st->d, nullptr, st->feat_dt, 0, nullptr, st->aux,
                             st->aux_bytes, s));
       else
-        CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->qd, blk,
+        CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
                            st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
                            st->fwork_bytes, s));
       ref = 1;
@@ -244,6 +332,55 @@ csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t,
   if (lambda_t) *lambda_t = st->lam;
   if (refined) *refined = ref;
   if (count) *count = cnt;
+  return CSC_OK;
+}
+
+}  // namespace
+
+csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t, int* refined,
+                    double* count, void* stream) {
+  if (!st || !gh || !labels) return fail(CSC_E_ARG, "null argument");
+  if (gh->g.n != st->n) return fail(CSC_E_ARG, "graph size differs from the state's");
+  return step_impl(st, &gh->g, 0, false, labels, lambda_t, refined, count, as_stream(stream));
+}
+
+// S snapshots in order.  After the first snapshot of the sequence, the fresh blocks of up to
+// `batch` snapshots are drawn and their recurrences advanced together (one launch per step);
+// the cut-off decisions, refinements and k-means then run snapshot by snapshot as in
+// Algorithm 1, so the results equal those of S calls to dyn_step.
+csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
+                     double* lambdas, int* refined, double* counts, void* stream) {
+  if (!st || !graphs || !labels || S < 0) return fail(CSC_E_ARG, "null argument");
+  hipStream_t s = as_stream(stream);
+  for (int i = 0; i < S; ++i) {
+    if (!graphs[i] || !labels[i]) return fail(CSC_E_ARG, "null graph or labels");
+    if (graphs[i]->g.n != st->n) return fail(CSC_E_ARG, "graph size differs from the state's");
+  }
+  int i = 0;
+  auto out = [&](int j) {
+    return std::make_tuple(lambdas ? lambdas + j : nullptr, refined ? refined + j : nullptr,
+                           counts ? counts + j : nullptr);
+  };
+  while (i < S) {
+    if (st->t == 0 || !st->basis) {
+      auto [l, r, c] = out(i);
+      CSC_TRY(step_impl(st, &graphs[i]->g, 0, false, labels[i], l, r, c, s));
+      ++i;
+      continue;
+    }
+    const int nb = std::min(st->batch, S - i);
+    const Graph* gs[8];
+    for (int q = 0; q < nb; ++q) {
+      gs[q] = &graphs[i + q]->g;
+      CSC_TRY(draw_signals(st, st->t + 1 + q, q, s));
+    }
+    CSC_TRY(batch_basis(st, gs, nb, s));
+    for (int q = 0; q < nb; ++q) {
+      auto [l, r, c] = out(i + q);
+      CSC_TRY(step_impl(st, gs[q], q, true, labels[i + q], l, r, c, s));
+    }
+    i += nb;
+  }
   return CSC_OK;
 }
 

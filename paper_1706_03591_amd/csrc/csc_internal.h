@@ -133,6 +133,12 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
 csc_status run_basis_moments(const void* basis, int64_t n, int w, int m, csc_dtype iter_dt,
                              int variant, double* moments, void* aux, size_t aux_bytes,
                              hipStream_t s);
+// S (<= 8) independent recurrences advanced together, one launch per step.
+csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m,
+                           const void* const* X, csc_dtype x_dt, int64_t ldx, int w,
+                           csc_dtype iter_dt, int variant, void* const* bases, size_t bytes,
+                           hipStream_t s, bool timed);
+double basis_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dtype iter_dt);
 
 // ------------------------------------------------------------------------------------
 // reductions, RNG

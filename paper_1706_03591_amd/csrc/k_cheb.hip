@@ -124,8 +124,10 @@ __device__ inline void block_reduce2(double& a, double& b) {
   }
 }
 
+// Body of one step for block `bid` of a launch of `nblocks` blocks (the batched launch runs
+// several snapshots' steps, each with its own parameters and block range).
 template <typename TZ, typename TV, int LPR>
-__global__ __launch_bounds__(kThreads) void k_step(StepParams p) {
+__device__ inline void step_body(const StepParams& p, const int64_t bid, const int64_t nblocks) {
   using P = Pack<TZ>;
   constexpr int VEC = P::VEC;
   constexpr int WT = LPR * VEC;
@@ -133,7 +135,6 @@ __global__ __launch_bounds__(kThreads) void k_step(StepParams p) {
   __shared__ int32_t s_col[kStageCap];
   __shared__ float s_val[kStageCap];
 
-  const int64_t bid = blockIdx.x;
   const int64_t tile = bid / p.row_blocks;
   const int64_t rb = bid - tile * p.row_blocks;
   const int64_t r0 = rb * RPB;
@@ -265,9 +266,28 @@ __global__ __launch_bounds__(kThreads) void k_step(StepParams p) {
     block_reduce2(d1, d2);
     if (threadIdx.x == 0) {
       p.mom_part[bid] = d1;
-      p.mom_part[gridDim.x + bid] = d2;
+      p.mom_part[nblocks + bid] = d2;
     }
   }
+}
+
+template <typename TZ, typename TV, int LPR>
+__global__ __launch_bounds__(kThreads) void k_step(StepParams p) {
+  step_body<TZ, TV, LPR>(p, blockIdx.x, gridDim.x);
+}
+
+// Several independent steps (one per snapshot of a batch, same n and tile shape) in one
+// launch: block b runs step b / per of the batch.
+constexpr int kMaxBatch = 8;
+struct StepBatch {
+  StepParams p[kMaxBatch];
+  int64_t per;
+};
+
+template <typename TZ, typename TV, int LPR>
+__global__ __launch_bounds__(kThreads) void k_step_batch(StepBatch b) {
+  const int s = static_cast<int>(blockIdx.x / b.per);
+  step_body<TZ, TV, LPR>(b.p[s], blockIdx.x - s * b.per, b.per);
 }
 
 // Z_0 (tiled, iter type) from X (row-major, x_dt); acc = a0 * Z_0 when acc != null.
@@ -343,6 +363,19 @@ StepFn pick_step(int lpr, csc_dtype val_dt) {
 }
 
 const int kLpr[] = {4, 8, 16, 32};
+
+using BatchFn = void (*)(StepBatch);
+
+template <typename TZ>
+BatchFn pick_batch(int lpr, csc_dtype val_dt) {
+  const bool vb = val_dt == CSC_BF16;
+  switch (lpr) {
+    case 4: return vb ? k_step_batch<TZ, uint16_t, 4> : k_step_batch<TZ, float, 4>;
+    case 8: return vb ? k_step_batch<TZ, uint16_t, 8> : k_step_batch<TZ, float, 8>;
+    case 16: return vb ? k_step_batch<TZ, uint16_t, 16> : k_step_batch<TZ, float, 16>;
+    default: return vb ? k_step_batch<TZ, uint16_t, 32> : k_step_batch<TZ, float, 32>;
+  }
+}
 
 }  // namespace
 
@@ -1093,6 +1126,83 @@ csc_status run_basis_moments(const void* basis, int64_t n, int w, int m, csc_dty
   hipLaunchKernelGGL(k_moments, dim3(1), dim3(64), 0, s, sums, J, m, moments);
   CSC_HIP(hipGetLastError());
   return CSC_OK;
+}
+
+}  // namespace csc
+
+// =====================================================================================
+// Batched basis: the recurrences of S snapshots (same n, width and tile shape; each with its
+// own graph, signals and basis) advance together, one launch per step.
+namespace csc {
+
+csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m,
+                           const void* const* X, csc_dtype x_dt, int64_t ldx, int w,
+                           csc_dtype iter_dt, int variant, void* const* bases, size_t bytes,
+                           hipStream_t s, bool timed) {
+  if (S < 1 || S > kMaxBatch) return fail(CSC_E_ARG, "batch size must be in [1, 8]");
+  const int64_t n = graphs[0]->n;
+  for (int i = 0; i < S; ++i) {
+    if (graphs[i]->n != n) return fail(CSC_E_ARG, "batched graphs must have the same n");
+    if (graphs[i]->val_dt != graphs[0]->val_dt) return fail(CSC_E_DTYPE, "batched graphs must share the value type");
+  }
+  if (m < 1 || w < 1 || ldx < w) return fail(CSC_E_ARG, "bad basis arguments");
+  if (iter_dt != CSC_F32 && iter_dt != CSC_BF16) return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
+  const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
+  if (bytes < static_cast<size_t>(m + 1) * slot_bytes) return fail(CSC_E_ARG, "basis buffer too small");
+  const int wt = pl.shape.wt();
+  const int64_t total = n * pl.wpad;
+  const unsigned iblocks = static_cast<unsigned>((total + 255) / 256);
+  for (int i = 0; i < S; ++i) {
+    if (iter_dt == CSC_F32)
+      hipLaunchKernelGGL(k_init<float>, dim3(iblocks), dim3(256), 0, s, X[i], int(x_dt), ldx, n, w,
+                         pl.wpad, wt, static_cast<float*>(bases[i]), static_cast<float*>(nullptr), 0.f);
+    else
+      hipLaunchKernelGGL(k_init<uint16_t>, dim3(iblocks), dim3(256), 0, s, X[i], int(x_dt), ldx, n, w,
+                         pl.wpad, wt, static_cast<uint16_t*>(bases[i]), static_cast<float*>(nullptr),
+                         0.f);
+  }
+  const BatchFn fn = iter_dt == CSC_F32 ? pick_batch<float>(pl.shape.lpr, graphs[0]->val_dt)
+                                        : pick_batch<uint16_t>(pl.shape.lpr, graphs[0]->val_dt);
+  const int64_t per = pl.row_blocks * pl.ntiles;
+  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
+  const float beta = static_cast<float>(2.0 / lmax);
+  double bytes_alg = 0.0;
+  if (timed) timing_begin(s);
+  for (int j = 0; j < m; ++j) {
+    StepBatch b{};
+    b.per = per;
+    for (int i = 0; i < S; ++i) {
+      StepParams& p = b.p[i];
+      const Graph* g = graphs[i];
+      char* base = static_cast<char*>(bases[i]);
+      p.rowptr = g->rowptr;
+      p.colidx = g->colidx;
+      p.vals = g->vals;
+      p.zcur = base + static_cast<size_t>(j) * slot_bytes;
+      p.zprev = j > 0 ? base + static_cast<size_t>(j - 1) * slot_bytes : nullptr;
+      p.zout = base + static_cast<size_t>(j + 1) * slot_bytes;
+      p.w = w;
+      p.n = n;
+      p.row_blocks = pl.row_blocks;
+      p.alpha = alpha;
+      p.beta = beta;
+      p.flags = F_STORE | (j == 0 ? F_FIRST : 0) | (alpha != 0.f ? F_OWN : 0);
+      bytes_alg += step_bytes(g, n, w, iter_dt, p.flags, CSC_F32);
+    }
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(per * S)), dim3(kThreads), 0, s, b);
+  }
+  if (timed) timing_end(s, m, bytes_alg);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+double basis_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dtype iter_dt) {
+  double b = 0.0;
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < m; ++j)
+      b += step_bytes(graphs[i], graphs[i]->n, w, iter_dt, F_STORE | (j == 0 ? F_FIRST : 0), CSC_F32);
+  return b;
 }
 
 }  // namespace csc

@@ -162,6 +162,166 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
   }
 }
 
+// MFMA form of the assignment (when the centroids fit in LDS).  The cross term F C^T is a
+// dense contraction, done with FP64 matrix cores (v_mfma_f64_16x16x4: A[i][k] from lane
+// i + 16k, B[k][j] from lane j + 16k, output register r of lane l holds D[4r + l/16][l%16]).
+// Each wave owns 16 rows at a time with the row values in registers (as doubles); the
+// centroids are staged once per block in LDS (row stride DP + 1 to avoid bank conflicts)
+// together with their FP64 squared norms.  Distances ||f||^2 - 2 f.c + ||c||^2 are formed in
+// FP64 (cancellation error ~1e-16 ||f||^2, far below FP32 resolution), the two best are
+// merged across lanes in (distance, index) order, and re-scored in the FP64 direct form so
+// that exact ties still go to the lowest index.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <int DP>
+struct MfmaLds {
+  static constexpr int kStride = DP + 1;
+};
+
+__device__ inline void top2_merge(double& b1, int& i1, double& b2, int& i2, double c1, int j1,
+                                  double c2, int j2) {
+  // merge two sorted (value, index) pairs lists of length two, keep the two smallest
+  auto less = [](double va, int ia, double vb, int ib) { return va < vb || (va == vb && ia < ib); };
+  double o1, o2;
+  int p1, p2;
+  if (less(b1, i1, c1, j1)) {
+    o1 = b1; p1 = i1;
+    if (less(b2, i2, c1, j1)) { o2 = b2; p2 = i2; } else { o2 = c1; p2 = j1; }
+  } else {
+    o1 = c1; p1 = j1;
+    if (less(b1, i1, c2, j2)) { o2 = b1; p2 = i1; } else { o2 = c2; p2 = j2; }
+  }
+  b1 = o1; i1 = p1; b2 = o2; i2 = p2;
+}
+
+template <typename TF, int DP>
+__global__ __launch_bounds__(256) void k_assign_mfma(const TF* F, int64_t ldf, int64_t n, int d,
+                                                     const float* C, int k, int kp,
+                                                     int32_t* labels, float* best_d2,
+                                                     double* obj_part) {
+  extern __shared__ float s_mem[];  // kp * (DP + 1) floats, then kp doubles
+  constexpr int ST = MfmaLds<DP>::kStride;
+  constexpr int NK = DP / 4;  // k-steps of the contraction
+  float* s_c = s_mem;
+  double* s_cn = reinterpret_cast<double*>(s_mem + ((kp * ST + 1) & ~1));
+  for (int t = threadIdx.x; t < kp * ST; t += blockDim.x) {
+    const int c = t / ST, col = t - c * ST;
+    s_c[t] = (c < k && col < d) ? C[static_cast<int64_t>(c) * d + col] : 0.f;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < kp; c += blockDim.x) {
+    double q = 0.0;
+    for (int col = 0; col < DP; ++col) {
+      const double v = static_cast<double>(s_c[c * ST + col]);
+      q += v * v;
+    }
+    s_cn[c] = q;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  double objsum = 0.0;
+  const int64_t tiles = (n + 15) / 16;
+  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * waves + wave; tile < tiles;
+       tile += static_cast<int64_t>(gridDim.x) * waves) {
+    const int64_t row0 = tile * 16;
+    // A operands: row row0 + li, columns lq + 4 i
+    double a[NK];
+    const int64_t arow = row0 + li;
+    const bool avalid = arow < n;
+    double fsq = 0.0;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const int col = lq + 4 * i;
+      const double v = (avalid && col < d) ? static_cast<double>(to_f<TF>(F[arow * ldf + col])) : 0.0;
+      a[i] = v;
+      fsq += v * v;
+    }
+    fsq += __shfl_xor(fsq, 16, 64);
+    fsq += __shfl_xor(fsq, 32, 64);  // ||f||^2 of row row0 + li, in every lane with that li
+    double fn[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fn[r] = __shfl(fsq, 4 * r + lq, 64);  // rows 4 r + lq
+    double b1[4], b2[4];
+    int i1[4], i2[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { b1[r] = INFINITY; b2[r] = INFINITY; i1[r] = 0x7fffffff; i2[r] = 0x7fffffff; }
+    for (int ct = 0; ct < kp / 16; ++ct) {
+      mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      const float* cb = s_c + (ct * 16 + li) * ST + lq;
+#pragma unroll
+      for (int i = 0; i < NK; ++i)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], static_cast<double>(cb[4 * i]), acc, 0, 0, 0);
+      const int cent = ct * 16 + li;
+      const double cn = s_cn[cent];
+      if (cent < k) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double dist = fn[r] - 2.0 * acc[r] + cn;
+          if (dist < b1[r]) { b2[r] = b1[r]; i2[r] = i1[r]; b1[r] = dist; i1[r] = cent; }
+          else if (dist < b2[r]) { b2[r] = dist; i2[r] = cent; }
+        }
+      }
+    }
+    // merge the per-lane top-2 over the 16 lanes that share lq (one centroid column each)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const double c1 = __shfl_xor(b1[r], off, 64);
+        const int j1 = __shfl_xor(i1[r], off, 64);
+        const double c2 = __shfl_xor(b2[r], off, 64);
+        const int j2 = __shfl_xor(i2[r], off, 64);
+        top2_merge(b1[r], i1[r], b2[r], i2[r], c1, j1, c2, j2);
+      }
+    }
+    // FP64 direct re-score of the two candidates when their expanded-form distances are
+    // within a guard far above the expanded form's rounding (~1e-16 (||f||^2 + ||c||^2)), so
+    // that exact ties still go to the lowest index; lanes li split the row's columns.
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 4 * r + lq;
+      const bool valid = row < n;
+      const int c1 = i1[r];
+      const bool has2 = i2[r] < k;
+      const int c2 = has2 ? i2[r] : c1;
+      int lab = c1;
+      double best = b1[r];
+      const bool close = has2 && (b2[r] - b1[r]) <= 1e-10 * (fn[r] + fabs(b2[r]) + s_cn[c2]);
+      if (close) {
+        double e1 = 0.0, e2 = 0.0;
+        for (int col = li; col < d; col += 16) {
+          const double fv = valid ? static_cast<double>(to_f<TF>(F[row * ldf + col])) : 0.0;
+          const double t1 = fv - static_cast<double>(s_c[c1 * ST + col]);
+          const double t2 = fv - static_cast<double>(s_c[c2 * ST + col]);
+          e1 += t1 * t1;
+          e2 += t2 * t2;
+        }
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          e1 += __shfl_xor(e1, off, 16);
+          e2 += __shfl_xor(e2, off, 16);
+        }
+        best = e1;
+        if (e2 < e1 || (e2 == e1 && c2 < c1)) { lab = c2; best = e2; }
+      } else {
+        best = fmax(best, 0.0);
+      }
+      if (valid && li == 0) {
+        labels[row] = lab;
+        if (best_d2) best_d2[row] = static_cast<float>(best);
+        objsum += best;
+      }
+    }
+  }
+  if (obj_part) {
+    const double sm = block_sum(objsum);
+    if (threadIdx.x == 0) obj_part[blockIdx.x] = sm;
+  }
+}
+
 // Cp[c][col] = C[c][col] for c < k and col < d, zero elsewhere (kp x dp).
 __global__ void k_pad_centroids(const float* C, int k, int d, int kp, int dp, float* Cp) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -440,7 +600,7 @@ KmLayout km_layout(int64_t n, int d, int k) {
   L.off_sums = off; off += align_up(static_cast<size_t>(k) * d * 8);
   L.off_cnt = off; off += align_up(static_cast<size_t>(k) * 4);
   L.off_max = off; off += 256;
-  L.off_obj = off; off += align_up(static_cast<size_t>(blocks) * 8);
+  L.off_obj = off; off += align_up(static_cast<size_t>(std::max<int64_t>(blocks, 2048)) * 8);
   L.off_objv = off; off += align_up(static_cast<size_t>(1024 + 1) * 8);
   L.off_sel = off; off += 256;
   L.off_cp = off; off += align_up(static_cast<size_t>(padded_k(k)) * padded_d(d) * 4);
@@ -500,9 +660,48 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
 
 size_t kmeans_workspace(int64_t n, int d, int k) { return km_layout(n, d, k).total; }
 
+// LDS bytes of the MFMA assignment for (k, d), or 0 when it does not apply.
+size_t mfma_lds_bytes(int k, int d, int* dp_out) {
+  int dp = 16;
+  while (dp < d) dp <<= 1;
+  if (dp > 256) return 0;
+  const int kp = (k + 15) / 16 * 16;
+  const size_t bytes = static_cast<size_t>((kp * (dp + 1) + 1) & ~1) * 4 + static_cast<size_t>(kp) * 8;
+  if (bytes > 48 * 1024) return 0;
+  *dp_out = dp;
+  return bytes;
+}
+
+int64_t mfma_blocks(int64_t n) {
+  const int64_t tiles = (n + 15) / 16;
+  return std::max<int64_t>(1, std::min<int64_t>(2048, (tiles + 3) / 4));
+}
+
 static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                               const float* C, int k, int32_t* labels, float* best_d2,
                               double* obj_part, float* Cp, hipStream_t s) {
+  int dp2 = 0;
+  const size_t mlds = mfma_lds_bytes(k, d, &dp2);
+  if (mlds) {
+    const unsigned blocks = static_cast<unsigned>(mfma_blocks(n));
+    const int kp = (k + 15) / 16 * 16;
+#define CSC_MF(TF, DPV)                                                                           \
+  hipLaunchKernelGGL((k_assign_mfma<TF, DPV>), dim3(blocks), dim3(256), mlds, s,                  \
+                     static_cast<const TF*>(F), ldf, n, d, C, k, kp, labels, best_d2, obj_part)
+#define CSC_MF_DP(TF)                        \
+  switch (dp2) {                             \
+    case 16: CSC_MF(TF, 16); break;          \
+    case 32: CSC_MF(TF, 32); break;          \
+    case 64: CSC_MF(TF, 64); break;          \
+    case 128: CSC_MF(TF, 128); break;        \
+    default: CSC_MF(TF, 256); break;         \
+  }
+    if (f_dt == CSC_F32) { CSC_MF_DP(float) } else { CSC_MF_DP(uint16_t) }
+#undef CSC_MF_DP
+#undef CSC_MF
+    CSC_HIP(hipGetLastError());
+    return CSC_OK;
+  }
   const bool vec = rows_aligned(F, f_dt, ldf);
   const unsigned blocks = static_cast<unsigned>(assign_blocks(n));
   const int dp = padded_d(d);
@@ -622,7 +821,8 @@ csc_status run_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
       hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
                          static_cast<const uint16_t*>(F), ldf, n, d, mx);
   }
-  const int64_t nparts = assign_blocks(n);
+  int dp2 = 0;
+  const int64_t nparts = mfma_lds_bytes(k, d, &dp2) ? mfma_blocks(n) : assign_blocks(n);
   for (int it = 0; it <= iters; ++it) {
     CSC_TRY(assign_impl(F, f_dt, ldf, n, d, C, k, labels, nullptr, objective ? obj : nullptr,
                         reinterpret_cast<float*>(base + L.off_cp), s));

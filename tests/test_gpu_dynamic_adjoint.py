@@ -108,3 +108,23 @@ def test_lmax_estimate_is_upper_bound(csc):
     est = G.lmax(100)
     say(f"  lmax est {est:.6f} true {lam[-1]:.6f}")
     assert lam[-1] * 0.999 <= est <= 2.0
+
+
+@pytest.mark.parametrize("batch,use_graph", [(1, True), (3, False), (4, True)])
+def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph):
+    say(f"batched dynamic batch={batch} graph={use_graph}")
+    k, m, d, seed = 4, 40, 32, 62
+    ref = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1)
+    G_ref = [csc.Graph.from_workload(g) for g in seq]
+    ref_out = [ref.step(G) for G in G_ref]
+    ref_theta = ref.features()
+    bat = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1,
+                         batch=batch, use_graph=use_graph)
+    G_bat = [csc.Graph.from_workload(g) for g in seq]
+    labels, lams, refs, cnts = bat.steps(G_bat)
+    for t in range(len(seq)):
+        assert lams[t] == ref_out[t][1]
+        assert refs[t] == ref_out[t][2]
+        assert cnts[t] == ref_out[t][3]
+        assert torch.equal(labels[t], ref_out[t][0])
+    assert torch.equal(bat.features(), ref_theta)
