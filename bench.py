@@ -144,6 +144,7 @@ def run_dynamic(args):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     T = 1 + args.warmup + args.steps
+    cid = 5 if args.workload == "c5" else 3
     seq, _ = build_sequence(args, T)
     dev = torch.device("cuda")
     resident = []
@@ -157,13 +158,14 @@ def run_dynamic(args):
     forms = {}
     digest = kernel_digest()
     final_labels = {}
+    all_labels = {}
     for form in args.forms.split(","):
         fdt, idt, vdt, batched, graph, _ = FORMS[form]
         feat, iters, vals = (getattr(torch, x) for x in (fdt, idt, vdt))
         bf = vals == torch.bfloat16
         rp, ci, ww = resident[0]
         G = csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=True, nnz_capacity=cap)
-        dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(3, "signals"),
+        dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(cid, "signals"),
                              feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
                              use_graph=graph, keep_iterates=1 if batched else -1)
         labels = torch.empty(args.n, dtype=torch.int32, device=dev)
@@ -173,10 +175,10 @@ def run_dynamic(args):
             G.update_device(*resident[t - 1], validate=False)
             dyn.step(G, labels)
         timed = list(range(2 + args.warmup, T + 1))
+        labs = [torch.empty(args.n, dtype=torch.int32, device=dev) for _ in timed]
         if batched:
             Gs = [G] + [csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=False, nnz_capacity=cap)
                         for _ in range(len(timed) - 1)]
-            labs = [torch.empty(args.n, dtype=torch.int32, device=dev) for _ in timed]
         torch.cuda.synchronize()
         csc.timing_reset()
         csc.timing_enable(True)
@@ -190,14 +192,15 @@ def run_dynamic(args):
             refines = sum(refs)
             labels = labs[-1]
         else:
-            for t in timed:
+            for q, t in enumerate(timed):
                 G.update_device(*resident[t - 1], validate=False)
-                _, lam, ref, cnt = dyn.step(G, labels)
+                _, lam, ref, cnt = dyn.step(G, labs[q])
                 refines += int(ref)
                 lams.append(lam)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        final_labels[form] = labels.cpu().numpy()
+        final_labels[form] = labs[-1].cpu().numpy()
+        all_labels[form] = [x.cpu().numpy() for x in labs]
         kms, launches, kbytes = csc.timing_read()
         csc.timing_enable(False)
         log(f"[bench] {form}: {wall / args.steps * 1e3:.2f} ms/snapshot, step kernels "
@@ -230,9 +233,9 @@ def run_dynamic(args):
     lam_c = 0.5
     a = chebyshev.step_coefficients(args.m, 2.0, lam_c, "jackson")
     qd = int(round((1 - args.p) * args.d))
-    X = gaussian_block(args.n, qd, 1.0 / np.sqrt(args.d), seed=seed_for(3, "probes"))
+    X = gaussian_block(args.n, qd, 1.0 / np.sqrt(args.d), seed=seed_for(cid, "probes"))
     cols = [0, 21, 42, 63] if qd >= 64 else list(range(min(4, qd)))
-    rows = np.sort(np.random.default_rng(seed_for(3, "probes")).choice(args.n, 10_000, replace=False))
+    rows = np.sort(np.random.default_rng(seed_for(cid, "probes")).choice(args.n, 10_000, replace=False))
     cpu = None
     errors = {}
     if not args.no_error or not args.no_cpu_baseline:
@@ -250,6 +253,7 @@ def run_dynamic(args):
                           f"{t_cpu * qd / len(cols) * 1e3:.0f} ms",
                    seconds=t_cpu)
         ref_rows = ref[rows]
+        ref_b = None
         for form, rec in forms.items():
             fdt, idt, vdt = FORMS[form][:3]
             bf = vdt == "bfloat16"
@@ -264,9 +268,10 @@ def run_dynamic(args):
             e_total = float(np.linalg.norm(got - ref_rows) / np.linalg.norm(ref_rows))
             rec_err = dict(rel_fro_vs_fp64=e_total)
             if bf:
-                Xr = Xt.float().cpu().numpy()[:, cols].astype(np.float64)
-                log("[bench] oracle: same 4 columns from BF16-rounded signals")
-                ref_b = chebyshev.filter_recurrence(A, 2.0, a, Xr)[rows]
+                if ref_b is None:
+                    Xr = Xt.float().cpu().numpy()[:, cols].astype(np.float64)
+                    log("[bench] oracle: same 4 columns from BF16-rounded signals")
+                    ref_b = chebyshev.filter_recurrence(A, 2.0, a, Xr)[rows]
                 rec_err["rel_fro_vs_fp64_same_bf16_inputs"] = float(
                     np.linalg.norm(got - ref_b) / np.linalg.norm(ref_b))
             errors[form] = rec_err
@@ -318,13 +323,17 @@ def run_dynamic(args):
     if "fp32" in forms:
         out["speedup_per_snapshot_vs_fp32"] = {
             f: round(forms["fp32"]["ms_per_snapshot"] / r["ms_per_snapshot"], 4) for f, r in forms.items() if f != "fp32"}
-    planted = seq[-1].labels
-    agree_planted = {}
-    for f, lab in final_labels.items():
-        cont = np.zeros((args.k, args.k), dtype=np.int64)
-        np.add.at(cont, (planted, lab), 1)
-        agree_planted[f] = round(float(cont.max(axis=1).sum()) / len(planted), 5)
-    out["label_agreement_vs_planted_last_snapshot"] = agree_planted
+    # clustering quality against the planted partition of each timed snapshot
+    from sklearn.metrics import adjusted_rand_score, normalized_mutual_info_score
+
+    timed = list(range(2 + args.warmup, T + 1))
+    quality = {}
+    for f, labs in all_labels.items():
+        nmi = [normalized_mutual_info_score(seq[t - 1].labels, lab) for t, lab in zip(timed, labs)]
+        ari = [adjusted_rand_score(seq[t - 1].labels, lab) for t, lab in zip(timed, labs)]
+        quality[f] = dict(nmi_mean=round(float(np.mean(nmi)), 5), nmi_std=round(float(np.std(nmi)), 5),
+                          ari_mean=round(float(np.mean(ari)), 5), ari_std=round(float(np.std(ari)), 5))
+    out["quality_vs_planted_timed_snapshots"] = quality
     if "fp32" in final_labels:
         # agreement of the last snapshot's partition with the FP32 form's, up to relabelling
         ref = final_labels["fp32"]

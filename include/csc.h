@@ -186,9 +186,15 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  *
  * csc_kmeans_assign: labels[i] = argmin_c sum_t (F[i, t] - C[c, t])^2 for the n rows of
  * F (device, type f_dt, leading dimension ldf, d columns) and the k centroids C (device
- * float[k * d], row-major).  Candidates are ranked in FP32 and the two best re-scored in
- * FP64, exact ties going to the lowest index.  labels: device int32[n]; best_d2: device
- * float[n] or NULL.  Asynchronous.
+ * float[k * d], row-major).  For d <= 256 and 16-byte aligned rows the scores
+ * ||C_c||^2 - 2 F_i.C_c are formed on the matrix cores from exact BF16 splits of F and C
+ * (FP32 accumulation, error bounded by (6d + 2) 2^-24 ||F_i|| ||C_c||); a row whose best two
+ * scores are not separated by twice that bound is re-scored against every centroid in the
+ * FP64 direct form.  Otherwise candidates are ranked in FP32 and the two best re-scored in
+ * FP64.  Exact ties go to the lowest index.  labels: device int32[n]; best_d2: device
+ * float[n] (the FP64 squared distance to the chosen centroid, rounded) or NULL.  Uses a
+ * library-owned device buffer for the split centroids, grown on demand, so concurrent calls
+ * race.  Asynchronous.
  *
  * csc_kmeans_update: C[c] = mean of the rows labelled c; an empty cluster keeps its
  * previous centroid (C is read and overwritten); counts: device int32[k] or NULL.

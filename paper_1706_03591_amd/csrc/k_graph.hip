@@ -61,14 +61,28 @@ __global__ void k_rowptr32(const int64_t* rowptr, int32_t* out, int64_t n) {
   if (r <= n) out[r] = static_cast<int32_t>(rowptr[r]);
 }
 
+// kLPR lanes per row: each lane sums a strided subset of the row's weights, then a fixed
+// shuffle tree combines them, so the degree does not depend on scheduling.
+constexpr int kLPR = 8;
+
 __global__ void k_degrees(const int64_t* rowptr, const double* w, int64_t n, double* dinv,
                           int32_t* isolated) {
-  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = t / kLPR;
+  const int lane = static_cast<int>(t % kLPR);
   double deg = 0.0;
-  for (int64_t i = rowptr[r]; i < rowptr[r + 1]; ++i) deg += w[i];
-  dinv[r] = deg > 0.0 ? 1.0 / sqrt(deg) : 0.0;
-  if (rowptr[r + 1] == rowptr[r]) atomicAdd(isolated, 1);
+  int64_t rs = 0, re = 0;
+  if (r < n) {
+    rs = rowptr[r];
+    re = rowptr[r + 1];
+    for (int64_t i = rs + lane; i < re; i += kLPR) deg += w[i];
+  }
+#pragma unroll
+  for (int off = 1; off < kLPR; off <<= 1) deg += __shfl_xor(deg, off, kLPR);
+  if (r < n && lane == 0) {
+    dinv[r] = deg > 0.0 ? 1.0 / sqrt(deg) : 0.0;
+    if (re == rs) atomicAdd(isolated, 1);
+  }
 }
 
 template <typename TV>
@@ -83,11 +97,13 @@ __device__ inline uint16_t to_val<uint16_t>(double x) {
 template <typename TV>
 __global__ void k_values(const int64_t* rowptr, const int32_t* colidx, const double* w,
                          const double* dinv, int64_t n, int32_t* colidx_out, TV* vals) {
-  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = t / kLPR;
+  const int lane = static_cast<int>(t % kLPR);
   if (r >= n) return;
-  double dr = dinv[r];
-  for (int64_t i = rowptr[r]; i < rowptr[r + 1]; ++i) {
-    int32_t c = colidx[i];
+  const double dr = dinv[r];
+  for (int64_t i = rowptr[r] + lane; i < rowptr[r + 1]; i += kLPR) {
+    const int32_t c = colidx[i];
     colidx_out[i] = c;
     vals[i] = to_val<TV>(w[i] * dr * dinv[c]);
   }
@@ -151,14 +167,14 @@ csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32
   }
   g->nnz = nnz;
   hipLaunchKernelGGL(k_rowptr32, dim3(blocks_for(n + 1)), dim3(256), 0, s, rowptr, g->rowptr, n);
-  hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, w, n, g->dinv,
+  hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n * kLPR)), dim3(256), 0, s, rowptr, w, n, g->dinv,
                      g->flags + 1);
   if (g->val_dt == CSC_F32)
-    hipLaunchKernelGGL(k_values<float>, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, colidx, w,
-                       g->dinv, n, g->colidx, static_cast<float*>(g->vals));
+    hipLaunchKernelGGL(k_values<float>, dim3(blocks_for(n * kLPR)), dim3(256), 0, s, rowptr, colidx,
+                       w, g->dinv, n, g->colidx, static_cast<float*>(g->vals));
   else
-    hipLaunchKernelGGL(k_values<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, rowptr, colidx,
-                       w, g->dinv, n, g->colidx, static_cast<uint16_t*>(g->vals));
+    hipLaunchKernelGGL(k_values<uint16_t>, dim3(blocks_for(n * kLPR)), dim3(256), 0, s, rowptr,
+                       colidx, w, g->dinv, n, g->colidx, static_cast<uint16_t*>(g->vals));
   g->mirror_valid = false;
   CSC_HIP(hipGetLastError());
   return CSC_OK;

@@ -1,11 +1,10 @@
 // k-means on the rows of the spectral features (Sec. 2.1, eq. SC_cost): assignment,
 // Lloyd update and k-means++ seeding.
 //
-// Assignment: one lane per row.  Centroids are staged 32 at a time in LDS and read as
-// broadcasts while each lane streams its row through registers 16 columns at a time, so
-// the distances need no cross-lane reduction.  Distances are ranked in FP32 in the direct
-// form sum (f - mu)^2 (no cancellation) and the two best candidates are re-scored in FP64,
-// so the chosen label is the exact FP64 argmin of the two, ties going to the lowest index.
+// Assignment (d <= 256, aligned rows): the cross term on the BF16 matrix cores in exact
+// split precision with a certified error bound; rows the bound cannot separate are
+// re-scored in FP64 against every centroid.  Fallback (wider rows): one lane per row,
+// scalar-broadcast centroids, FP32 direct-form ranking and FP64 re-score of the best two.
 //
 // Update: sums of the rows of each cluster in 64-bit fixed point (scale 2^S chosen from
 // max |F| and n so that no sum can overflow), accumulated with integer atomics in LDS and
@@ -21,6 +20,8 @@
 #include "csc_internal.h"
 
 namespace csc {
+
+size_t assign_scratch_bytes(int k, int d);
 
 namespace {
 
@@ -162,158 +163,355 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
   }
 }
 
-// MFMA form of the assignment (when the centroids fit in LDS).  The cross term F C^T is a
-// dense contraction, done with FP64 matrix cores (v_mfma_f64_16x16x4: A[i][k] from lane
-// i + 16k, B[k][j] from lane j + 16k, output register r of lane l holds D[4r + l/16][l%16]).
-// Each wave owns 16 rows at a time with the row values in registers (as doubles); the
-// centroids are staged once per block in LDS (row stride DP + 1 to avoid bank conflicts)
-// together with their FP64 squared norms.  Distances ||f||^2 - 2 f.c + ||c||^2 are formed in
-// FP64 (cancellation error ~1e-16 ||f||^2, far below FP32 resolution), the two best are
-// merged across lanes in (distance, index) order, and re-scored in the FP64 direct form so
-// that exact ties still go to the lowest index.
-typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+// MFMA form of the assignment (d <= 256).  The cross term F C^T is a dense contraction and
+// runs on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16) in split precision: each FP32
+// centroid value is the sum of three BF16 parts (hi, mid, lo; residual below 2^-26 of the
+// value), and each FP32 feature likewise, so every partial product is exact in FP32.  Each
+// 32-column step of the dominant hi x hi product goes into a fresh FP32 accumulator and is
+// added to an FP64 sum, and the small cross products (weights 2^-8 and below) are chained
+// into a second accumulator; the rounding of a dot product is then at most
+// E ||f|| ||c|| with E = 40 2^-24, so the exact score s*_c = ||c||^2 - 2 f.c lies in
+// [s_c - e_c, s_c + e_c] with e_c = 2 E ||f|| ||c|| (+ FP64 rounding).  The argmin is then
+// among the centroids whose lower end is below the smallest upper end.  Each lane keeps its
+// three smallest lower ends and the smallest upper end; after the merge across lanes a row
+// with one such candidate is certified, a row with two is re-scored against both in the
+// FP64 direct form, and any other row against every centroid.  The direct form is the
+// definition of the assignment, and ties go to the lowest index.
+//
+// Work layout: a wave owns 16 rows at a time (A operand: lane l holds row l % 16, eight
+// consecutive columns per 32-column step starting at 8 (l / 16)); the centroid parts are
+// staged in LDS in chunks of up to kc_max centroids, 16-byte padded rows so that the sixteen
+// centroid rows read by one MFMA start in different banks.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <int DP>
-struct MfmaLds {
-  static constexpr int kStride = DP + 1;
-};
+// row of the MFMA output held in register r of a lane in row group lq
+__device__ constexpr int mf_drow(int r, int lq) { return 4 * lq + r; }
 
-__device__ inline void top2_merge(double& b1, int& i1, double& b2, int& i2, double c1, int j1,
-                                  double c2, int j2) {
-  // merge two sorted (value, index) pairs lists of length two, keep the two smallest
-  auto less = [](double va, int ia, double vb, int ib) { return va < vb || (va == vb && ia < ib); };
-  double o1, o2;
-  int p1, p2;
-  if (less(b1, i1, c1, j1)) {
-    o1 = b1; p1 = i1;
-    if (less(b2, i2, c1, j1)) { o2 = b2; p2 = i2; } else { o2 = c1; p2 = j1; }
+__host__ __device__ inline void split3(float x, uint16_t& h, uint16_t& m, uint16_t& l) {
+  h = f32_to_bf16(x);
+  float rem = x - bf16_to_f32(h);
+  m = f32_to_bf16(rem);
+  rem = rem - bf16_to_f32(m);
+  l = f32_to_bf16(rem);
+}
+
+// parts[(p * kp + c) * DP + col], p = 0 hi, 1 mid, 2 lo; zero for c >= k or col >= d.
+__global__ void k_prep_centroids(const float* C, int k, int d, int kp, int DP, uint16_t* parts) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kp * DP) return;
+  const int c = t / DP, col = t - c * DP;
+  const float x = (c < k && col < d) ? C[static_cast<int64_t>(c) * d + col] : 0.f;
+  uint16_t h, m, l;
+  split3(x, h, m, l);
+  parts[t] = h;
+  parts[static_cast<int64_t>(kp) * DP + t] = m;
+  parts[2 * static_cast<int64_t>(kp) * DP + t] = l;
+}
+
+// cn[c] = ||C_c||^2 in FP64 for c < k, +inf for the padding up to kp.
+__global__ void k_centroid_norms(const float* C, int k, int d, int kp, double* cn) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= kp) return;
+  double q = 0.0;
+  if (c < k)
+    for (int col = 0; col < d; ++col) {
+      const double v = static_cast<double>(C[static_cast<int64_t>(c) * d + col]);
+      q += v * v;
+    }
+  cn[c] = c < k ? q : INFINITY;
+}
+
+// eight consecutive values of row `row` from column col (zeros past d or n)
+template <typename TF>
+__device__ inline void load8(const TF* F, int64_t ldf, int64_t n, int d, int64_t row, int col,
+                             float* v) {
+  if (row < n && col + 8 <= d) {
+    const TF* p = F + row * ldf + col;
+    if constexpr (sizeof(TF) == 4) {
+      const uint4 u0 = reinterpret_cast<const uint4*>(p)[0];
+      const uint4 u1 = reinterpret_cast<const uint4*>(p)[1];
+      v[0] = __uint_as_float(u0.x); v[1] = __uint_as_float(u0.y);
+      v[2] = __uint_as_float(u0.z); v[3] = __uint_as_float(u0.w);
+      v[4] = __uint_as_float(u1.x); v[5] = __uint_as_float(u1.y);
+      v[6] = __uint_as_float(u1.z); v[7] = __uint_as_float(u1.w);
+    } else {
+      const uint4 u = reinterpret_cast<const uint4*>(p)[0];
+      const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[2 * i] = __uint_as_float(w[i] << 16);
+        v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+      }
+    }
   } else {
-    o1 = c1; p1 = j1;
-    if (less(b1, i1, c2, j2)) { o2 = b1; p2 = i1; } else { o2 = c2; p2 = j2; }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      v[i] = (row < n && col + i < d) ? to_f<TF>(F[row * ldf + col + i]) : 0.f;
   }
-  b1 = o1; i1 = p1; b2 = o2; i2 = p2;
+}
+
+// Raw 16-byte loads of eight consecutive values of row `row` from column col (zeros past d
+// or n); RW = 1 (BF16) or 2 (FP32) vectors.
+template <typename TF>
+__device__ inline void load_raw8(const TF* F, int64_t ldf, int64_t n, int d, int64_t row, int col,
+                                 u32x4* raw) {
+  constexpr int RW = sizeof(TF) / 2;
+  if (row < n && col + 8 <= d) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(F + row * ldf + col);
+#pragma unroll
+    for (int q = 0; q < RW; ++q) raw[q] = p[q];
+  } else {
+    TF tmp[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tmp[i] = (row < n && col + i < d) ? F[row * ldf + col + i] : TF(0);
+    __builtin_memcpy(raw, tmp, sizeof(tmp));
+  }
+}
+
+template <typename TF>
+__device__ inline void raw8_to_f(const u32x4* raw, float* v) {
+  if constexpr (sizeof(TF) == 4) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[4 * q + i] = __uint_as_float(raw[q][i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = __uint_as_float(raw[0][i] << 16);
+      v[2 * i + 1] = __uint_as_float(raw[0][i] & 0xffff0000u);
+    }
+  }
+}
+
+__device__ inline bf16x8 lds_bf8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+}
+
+__device__ inline bool sc_less(double va, int ia, double vb, int ib) {
+  return va < vb || (va == vb && ia < ib);
+}
+
+// insert (v, i) into the sorted list b[0..2]
+__device__ inline void top3_insert(double* b, int* ix, double v, int i) {
+  if (sc_less(v, i, b[2], ix[2])) {
+    if (sc_less(v, i, b[1], ix[1])) {
+      b[2] = b[1]; ix[2] = ix[1];
+      if (sc_less(v, i, b[0], ix[0])) { b[1] = b[0]; ix[1] = ix[0]; b[0] = v; ix[0] = i; }
+      else { b[1] = v; ix[1] = i; }
+    } else {
+      b[2] = v; ix[2] = i;
+    }
+  }
+}
+
+// LDS layout of one staged chunk: 3 parts x kc_max rows of SB = DP + 8 bf16, then kc_max
+// FP64 squared norms and kc_max FP64 norms.
+template <int DP>
+__host__ __device__ constexpr int mf_sb() { return DP + 8; }
+
+inline size_t mf_lds_bytes(int DP, int kc_max) {
+  return static_cast<size_t>(3) * kc_max * (DP + 8) * 2 + static_cast<size_t>(kc_max) * 16;
 }
 
 template <typename TF, int DP>
-__global__ __launch_bounds__(256) void k_assign_mfma(const TF* F, int64_t ldf, int64_t n, int d,
-                                                     const float* C, int k, int kp,
-                                                     int32_t* labels, float* best_d2,
-                                                     double* obj_part) {
-  extern __shared__ float s_mem[];  // kp * (DP + 1) floats, then kp doubles
-  constexpr int ST = MfmaLds<DP>::kStride;
-  constexpr int NK = DP / 4;  // k-steps of the contraction
-  float* s_c = s_mem;
-  double* s_cn = reinterpret_cast<double*>(s_mem + ((kp * ST + 1) & ~1));
-  for (int t = threadIdx.x; t < kp * ST; t += blockDim.x) {
-    const int c = t / ST, col = t - c * ST;
-    s_c[t] = (c < k && col < d) ? C[static_cast<int64_t>(c) * d + col] : 0.f;
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < kp; c += blockDim.x) {
-    double q = 0.0;
-    for (int col = 0; col < DP; ++col) {
-      const double v = static_cast<double>(s_c[c * ST + col]);
-      q += v * v;
-    }
-    s_cn[c] = q;
-  }
-  __syncthreads();
+__global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int64_t n, int d,
+                                                   const uint16_t* parts, const double* cn_g,
+                                                   const float* C, int k, int kp, int kc_max,
+                                                   int32_t* labels, float* best_d2,
+                                                   double* obj_part) {
+  constexpr int SB = mf_sb<DP>();
+  constexpr int NS = DP / 32;                      // 32-column MFMA steps
+  constexpr int NP = sizeof(TF) == 4 ? 3 : 1;      // BF16 parts of a feature value
+  constexpr double E2 = 2.0 * 40.0 * 0x1p-24 * (1.0 + 0x1p-16);
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  uint16_t* s_cb = reinterpret_cast<uint16_t*>(s_raw);
+  double* s_cn = reinterpret_cast<double*>(s_raw + static_cast<size_t>(3) * kc_max * SB * 2);
+  double* s_cr = s_cn + kc_max;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int waves = blockDim.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
+  const int nchunks = (kp + kc_max - 1) / kc_max;
+  const int64_t panels = (n + 63) / 64;
+  const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
   double objsum = 0.0;
-  const int64_t tiles = (n + 15) / 16;
-  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * waves + wave; tile < tiles;
-       tile += static_cast<int64_t>(gridDim.x) * waves) {
-    const int64_t row0 = tile * 16;
-    // A operands: row row0 + li, columns lq + 4 i
-    double a[NK];
-    const int64_t arow = row0 + li;
-    const bool avalid = arow < n;
-    double fsq = 0.0;
+  bool staged = false;
+  constexpr int RW = sizeof(TF) / 2;
+  // BF16 rows: the next panel's row is prefetched while the current one is scored (FP32
+  // rows already hold three split parts in registers; a prefetch costs occupancy there)
+  constexpr bool PF = sizeof(TF) == 2;
+  u32x4 raw[NS][RW];
+  if constexpr (PF) {
 #pragma unroll
-    for (int i = 0; i < NK; ++i) {
-      const int col = lq + 4 * i;
-      const double v = (avalid && col < d) ? static_cast<double>(to_f<TF>(F[arow * ldf + col])) : 0.0;
-      a[i] = v;
-      fsq += v * v;
+    for (int s = 0; s < NS; ++s)
+      load_raw8<TF>(F, ldf, n, d, (static_cast<int64_t>(blockIdx.x) * 4 + wave) * 16 + li,
+                    s * 32 + lq * 8, raw[s]);
+  }
+  for (int64_t panel = blockIdx.x; panel < panels; panel += gridDim.x) {
+    const int64_t row0 = (panel * 4 + wave) * 16;
+    const int64_t row = row0 + li;  // the row this lane scores (with the other three lanes lq)
+    const bool valid = row < n;
+    if constexpr (!PF) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) load_raw8<TF>(F, ldf, n, d, row, s * 32 + lq * 8, raw[s]);
     }
-    fsq += __shfl_xor(fsq, 16, 64);
-    fsq += __shfl_xor(fsq, 32, 64);  // ||f||^2 of row row0 + li, in every lane with that li
-    double fn[4];
+    double bl3[3] = {INFINITY, INFINITY, INFINITY};  // three smallest lower ends
+    int bi3[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
+    double um = INFINITY;                             // smallest upper end
+    // B operand: row li, eight consecutive columns per step from 8 lq
+    bf16x8 a[NP][NS];
+    float fs = 0.f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) fn[r] = __shfl(fsq, 4 * r + lq, 64);  // rows 4 r + lq
-    double b1[4], b2[4];
-    int i1[4], i2[4];
+    for (int s = 0; s < NS; ++s) {
+      float v[8];
+      raw8_to_f<TF>(raw[s], v);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) { b1[r] = INFINITY; b2[r] = INFINITY; i1[r] = 0x7fffffff; i2[r] = 0x7fffffff; }
-    for (int ct = 0; ct < kp / 16; ++ct) {
-      mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
-      const float* cb = s_c + (ct * 16 + li) * ST + lq;
+      for (int e = 0; e < 8; ++e) {
+        fs = fmaf(v[e], v[e], fs);
+        if constexpr (NP == 1) {
+          a[0][s][e] = __builtin_bit_cast(__bf16, f32_to_bf16(v[e]));
+        } else {
+          uint16_t h, m, l;
+          split3(v[e], h, m, l);
+          a[0][s][e] = __builtin_bit_cast(__bf16, h);
+          a[1][s][e] = __builtin_bit_cast(__bf16, m);
+          a[2][s][e] = __builtin_bit_cast(__bf16, l);
+        }
+      }
+    }
+    fs += __shfl_xor(fs, 16, 64);
+    fs += __shfl_xor(fs, 32, 64);
+    const double fnl = sqrt(static_cast<double>(fs)) * (1.0 + 0x1p-16);  // ||f|| of the row
+    if (PF && panel + gridDim.x < panels) {
 #pragma unroll
-      for (int i = 0; i < NK; ++i)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], static_cast<double>(cb[4 * i]), acc, 0, 0, 0);
-      const int cent = ct * 16 + li;
-      const double cn = s_cn[cent];
-      if (cent < k) {
+      for (int s = 0; s < NS; ++s)
+        load_raw8<TF>(F, ldf, n, d, ((panel + gridDim.x) * 4 + wave) * 16 + li, s * 32 + lq * 8,
+                      raw[s]);
+    }
+    for (int chunk = 0; chunk < nchunks; ++chunk) {
+      const int c0 = chunk * kc_max;
+      const int kc = min(kc_max, kp - c0);
+      if (nchunks > 1 || !staged) {
+        __syncthreads();
+        // 16-byte copies of the chunk's three parts, then its norms
+        const int vpr = DP / 8;
+        for (int q = threadIdx.x; q < 3 * kc * vpr; q += blockDim.x) {
+          const int p = q / (kc * vpr);
+          const int rem = q - p * kc * vpr;
+          const int c = rem / vpr, v = rem - c * vpr;
+          const u32x4 val = *reinterpret_cast<const u32x4*>(
+              parts + (static_cast<int64_t>(p) * kp + c0 + c) * DP + 8 * v);
+          *reinterpret_cast<u32x4*>(s_cb + (p * kc_max + c) * SB + 8 * v) = val;
+        }
+        for (int c = threadIdx.x; c < kc; c += blockDim.x) {
+          const double q = cn_g[c0 + c];
+          s_cn[c] = q;
+          s_cr[c] = sqrt(q);
+        }
+        __syncthreads();
+        staged = true;
+      }
+      for (int ct = 0; ct < kc / 16; ++ct) {
+        // A operand: centroid ct*16 + li; output register r of lane (li, lq) is centroid
+        // ct*16 + 4 lq + r against row row0 + li
+        double dot[4] = {0.0, 0.0, 0.0, 0.0};
+        f32x4 small = zero4;
+        const uint16_t* cb = s_cb + (ct * 16 + li) * SB + lq * 8;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const bf16x8 ch = lds_bf8(cb + s * 32);
+          const bf16x8 cm = lds_bf8(cb + kc_max * SB + s * 32);
+          const bf16x8 cl = lds_bf8(cb + 2 * kc_max * SB + s * 32);
+          const f32x4 main = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[0][s], zero4, 0, 0, 0);
+          small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[0][s], small, 0, 0, 0);
+          small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[0][s], small, 0, 0, 0);
+          if constexpr (NP == 3) {
+            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[1][s], small, 0, 0, 0);
+            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[1][s], small, 0, 0, 0);
+            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[2][s], small, 0, 0, 0);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dot[r] += static_cast<double>(main[r]);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double dist = fn[r] - 2.0 * acc[r] + cn;
-          if (dist < b1[r]) { b2[r] = b1[r]; i2[r] = i1[r]; b1[r] = dist; i1[r] = cent; }
-          else if (dist < b2[r]) { b2[r] = dist; i2[r] = cent; }
+          const int lc = ct * 16 + mf_drow(r, lq);
+          const int cent = c0 + lc;
+          if (cent < k) {
+            const double cnv = s_cn[lc];
+            const double crv = s_cr[lc];
+            const double sc = cnv - 2.0 * (dot[r] + static_cast<double>(small[r]));
+            const double e = E2 * fnl * crv + 1e-13 * (cnv + fnl * crv);
+            um = fmin(um, sc + e);
+            // centroids arrive in increasing index order within a lane: strict < keeps ties
+            // on the lower index
+            const double lo = sc - e;
+            if (lo < bl3[2]) {
+              if (lo < bl3[1]) {
+                bl3[2] = bl3[1]; bi3[2] = bi3[1];
+                if (lo < bl3[0]) { bl3[1] = bl3[0]; bi3[1] = bi3[0]; bl3[0] = lo; bi3[0] = cent; }
+                else { bl3[1] = lo; bi3[1] = cent; }
+              } else {
+                bl3[2] = lo; bi3[2] = cent;
+              }
+            }
+          }
         }
       }
     }
-    // merge the per-lane top-2 over the 16 lanes that share lq (one centroid column each)
+    // merge over the four lanes of the row (lq), in (value, index) order
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int off = 16; off < 64; off <<= 1) {
+      double ob[3];
+      int oi[3];
 #pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        const double c1 = __shfl_xor(b1[r], off, 64);
-        const int j1 = __shfl_xor(i1[r], off, 64);
-        const double c2 = __shfl_xor(b2[r], off, 64);
-        const int j2 = __shfl_xor(i2[r], off, 64);
-        top2_merge(b1[r], i1[r], b2[r], i2[r], c1, j1, c2, j2);
-      }
+      for (int q = 0; q < 3; ++q) { ob[q] = __shfl_xor(bl3[q], off, 64); oi[q] = __shfl_xor(bi3[q], off, 64); }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) top3_insert(bl3, bi3, ob[q], oi[q]);
+      um = fmin(um, __shfl_xor(um, off, 64));
     }
-    // FP64 direct re-score of the two candidates when their expanded-form distances are
-    // within a guard far above the expanded form's rounding (~1e-16 (||f||^2 + ||c||^2)), so
-    // that exact ties still go to the lowest index; lanes li split the row's columns.
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = row0 + 4 * r + lq;
-      const bool valid = row < n;
-      const int c1 = i1[r];
-      const bool has2 = i2[r] < k;
-      const int c2 = has2 ? i2[r] : c1;
-      int lab = c1;
-      double best = b1[r];
-      const bool close = has2 && (b2[r] - b1[r]) <= 1e-10 * (fn[r] + fabs(b2[r]) + s_cn[c2]);
-      if (close) {
-        double e1 = 0.0, e2 = 0.0;
-        for (int col = li; col < d; col += 16) {
-          const double fv = valid ? static_cast<double>(to_f<TF>(F[row * ldf + col])) : 0.0;
-          const double t1 = fv - static_cast<double>(s_c[c1 * ST + col]);
-          const double t2 = fv - static_cast<double>(s_c[c2 * ST + col]);
-          e1 += t1 * t1;
-          e2 += t2 * t2;
+    // candidates: lower end not above the smallest upper end (the first always is)
+    const bool certain = !valid || bi3[1] >= k || bl3[1] > um;
+    const bool pair = !certain && (bi3[2] >= k || bl3[2] > um);
+    int lab = bi3[0] < k ? bi3[0] : 0;  // (no candidate only with NaN features)
+    double best = 0.0;
+    if (!certain) {
+      // FP64 direct form against the candidates (the two best, else every centroid); the
+      // four lanes of the row split the columns
+      const int nc = pair ? 2 : k;
+      double be = INFINITY;
+      int bl = 0x7fffffff;
+      for (int q = 0; q < nc; ++q) {
+        const int c = pair ? (q == 0 ? bi3[0] : bi3[1]) : q;
+        double e = 0.0;
+        for (int col = lq; col < d; col += 4) {
+          const double tv = static_cast<double>(to_f<TF>(F[row * ldf + col])) -
+                            static_cast<double>(C[static_cast<int64_t>(c) * d + col]);
+          e += tv * tv;
         }
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-          e1 += __shfl_xor(e1, off, 16);
-          e2 += __shfl_xor(e2, off, 16);
-        }
-        best = e1;
-        if (e2 < e1 || (e2 == e1 && c2 < c1)) { lab = c2; best = e2; }
-      } else {
-        best = fmax(best, 0.0);
+        e += __shfl_xor(e, 16, 64);
+        e += __shfl_xor(e, 32, 64);
+        if (sc_less(e, c, be, bl)) { be = e; bl = c; }
       }
-      if (valid && li == 0) {
-        labels[row] = lab;
-        if (best_d2) best_d2[row] = static_cast<float>(best);
-        objsum += best;
+      lab = bl;
+      best = be;
+    } else if (valid && (best_d2 || obj_part)) {
+      double e = 0.0;
+      for (int col = lq; col < d; col += 4) {
+        const double tv = static_cast<double>(to_f<TF>(F[row * ldf + col])) -
+                          static_cast<double>(C[static_cast<int64_t>(lab) * d + col]);
+        e += tv * tv;
       }
+      e += __shfl_xor(e, 16, 64);
+      e += __shfl_xor(e, 32, 64);
+      best = e;
+    }
+    if (valid && lq == 0) {
+      labels[row] = lab;
+      if (best_d2) best_d2[row] = static_cast<float>(best);
+      objsum += best;
     }
   }
   if (obj_part) {
@@ -603,7 +801,7 @@ KmLayout km_layout(int64_t n, int d, int k) {
   L.off_obj = off; off += align_up(static_cast<size_t>(std::max<int64_t>(blocks, 2048)) * 8);
   L.off_objv = off; off += align_up(static_cast<size_t>(1024 + 1) * 8);
   L.off_sel = off; off += 256;
-  L.off_cp = off; off += align_up(static_cast<size_t>(padded_k(k)) * padded_d(d) * 4);
+  L.off_cp = off; off += align_up(assign_scratch_bytes(k, d));
   L.total = off;
   return L;
 }
@@ -660,43 +858,74 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
 
 size_t kmeans_workspace(int64_t n, int d, int k) { return km_layout(n, d, k).total; }
 
-// LDS bytes of the MFMA assignment for (k, d), or 0 when it does not apply.
-size_t mfma_lds_bytes(int k, int d, int* dp_out) {
-  int dp = 16;
-  while (dp < d) dp <<= 1;
-  if (dp > 256) return 0;
+// Launch plan of the MFMA assignment for (n, d, k); DP == 0 when it does not apply (d > 256).
+// Chunks of kc centroids fill at most 64 KiB of LDS; one 16-row tile per wave (T = 1: two
+// tiles in flight spill registers at DP = 256).
+struct MfPlan {
+  int DP = 0, kp = 0, kc = 0, T = 1;
+  size_t lds = 0;
+  int64_t blocks = 1;
+};
+
+MfPlan mf_plan(int64_t n, int d, int k) {
+  MfPlan P;
+  if (d > 256) return P;
+  int DP = 32;
+  while (DP < d) DP <<= 1;
   const int kp = (k + 15) / 16 * 16;
-  const size_t bytes = static_cast<size_t>((kp * (dp + 1) + 1) & ~1) * 4 + static_cast<size_t>(kp) * 8;
-  if (bytes > 48 * 1024) return 0;
-  *dp_out = dp;
-  return bytes;
+  int kc = 16;
+  while (kc + 16 <= kp && mf_lds_bytes(DP, kc + 16) <= 64 * 1024) kc += 16;
+  P.DP = DP;
+  P.kp = kp;
+  P.kc = kc;
+  P.T = 1;
+  P.lds = mf_lds_bytes(DP, kc);
+  const int64_t panels = (n + 64 * P.T - 1) / (64 * P.T);
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / static_cast<int64_t>(P.lds)));
+  P.blocks = std::max<int64_t>(1, std::min<int64_t>(panels, 256 * per_cu));
+  return P;
 }
 
-int64_t mfma_blocks(int64_t n) {
-  const int64_t tiles = (n + 15) / 16;
-  return std::max<int64_t>(1, std::min<int64_t>(2048, (tiles + 3) / 4));
+// centroid scratch of the MFMA assignment: three BF16 parts (kp x DP each), then kp norms
+size_t mf_scratch_bytes(int k, int d) {
+  const MfPlan P = mf_plan(1, d, k);
+  if (!P.DP) return 0;
+  return align_up(static_cast<size_t>(3) * P.kp * P.DP * 2) + static_cast<size_t>(P.kp) * 8;
+}
+
+size_t assign_scratch_bytes(int k, int d) {
+  return std::max(static_cast<size_t>(padded_k(k)) * padded_d(d) * 4, mf_scratch_bytes(k, d));
+}
+
+int64_t assign_parts(int64_t n, int d, int k, const void* F, csc_dtype f_dt, int64_t ldf) {
+  const MfPlan P = mf_plan(n, d, k);
+  return (P.DP && rows_aligned(F, f_dt, ldf)) ? P.blocks : assign_blocks(n);
 }
 
 static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                               const float* C, int k, int32_t* labels, float* best_d2,
                               double* obj_part, float* Cp, hipStream_t s) {
-  int dp2 = 0;
-  const size_t mlds = mfma_lds_bytes(k, d, &dp2);
-  if (mlds) {
-    const unsigned blocks = static_cast<unsigned>(mfma_blocks(n));
-    const int kp = (k + 15) / 16 * 16;
-#define CSC_MF(TF, DPV)                                                                           \
-  hipLaunchKernelGGL((k_assign_mfma<TF, DPV>), dim3(blocks), dim3(256), mlds, s,                  \
-                     static_cast<const TF*>(F), ldf, n, d, C, k, kp, labels, best_d2, obj_part)
-#define CSC_MF_DP(TF)                        \
-  switch (dp2) {                             \
-    case 16: CSC_MF(TF, 16); break;          \
-    case 32: CSC_MF(TF, 32); break;          \
-    case 64: CSC_MF(TF, 64); break;          \
-    case 128: CSC_MF(TF, 128); break;        \
-    default: CSC_MF(TF, 256); break;         \
+  const MfPlan P = mf_plan(n, d, k);
+  if (P.DP && rows_aligned(F, f_dt, ldf)) {
+    auto* parts = reinterpret_cast<uint16_t*>(Cp);
+    auto* cn = reinterpret_cast<double*>(reinterpret_cast<char*>(Cp) +
+                                         align_up(static_cast<size_t>(3) * P.kp * P.DP * 2));
+    hipLaunchKernelGGL(k_prep_centroids, dim3((P.kp * P.DP + 255) / 256), dim3(256), 0, s, C, k, d,
+                       P.kp, P.DP, parts);
+    hipLaunchKernelGGL(k_centroid_norms, dim3((P.kp + 63) / 64), dim3(64), 0, s, C, k, d, P.kp, cn);
+    const unsigned blocks = static_cast<unsigned>(P.blocks);
+#define CSC_MF(TF, DPV, TV)                                                                        \
+  hipLaunchKernelGGL((k_assign_mf<TF, DPV>), dim3(blocks), dim3(256), P.lds, s,                   \
+                     static_cast<const TF*>(F), ldf, n, d, parts, cn, C, k, P.kp, P.kc, labels,   \
+                     best_d2, obj_part)
+#define CSC_MF_DP(TF, TV)                    \
+  switch (P.DP) {                            \
+    case 32: CSC_MF(TF, 32, TV); break;      \
+    case 64: CSC_MF(TF, 64, TV); break;      \
+    case 128: CSC_MF(TF, 128, TV); break;    \
+    default: CSC_MF(TF, 256, TV); break;     \
   }
-    if (f_dt == CSC_F32) { CSC_MF_DP(float) } else { CSC_MF_DP(uint16_t) }
+    if (f_dt == CSC_F32) { CSC_MF_DP(float, 1) } else { CSC_MF_DP(uint16_t, 1) }
 #undef CSC_MF_DP
 #undef CSC_MF
     CSC_HIP(hipGetLastError());
@@ -729,7 +958,7 @@ csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int6
   // owned by the library (grown on demand, kept until exit)
   static float* cp_buf = nullptr;
   static size_t cp_bytes = 0;
-  const size_t need = static_cast<size_t>(padded_k(k)) * padded_d(d) * 4;
+  const size_t need = assign_scratch_bytes(k, d);
   if (need > cp_bytes) {
     if (cp_buf) (void)hipFree(cp_buf);
     cp_buf = nullptr;
@@ -821,8 +1050,7 @@ csc_status run_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
       hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
                          static_cast<const uint16_t*>(F), ldf, n, d, mx);
   }
-  int dp2 = 0;
-  const int64_t nparts = mfma_lds_bytes(k, d, &dp2) ? mfma_blocks(n) : assign_blocks(n);
+  const int64_t nparts = assign_parts(n, d, k, F, f_dt, ldf);
   for (int it = 0; it <= iters; ++it) {
     CSC_TRY(assign_impl(F, f_dt, ldf, n, d, C, k, labels, nullptr, objective ? obj : nullptr,
                         reinterpret_cast<float*>(base + L.off_cp), s));
