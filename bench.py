@@ -37,7 +37,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--k", type=int, default=50)
@@ -51,6 +51,12 @@ def parse():
     ap.add_argument("--headline", default="bf16b")
     ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
     ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3")
+    ap.add_argument("--probe", metavar="FORM",
+                    help="counter probe: snapshot 1 and one batch of FORM's dynamic steps on the "
+                         "C3 sequence, then a plain 1 GiB device copy (run under rocprofv3 --pmc)")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) "
+                         "of --probe FORM into profiles/k_step_c3_traffic.json")
     args = ap.parse_args()
     if args.workload == "c5" and "--n" not in sys.argv:
         args.n, args.k, args.d, args.m, args.p = 8_000_000, 200, 256, 150, 0.75
@@ -132,7 +138,96 @@ def main():
               "across GPUs is described in DESIGN.md but not built); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    if args.traffic:
+        return traffic_summary(args)
+    if args.probe:
+        return run_probe(args)
     {"c3": run_dynamic, "c5": run_dynamic, "c2": run_static, "c4": run_adjoint}[args.workload](args)
+
+
+def run_probe(args):
+    """Snapshot 1 plus one batch of the form's dynamic steps, then a 1 GiB device copy whose
+    counter readings calibrate FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+
+    import paper_1706_03591_amd as csc
+    from workloads import seed_for
+
+    fdt, idt, vdt, batched, graph, _ = FORMS[args.probe]
+    feat, iters, vals = (getattr(torch, x) for x in (fdt, idt, vdt))
+    T = 1 + args.batch
+    seq, _ = build_sequence(args, T)
+    dev = torch.device("cuda")
+    cap = max(g.nnz for g in seq)
+    Gs = [csc.Graph(args.n, *(torch.from_numpy(a).to(dev) for a in (g.rowptr, g.colidx, g.w)),
+                    val_dtype=vals, validate=False, nnz_capacity=cap) for g in seq]
+    dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(3, "signals"),
+                         feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
+                         use_graph=graph, keep_iterates=1 if batched else -1)
+    dyn.step(Gs[0])
+    if batched:
+        dyn.steps(Gs[1:])
+    else:
+        for G in Gs[1:]:
+            dyn.step(G)
+    torch.cuda.synchronize()
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("[bench] probe done")
+
+
+def traffic_summary(args):
+    """HBM bytes per launch of the dominant step kernel: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch, summed over the counter's instances) scaled by what the same counters read for
+    the plain 1 GiB copy of the probe."""
+    import csv
+    import statistics
+
+    form = args.probe or args.headline
+    kname = "k_step_batch"  # the stored-basis step of every form at C3
+
+    def per_dispatch(path, counter):
+        out = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                name, v = out.get(r["Dispatch_Id"], (r["Kernel_Name"], 0.0))
+                out[r["Dispatch_Id"]] = (name, v + float(r["Counter_Value"]))
+        return list(out.values())
+
+    fetch = per_dispatch(args.traffic[0], "FETCH_SIZE")
+    write = per_dispatch(args.traffic[1], "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    # the probe's 1 GiB copy is the largest copy dispatch (the others move labels and CSR)
+    cf = max(v for n, v in fetch if "copyBuffer" in n)
+    cw = max(v for n, v in write if "copyBuffer" in n)
+    sf, sw = gib_kib / cf, gib_kib / cw
+    sel = lambda rows: [v for n, v in rows if kname in n and "<" in n]  # noqa: E731
+    stf, stw = sel(fetch), sel(write)
+    per_launch = (statistics.mean(stf) * sf + statistics.mean(stw) * sw) * 1024.0
+    path = os.path.join(ROOT, "profiles", "k_step_c3_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    digest = kernel_digest()
+    if rec.get("kernel_sha256_16") != digest:
+        rec = {"kernel_sha256_16": digest, "bytes_per_launch": {}, "detail": {}}
+    rec["bytes_per_launch"][form] = per_launch
+    rec["detail"][form] = {
+        "kernel": kname, "launches": len(stf),
+        "fetch_kib_raw_mean": statistics.mean(stf), "write_kib_raw_mean": statistics.mean(stw),
+        "copy_fetch_kib_raw": cf, "copy_write_kib_raw": cw,
+        "scale_fetch": sf, "scale_write": sw,
+    }
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({"form": form, "bytes_per_launch": per_launch, **rec["detail"][form]}))
 
 
 def run_dynamic(args):
@@ -305,7 +400,7 @@ def run_dynamic(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step (fused Chebyshev SpMM + three-term update + accumulate)",
+            "kernel": "k_step_batch (fused Chebyshev SpMM + three-term update, iterates kept for recombination)",
             "achieved": round(achieved, 1),
             "peak": PEAK_GBPS,
             "unit": "GB/s",

@@ -648,36 +648,77 @@ __global__ void k_pp_first(const TF* F, int64_t ldf, int64_t n, int d, const dou
   for (int t = threadIdx.x; t < d; t += blockDim.x) C[t] = to_f<TF>(F[i * ldf + t]);
 }
 
-// d2[i] = min(d2[i], ||f_i - Cj||^2) in FP64 (first round: the distance itself); one lane
-// per row, kRIT rows per thread, so block b covers the contiguous rows
-// [b * kThreads * kRIT, ...); bsum[b] = their sum (fixed reduction order).
-template <typename TF, bool VEC>
+// d2[i] = min(d2[i], ||f_i - Cj||^2) in FP64 (first round: the distance itself).  Block b
+// covers the contiguous rows [b * kThreads * kRIT, ...) and writes their sum to bsum[b].
+// Sixteen lanes share a row so that each load instruction reads whole rows (16-byte pieces
+// of four rows per wave); the lanes' partial sums meet in a fixed shuffle tree.
+template <typename TF, bool VEC, int NPC>
 __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, int64_t n, int d,
                                                       int dp, const float* Cj, int first,
                                                       double* d2, double* bsum) {
+  constexpr int V = 16 / sizeof(TF);  // values per 16-byte piece; a lane reads NPC pieces
+  constexpr int U = VEC ? 8 : 2;      // rows per group in flight
   __shared__ float s_cj[256];
   for (int t = threadIdx.x; t < dp; t += kThreads) s_cj[t] = t < d ? Cj[t] : 0.f;
   __syncthreads();
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kRIT;
+  const int l16 = threadIdx.x & 15;
+  const int grp = threadIdx.x >> 4;  // 16 row groups per block
   double local = 0.0;
-#pragma unroll 1
-  for (int q = 0; q < kRIT; ++q) {
-    const int64_t row = base + q * kThreads + threadIdx.x;
-    if (row >= n) continue;
-    const TF* rowp = F + row * ldf;
-    double s = 0.0;
-    for (int c0 = 0; c0 < dp; c0 += kCH) {
-      float f[kCH];
-      load_chunk<TF, VEC>(rowp, c0, d, f);
+  for (int q0 = 0; q0 < kThreads * kRIT / 16; q0 += U) {
+    uint4 raw[U][NPC];
 #pragma unroll
-      for (int i = 0; i < kCH; ++i) {
-        const double t = static_cast<double>(f[i]) - static_cast<double>(s_cj[c0 + i]);
-        s += t * t;
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = base + (q0 + u) * 16 + grp;
+      const TF* rowp = F + (row < n ? row : 0) * ldf;
+#pragma unroll
+      for (int pc = 0; pc < NPC; ++pc) {
+        const int c0 = (pc * 16 + l16) * V;
+        if (row < n && VEC && c0 + V <= d) {
+          raw[u][pc] = *reinterpret_cast<const uint4*>(rowp + c0);
+        } else {
+          TF tmp[V];
+#pragma unroll
+          for (int i = 0; i < V; ++i) tmp[i] = (row < n && c0 + i < d) ? rowp[c0 + i] : TF(0);
+          __builtin_memcpy(&raw[u][pc], tmp, 16);
+        }
       }
     }
-    const double v = first ? s : fmin(d2[row], s);
-    d2[row] = v;
-    local += v;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = base + (q0 + u) * 16 + grp;
+      double s = 0.0;
+#pragma unroll
+      for (int pc = 0; pc < NPC; ++pc) {
+        const int c0 = (pc * 16 + l16) * V;
+        const uint32_t w[4] = {raw[u][pc].x, raw[u][pc].y, raw[u][pc].z, raw[u][pc].w};
+        float f[V];
+        if constexpr (sizeof(TF) == 4) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(w[i]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            f[2 * i] = __uint_as_float(w[i] << 16);
+            f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          if (c0 + i < d) {
+            const double t = static_cast<double>(f[i]) - static_cast<double>(s_cj[c0 + i]);
+            s += t * t;
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 16);
+      if (row < n && l16 == 0) {
+        const double v = first ? s : fmin(d2[row], s);
+        d2[row] = v;
+        local += v;
+      }
+    }
   }
   const double tot = block_sum(local);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -999,24 +1040,36 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   else
     hipLaunchKernelGGL(k_pp_first<uint16_t>, dim3(1), dim3(256), 0, s,
                        static_cast<const uint16_t*>(F), ldf, n, d, u, C, idx, sel);
-#define CSC_PPD(TF, V)                                                                             \
-  hipLaunchKernelGGL((k_pp_dist<TF, V>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), 0, s, \
-                     static_cast<const TF*>(F), ldf, n, d, dp, Cj, first, d2, bsum)
+  const int npc = (d + (f32 ? 63 : 127)) / (f32 ? 64 : 128);  // 16-byte pieces per lane
+#define CSC_PPD_N(TF, V, NP)                                                                       \
+  hipLaunchKernelGGL((k_pp_dist<TF, V, NP>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), 0, \
+                     s, static_cast<const TF*>(F), ldf, n, d, dp, Cj, first, d2, bsum)
+#define CSC_PPD(TF, V)                               \
+  switch (npc) {                                     \
+    case 1: CSC_PPD_N(TF, V, 1); break;              \
+    case 2: CSC_PPD_N(TF, V, 2); break;              \
+    case 3: CSC_PPD_N(TF, V, 3); break;              \
+    default: CSC_PPD_N(TF, V, 4); break;             \
+  }
+#define CSC_PPD16(V)                                 \
+  if (npc == 1) { CSC_PPD_N(uint16_t, V, 1); } else { CSC_PPD_N(uint16_t, V, 2); }
   for (int j = 1; j < k; ++j) {
     const float* Cj = C + static_cast<int64_t>(j - 1) * d;
     const int first = j == 1 ? 1 : 0;
     if (f32) {
-      if (vec) CSC_PPD(float, true); else CSC_PPD(float, false);
+      if (vec) { CSC_PPD(float, true) } else { CSC_PPD(float, false) }
       hipLaunchKernelGGL(k_pp_pick<float>, dim3(1), dim3(1024), 0, s, static_cast<const float*>(F), ldf,
                          n, d, d2, bsum, nblk, rows_per_blk, u, j, C, idx, sel);
     } else {
-      if (vec) CSC_PPD(uint16_t, true); else CSC_PPD(uint16_t, false);
+      if (vec) { CSC_PPD16(true) } else { CSC_PPD16(false) }
       hipLaunchKernelGGL(k_pp_pick<uint16_t>, dim3(1), dim3(1024), 0, s,
                          static_cast<const uint16_t*>(F), ldf, n, d, d2, bsum, nblk, rows_per_blk, u,
                          j, C, idx, sel);
     }
   }
 #undef CSC_PPD
+#undef CSC_PPD16
+#undef CSC_PPD_N
   CSC_HIP(hipGetLastError());
   return CSC_OK;
 }
