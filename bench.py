@@ -260,9 +260,12 @@ def run_dynamic(args):
         bf = vals == torch.bfloat16
         rp, ci, ww = resident[0]
         G = csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=True, nnz_capacity=cap)
+        # kernel shape of the fresh block's recurrence, timed on snapshot 1
+        qd = int(round((1 - args.p) * args.d))
+        variant = G.autotune(qd, iter_dtype=iters)
         dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(cid, "signals"),
                              feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
-                             use_graph=graph, keep_iterates=1 if batched else -1)
+                             use_graph=graph, keep_iterates=1 if batched else -1, variant=variant)
         labels = torch.empty(args.n, dtype=torch.int32, device=dev)
         _, lam, ref, cnt = dyn.step(G, labels)
         log(f"[bench] {form}: snapshot 1 lambda {lam:.5f} count {cnt:.2f}")
@@ -313,6 +316,7 @@ def run_dynamic(args):
             storage=dict(signals=fdt, features=fdt, values=vdt, iterates=idt, accumulate="float32"),
             batch=args.batch if batched else 1,
             hip_graph=graph,
+            autotuned_variant=variant,
             G=G,
         )
         del dyn
@@ -464,6 +468,7 @@ def run_static(args):
     g = sbm(args.n, args.k, 20.0, 0.1, seed=seed_for(2, "graph"))
     log(f"[bench] C2 graph nnz {g.nnz}")
     G = csc.Graph.from_workload(g)
+    variant = G.autotune(args.d)
     R = torch.from_numpy(gaussian_block(args.n, args.d, 1 / np.sqrt(args.d), seed=seed_for(2, "signals"))).cuda()
     P = torch.from_numpy(gaussian_block(args.n, 24, 1 / np.sqrt(args.d), seed=seed_for(2, "probes"))).cuda()
     Y = torch.empty_like(R)
@@ -491,7 +496,7 @@ def run_static(args):
           "GB/s", wall * 1e3,
           {"config": {"workload": f"static SBM N={args.n}, k={args.k}, degree 20, ratio 0.1; 24 probes, "
                                   f"16 dichotomy steps, d={args.d}, m={args.m}, 20 Lloyd rounds",
-                      "nnz": g.nnz, "lambda": lam, "count": cnt},
+                      "nnz": g.nnz, "lambda": lam, "count": cnt, "autotuned_variant": variant},
            "roofline": {"bound": "hbm", "achieved": round(kbytes / (kms * 1e-3) / 1e9, 1),
                         "peak": PEAK_GBPS, "unit": "GB/s",
                         "frac": round(kbytes / (kms * 1e-3) / 1e9 / PEAK_GBPS, 4),

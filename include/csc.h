@@ -261,6 +261,9 @@ typedef struct {
                          iterates kept (0 or 1 -> one snapshot at a time) */
   int use_graph;      /* non-zero: the recurrence launches are captured once in a HIP graph
                          and replayed for every snapshot (or batch) */
+  int variant;        /* recurrence kernel shape (row group x column tile) for the fresh
+                         block, e.g. the one csc_autotune picked on the first snapshot;
+                         -1: the widest tile not wider than (1 - p) d */
 } csc_dyn_opts;
 
 csc_status csc_dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp,

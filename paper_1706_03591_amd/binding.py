@@ -44,7 +44,8 @@ pdbl, pi64, pint = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_in
 class DynOpts(C.Structure):
     _fields_ = [("lmax", C.c_double), ("tau", C.c_double), ("n_cand", C.c_int),
                 ("lloyd_iters", C.c_int), ("init", C.c_int), ("iter_dt", C.c_int),
-                ("keep_iterates", C.c_int), ("batch", C.c_int), ("use_graph", C.c_int)]
+                ("keep_iterates", C.c_int), ("batch", C.c_int), ("use_graph", C.c_int),
+                ("variant", C.c_int)]
 
 
 _SIGS = {
@@ -435,10 +436,11 @@ class DynamicCSC:
     def __init__(self, n: int, d: int, k: int, p: float, m: int, seed: int,
                  damping: int = DAMP_JACKSON, feat_dtype=torch.float32, iter_dtype=torch.float32,
                  lmax: float = 2.0, tau: float = 0.0, n_cand: int = 16, lloyd_iters: int = 20,
-                 init: int = 0, keep_iterates: int = -1, batch: int = 1, use_graph: bool = False):
+                 init: int = 0, keep_iterates: int = -1, batch: int = 1, use_graph: bool = False,
+                 variant: int = -1):
         opts = DynOpts(lmax=lmax, tau=tau, n_cand=n_cand, lloyd_iters=lloyd_iters, init=init,
                        iter_dt=_TORCH_DT[iter_dtype], keep_iterates=keep_iterates, batch=batch,
-                       use_graph=int(bool(use_graph)))
+                       use_graph=int(bool(use_graph)), variant=int(variant))
         h = C.c_void_p()
         _check(lib.csc_dyn_create(int(n), int(d), int(k), float(p), int(m), int(damping),
                                   _TORCH_DT[feat_dtype], int(seed), C.byref(opts), C.byref(h)))

@@ -112,6 +112,10 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     delete st;
     return fail(CSC_E_ARG, "batch must be in [1, 8]");
   }
+  if (opts && opts->variant >= num_variants()) {
+    delete st;
+    return fail(CSC_E_ARG, "variant must be -1 or in [0, " + std::to_string(num_variants()) + ")");
+  }
   const size_t es = dtype_size(feat_dt);
   st->fwork_bytes = filter_workspace(n, d, st->iter_dt);
   st->kwork_bytes = kmeans_workspace(n, d, k);
@@ -134,7 +138,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   if (keep != 0 && m + 1 <= 512) {
     Graph probe{};
     probe.variant_f32 = probe.variant_bf16 = -1;
-    st->variant = default_variant(&probe, qd, st->iter_dt);
+    st->variant = (opts && opts->variant >= 0) ? opts->variant : default_variant(&probe, qd, st->iter_dt);
     st->basis_bytes = basis_bytes(n, qd, m, st->iter_dt, st->variant);
     st->aux_bytes = basis_aux_bytes(n, m);
     size_t free_b = 0, total_b = 0;

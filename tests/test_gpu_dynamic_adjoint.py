@@ -128,3 +128,34 @@ def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph):
         assert cnts[t] == ref_out[t][3]
         assert torch.equal(labels[t], ref_out[t][0])
     assert torch.equal(bat.features(), ref_theta)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_dynamic_kernel_shape_does_not_change_results(csc, seq, variant):
+    """The row-group x column-tile shape (the autotuner's choice) changes only the order of
+    block partial sums, never the per-element arithmetic of the recurrence."""
+    say(f"dynamic variant={variant}")
+    k, m, d, seed = 4, 40, 32, 62
+    ref = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1)
+    alt = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1,
+                         variant=variant)
+    for g in seq:
+        G1, G2 = csc.Graph.from_workload(g), csc.Graph.from_workload(g)
+        l1, lam1, r1, c1 = ref.step(G1)
+        l2, lam2, r2, c2 = alt.step(G2)
+        assert c2 == pytest.approx(c1, rel=1e-9, abs=1e-9)
+        assert lam2 == lam1 and r2 == r1
+        assert torch.equal(l1, l2)
+    assert torch.equal(ref.features(), alt.features())
+
+
+def test_autotuned_variant_drives_dynamic_state(csc, seq):
+    say("autotune -> dynamic variant")
+    G = csc.Graph.from_workload(seq[0])
+    v = G.autotune(16, torch.float32)
+    assert 0 <= v < 4
+    dyn = csc.DynamicCSC(2000, 32, 4, 0.5, 40, seed=62, lloyd_iters=10, keep_iterates=1, variant=v)
+    lab, lam, _, cnt = dyn.step(G)
+    assert 0.0 < lam < 2.0 and lab.min() >= 0 and lab.max() < 4
+    with pytest.raises(csc.CscError):
+        csc.DynamicCSC(2000, 32, 4, 0.5, 40, seed=62, variant=4)
