@@ -5,9 +5,11 @@ sizes, mean degree 16, inter/intra ratio 0.1; each snapshot rewires 1% of the ed
 moves 0.5% of the nodes; d = 128 signals, Chebyshev degree m = 120, reuse p = 0.5.  A step
 is one dynamic snapshot (Algorithm 1 steps 4-8: operator build, q d = 64 fresh signals,
 filter, eigencount, refinement when needed, k-means with 20 Lloyd rounds), with every
-snapshot's CSR already resident in HBM.  Two storage forms run on the same snapshots:
-FP32 everywhere, and BF16 storage of the signals, features, operator values and recurrence
-iterates with FP32 arithmetic and accumulation (a third form, bf16io, keeps FP32 iterates).
+snapshot's CSR already resident in HBM.  The storage forms (FORMS below) run on the same
+snapshots: FP32 everywhere; BF16 signals/features/values with FP32 iterates (bf16io); BF16
+iterates (bf16); BF16 gathered iterate copies with an FP32 recurrence state (bf16s); and
+bf16s with the fresh blocks of several snapshots in one batched, graph-replayed recurrence
+(bf16sb, the headline).
 
 Printed: one JSON line.  `value` is the whole-job rate of the Chebyshev step kernels'
 algorithmic bytes (GB/s over the timed wall clock) of the headline form; `roofline` gives
@@ -46,9 +48,9 @@ def parse():
     ap.add_argument("--p", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16,bf16b",
+    ap.add_argument("--forms", default="fp32,bf16io,bf16,bf16s,bf16sb",
                     help="comma list of " + ", ".join(f"{k}: {v[5]}" for k, v in FORMS.items()))
-    ap.add_argument("--headline", default="bf16b")
+    ap.add_argument("--headline", default="bf16sb")
     ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
     ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3")
     ap.add_argument("--probe", metavar="FORM",
@@ -79,7 +81,21 @@ FORMS = {
               "the bf16 form with the fresh blocks of --batch snapshots filtered in one batched "
               "recurrence replayed from a HIP graph"),
     "fp32g": ("float32", "float32", "float32", False, True, "FP32 with HIP-graph replay"),
+    "bf16s": ("bfloat16", "bf16s", "bfloat16", False, False,
+              "BF16 signals, features, operator values and gathered iterate copies; the "
+              "recurrence state, arithmetic and accumulation FP32"),
+    "bf16sb": ("bfloat16", "bf16s", "bfloat16", True, True,
+               "the bf16s form with the fresh blocks of --batch snapshots filtered in one "
+               "batched recurrence replayed from a HIP graph"),
 }
+
+
+def torch_types(form):
+    """(features, iterates, values) of a form; iterates may be the mode string "bf16s"."""
+    import torch
+
+    fdt, idt, vdt = FORMS[form][:3]
+    return getattr(torch, fdt), (idt if idt == "bf16s" else getattr(torch, idt)), getattr(torch, vdt)
 
 
 def kernel_digest() -> str:
@@ -154,7 +170,7 @@ def run_probe(args):
     from workloads import seed_for
 
     fdt, idt, vdt, batched, graph, _ = FORMS[args.probe]
-    feat, iters, vals = (getattr(torch, x) for x in (fdt, idt, vdt))
+    feat, iters, vals = torch_types(args.probe)
     T = 1 + args.batch
     seq, _ = build_sequence(args, T)
     dev = torch.device("cuda")
@@ -256,8 +272,7 @@ def run_dynamic(args):
     all_labels = {}
     for form in args.forms.split(","):
         fdt, idt, vdt, batched, graph, _ = FORMS[form]
-        feat, iters, vals = (getattr(torch, x) for x in (fdt, idt, vdt))
-        bf = vals == torch.bfloat16
+        feat, iters, vals = torch_types(form)
         rp, ci, ww = resident[0]
         G = csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=True, nnz_capacity=cap)
         # kernel shape of the fresh block's recurrence, timed on snapshot 1
@@ -359,7 +374,7 @@ def run_dynamic(args):
             Xt = torch.from_numpy(X).to(dev)
             if bf:
                 Xt = Xt.to(torch.bfloat16)
-            iters = getattr(torch, idt)
+            iters = torch_types(form)[1]
             G = rec["G"]
             G.update_device(*resident[-1], validate=False)
             Y = csc.cheb_filter(G, a, Xt, out_dtype=Xt.dtype, iter_dtype=iters).float().cpu().numpy()

@@ -16,11 +16,23 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsc.so")
 
-F32, BF16, F64 = 0, 1, 2
+F32, BF16, F64, BF16S = 0, 1, 2, 3
+# iterate storage modes: a torch dtype, or "bf16s" (BF16 copies for the gathers and the kept
+# basis, FP32 recurrence state)
+BF16S_ITER = "bf16s"
 DAMP_NONE, DAMP_JACKSON = 0, 1
 
 _TORCH_DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
 _DT_TORCH = {F32: torch.float32, BF16: torch.bfloat16, F64: torch.float64}
+
+
+def _it(iter_dtype) -> int:
+    """Iterate-mode code of a torch dtype or of "bf16s"."""
+    if isinstance(iter_dtype, str):
+        if iter_dtype.lower() == BF16S_ITER:
+            return BF16S
+        raise ValueError(f"unknown iterate mode {iter_dtype!r}")
+    return _TORCH_DT[iter_dtype]
 
 STATUS = {0: "CSC_OK", 1: "CSC_E_ARG", 2: "CSC_E_GRAPH", 3: "CSC_E_DTYPE", 4: "CSC_E_NOMEM",
           5: "CSC_E_HIP", 6: "CSC_E_STATE"}
@@ -242,16 +254,16 @@ class Graph:
         return v.value
 
     def autotune(self, w: int, iter_dtype=torch.float32, stream=None) -> int:
-        need = lib.csc_cheb_filter_workspace_bytes(self.n, w, _TORCH_DT[iter_dtype])
+        need = lib.csc_cheb_filter_workspace_bytes(self.n, w, _it(iter_dtype))
         need += 2 * ((self.n * w * 4 + 255) // 256 * 256) + 4096
         ws = workspace(need)
         v = C.c_int()
-        _check(lib.csc_autotune(self.h, int(w), _TORCH_DT[iter_dtype], _ptr(ws), ws.numel(),
+        _check(lib.csc_autotune(self.h, int(w), _it(iter_dtype), _ptr(ws), ws.numel(),
                                 _stream(stream), C.byref(v)))
         return v.value
 
     def set_variant(self, variant: int, iter_dtype=torch.float32):
-        _check(lib.csc_set_variant(self.h, _TORCH_DT[iter_dtype], int(variant)))
+        _check(lib.csc_set_variant(self.h, _it(iter_dtype), int(variant)))
 
     def close(self):
         if getattr(self, "h", None):
@@ -304,10 +316,10 @@ def cheb_filter(g: Graph, a, X: torch.Tensor, out: torch.Tensor | None = None,
     a = np.asarray(a, dtype=np.float64)
     m = len(a) - 1
     mom = torch.empty(m + 1, dtype=torch.float64, device=X.device) if moments else None
-    need = lib.csc_cheb_filter_workspace_bytes(n, w, _TORCH_DT[iter_dtype])
+    need = lib.csc_cheb_filter_workspace_bytes(n, w, _it(iter_dtype))
     ws = workspace(need, X.device)
     _check(lib.csc_cheb_filter(g.h, float(lmax), m, _dbl_array(a), _ptr(X), _dt(X), _ld(X),
-                               _ptr(out), _dt(out), _ld(out), int(w), _TORCH_DT[iter_dtype],
+                               _ptr(out), _dt(out), _ld(out), int(w), _it(iter_dtype),
                                _ptr(mom), _ptr(ws), ws.numel(), _stream(stream)))
     return (out, mom) if moments else out
 
@@ -316,10 +328,10 @@ def cheb_moments(g: Graph, m: int, P: torch.Tensor, iter_dtype=torch.float32, lm
                  stream=None) -> torch.Tensor:
     n, w = P.shape
     mom = torch.empty(m + 1, dtype=torch.float64, device=P.device)
-    need = lib.csc_cheb_filter_workspace_bytes(n, w, _TORCH_DT[iter_dtype])
+    need = lib.csc_cheb_filter_workspace_bytes(n, w, _it(iter_dtype))
     ws = workspace(need, P.device)
     _check(lib.csc_cheb_moments(g.h, float(lmax), int(m), _ptr(P), _dt(P), _ld(P), int(w),
-                                _TORCH_DT[iter_dtype], _ptr(mom), _ptr(ws), ws.numel(),
+                                _it(iter_dtype), _ptr(mom), _ptr(ws), ws.numel(),
                                 _stream(stream)))
     return mom
 
@@ -330,14 +342,14 @@ def eigcount(g: Graph, m: int, P: torch.Tensor, sigma2: float, k: float, n_cand:
     """Returns (lambda_c, count, trace (n_cand x 2), moments)."""
     n, w = P.shape
     hi = lmax if hi is None else hi
-    need = lib.csc_cheb_filter_workspace_bytes(n, w, _TORCH_DT[iter_dtype]) + (m + 1) * 8 + 512
+    need = lib.csc_cheb_filter_workspace_bytes(n, w, _it(iter_dtype)) + (m + 1) * 8 + 512
     ws = workspace(need, P.device)
     lam, cnt = C.c_double(), C.c_double()
     trace = (C.c_double * (2 * max(n_cand, 1)))()
     mom = (C.c_double * (m + 1))()
     _check(lib.csc_eigcount(g.h, float(lmax), int(m), int(damping), _ptr(P), _dt(P), _ld(P), int(w),
                             float(sigma2), float(k), int(n_cand), float(lo), float(hi),
-                            _TORCH_DT[iter_dtype], C.byref(lam), C.byref(cnt), trace, mom,
+                            _it(iter_dtype), C.byref(lam), C.byref(cnt), trace, mom,
                             _ptr(ws), ws.numel(), _stream(stream)))
     tr = np.frombuffer(trace, dtype=np.float64).reshape(-1, 2)[:n_cand].copy()
     return lam.value, cnt.value, tr, np.frombuffer(mom, dtype=np.float64).copy()
@@ -439,7 +451,7 @@ class DynamicCSC:
                  init: int = 0, keep_iterates: int = -1, batch: int = 1, use_graph: bool = False,
                  variant: int = -1):
         opts = DynOpts(lmax=lmax, tau=tau, n_cand=n_cand, lloyd_iters=lloyd_iters, init=init,
-                       iter_dt=_TORCH_DT[iter_dtype], keep_iterates=keep_iterates, batch=batch,
+                       iter_dt=_it(iter_dtype), keep_iterates=keep_iterates, batch=batch,
                        use_graph=int(bool(use_graph)), variant=int(variant))
         h = C.c_void_p()
         _check(lib.csc_dyn_create(int(n), int(d), int(k), float(p), int(m), int(damping),

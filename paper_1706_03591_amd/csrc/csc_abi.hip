@@ -498,7 +498,7 @@ csc_status csc_timing_read(double* ms, int64_t* launches, double* bytes) {
 csc_status csc_autotune(csc_graph h, int w, csc_dtype iter_dt, void* work, size_t work_bytes,
                         void* stream, int* variant) {
   if (!h) return fail(CSC_E_ARG, "null graph");
-  if (iter_dt != CSC_F32 && iter_dt != CSC_BF16) return fail(CSC_E_DTYPE, "bad iterate type");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "bad iterate type");
   Graph& g = h->g;
   hipStream_t s = as_stream(stream);
   const size_t need = filter_workspace(g.n, w, iter_dt);
@@ -538,7 +538,7 @@ csc_status csc_autotune(csc_graph h, int w, csc_dtype iter_dt, void* work, size_
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (iter_dt == CSC_BF16) g.variant_bf16 = best;
+  if (iter_dt != CSC_F32) g.variant_bf16 = best;
   else g.variant_f32 = best;
   if (variant) *variant = best;
   return CSC_OK;
@@ -547,7 +547,8 @@ csc_status csc_autotune(csc_graph h, int w, csc_dtype iter_dt, void* work, size_
 csc_status csc_set_variant(csc_graph h, csc_dtype iter_dt, int variant) {
   if (!h) return fail(CSC_E_ARG, "null graph");
   if (variant < -1 || variant >= num_variants()) return fail(CSC_E_ARG, "bad variant");
-  if (iter_dt == CSC_BF16) h->g.variant_bf16 = variant;
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "bad iterate type");
+  if (iter_dt != CSC_F32) h->g.variant_bf16 = variant;
   else h->g.variant_f32 = variant;
   return CSC_OK;
 }

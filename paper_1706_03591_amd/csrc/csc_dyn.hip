@@ -104,9 +104,9 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     st->iter_dt = opts->iter_dt;
   }
   if (st->tau <= 0.0) st->tau = std::max(0.5, 2.0 * std::sqrt(2.0 * k / qd));
-  if (st->iter_dt != CSC_F32 && st->iter_dt != CSC_BF16) {
+  if (!iter_type_ok(st->iter_dt)) {
     delete st;
-    return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
+    return fail(CSC_E_DTYPE, "iterates must be F32, BF16 or BF16S");
   }
   if (st->batch > 8) {
     delete st;
@@ -140,7 +140,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     probe.variant_f32 = probe.variant_bf16 = -1;
     st->variant = (opts && opts->variant >= 0) ? opts->variant : default_variant(&probe, qd, st->iter_dt);
     st->basis_bytes = basis_bytes(n, qd, m, st->iter_dt, st->variant);
-    st->aux_bytes = basis_aux_bytes(n, m);
+    st->aux_bytes = basis_aux_bytes(n, qd, m, st->iter_dt, st->variant);
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     const size_t margin = size_t(4) << 30;

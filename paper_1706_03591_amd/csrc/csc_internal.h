@@ -31,14 +31,20 @@ csc_status fail(csc_status st, const std::string& msg);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Element size; for the iterate mode CSC_BF16S, the size of the stored (gathered) copy.
 inline size_t dtype_size(csc_dtype t) {
   switch (t) {
     case CSC_F32: return 4;
     case CSC_BF16: return 2;
     case CSC_F64: return 8;
+    case CSC_BF16S: return 2;
   }
   return 0;
 }
+
+inline bool iter_type_ok(csc_dtype t) { return t == CSC_F32 || t == CSC_BF16 || t == CSC_BF16S; }
+// bytes per element of the separate FP32 recurrence state (CSC_BF16S only)
+inline size_t state_size(csc_dtype t) { return t == CSC_BF16S ? 4 : 0; }
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -106,7 +112,7 @@ struct FilterPlan {
   int wpad;       // ntiles * wt
   csc_dtype iter_dt;
   // workspace carve-up (byte offsets)
-  size_t off_z0, off_z1, off_acc, off_part, off_mom;
+  size_t off_z0, off_z1, off_s0, off_s1, off_acc, off_part, off_mom;
   size_t total;
   int64_t rows_per_block;
   int64_t row_blocks;
@@ -123,7 +129,7 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
 
 // Stored basis Z_0..Z_m (tiled, one slot per j) and its uses.
 size_t basis_bytes(int64_t n, int w, int m, csc_dtype iter_dt, int variant);
-size_t basis_aux_bytes(int64_t n, int m);
+size_t basis_aux_bytes(int64_t n, int w, int m, csc_dtype iter_dt, int variant);
 csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtype x_dt, int64_t ldx,
                      int w, csc_dtype iter_dt, int variant, void* basis, size_t bytes, hipStream_t s);
 csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype iter_dt, int variant,

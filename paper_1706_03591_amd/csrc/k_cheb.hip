@@ -16,6 +16,12 @@
 // stages its rows' column indices and values in LDS with one coalesced pass; each row is
 // served by `LPR` lanes that each own 16 bytes of the row (4 FP32 or 8 BF16 columns), so a
 // gather is one 16-byte load per lane and one contiguous segment per row group.
+//
+// Iterate modes: FP32; BF16 (iterates rounded to BF16 at every step); BF16S (BF16 copies of
+// the iterates for the gathers and the kept basis, while the recurrence state Z_{j-1}, Z_j,
+// Z_{j+1} of each row stays in a separate FP32 tiled array with the same element offsets).
+#include <type_traits>
+
 #include "csc_internal.h"
 
 namespace csc {
@@ -26,6 +32,11 @@ constexpr int kThreads = 256;
 constexpr int kStageCap = 2048;  // CSR entries staged in LDS per block
 
 enum : int { F_FIRST = 1, F_ACC = 2, F_LAST = 4, F_MOM = 8, F_STORE = 16, F_OWN = 32 };
+
+// Tag type of the BF16S iterate mode (BF16 gathered copies, FP32 state).
+struct Bf16S {};
+template <typename TZ>
+using GatherT = typename std::conditional<std::is_same<TZ, Bf16S>::value, uint16_t, TZ>::type;
 
 template <typename TZ>
 struct Pack;
@@ -81,6 +92,21 @@ __device__ inline float val_f<uint16_t>(uint16_t v) { return bf16_to_f32(v); }
 __device__ inline uint4 ld16(const void* p) { return *reinterpret_cast<const uint4*>(p); }
 __device__ inline void st16(void* p, const uint4& v) { *reinterpret_cast<uint4*>(p) = v; }
 
+// eight FP32 state values (32 bytes) of one lane
+__device__ inline void ld8f(const float* p, float* f) {
+  const uint4 a = ld16(p), b = ld16(p + 4);
+  f[0] = __uint_as_float(a.x); f[1] = __uint_as_float(a.y);
+  f[2] = __uint_as_float(a.z); f[3] = __uint_as_float(a.w);
+  f[4] = __uint_as_float(b.x); f[5] = __uint_as_float(b.y);
+  f[6] = __uint_as_float(b.z); f[7] = __uint_as_float(b.w);
+}
+__device__ inline void st8f(float* p, const float* f) {
+  st16(p, make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
+                     __float_as_uint(f[3])));
+  st16(p + 4, make_uint4(__float_as_uint(f[4]), __float_as_uint(f[5]), __float_as_uint(f[6]),
+                         __float_as_uint(f[7])));
+}
+
 struct StepParams {
   const int32_t* rowptr;
   const int32_t* colidx;
@@ -88,6 +114,9 @@ struct StepParams {
   const void* zcur;
   const void* zprev;
   void* zout;
+  const float* scur;   // BF16S: FP32 state Z_j (tiled like the copies)
+  const float* sprev;  // BF16S: FP32 state Z_{j-1}
+  float* sout;         // BF16S: FP32 state Z_{j+1} (in place over Z_{j-1})
   float* acc;      // row-major n x wpad
   int64_t ld_acc;  // = wpad
   void* yout;      // final output (row-major, ldy, y_dt) on the last step, else null
@@ -128,7 +157,9 @@ __device__ inline void block_reduce2(double& a, double& b) {
 // several snapshots' steps, each with its own parameters and block range).
 template <typename TZ, typename TV, int LPR>
 __device__ inline void step_body(const StepParams& p, const int64_t bid, const int64_t nblocks) {
-  using P = Pack<TZ>;
+  constexpr bool MIX = std::is_same<TZ, Bf16S>::value;
+  using TG = GatherT<TZ>;
+  using P = Pack<TG>;
   constexpr int VEC = P::VEC;
   constexpr int WT = LPR * VEC;
   constexpr int RPB = kThreads / LPR;
@@ -155,7 +186,7 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
   const int64_t row = r0 + threadIdx.x / LPR;
   const int lane = threadIdx.x % LPR;
   const int64_t tile_off = tile * p.n * WT;  // elements
-  const TZ* zc = static_cast<const TZ*>(p.zcur) + tile_off + lane * VEC;
+  const TG* zc = static_cast<const TG*>(p.zcur) + tile_off + lane * VEC;
   double d1 = 0.0, d2 = 0.0;
 
   if (row < p.n) {
@@ -208,9 +239,11 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
     }
 
     const int64_t own = row * WT;  // element offset of this row within the tile
+    const int64_t eoff = tile_off + lane * VEC + own;
     float zj[VEC];
     if (p.flags & F_OWN) {
-      P::unpack(ld16(zc + own), zj);
+      if constexpr (MIX) ld8f(p.scur + eoff, zj);
+      else P::unpack(ld16(zc + own), zj);
     } else {
 #pragma unroll
       for (int i = 0; i < VEC; ++i) zj[i] = 0.f;
@@ -221,14 +254,25 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
       for (int i = 0; i < VEC; ++i) zn[i] = fmaf(p.alpha, zj[i], -p.beta * acc[i]);
     } else {
       float zp[VEC];
-      P::unpack(ld16(static_cast<const TZ*>(p.zprev) + tile_off + lane * VEC + own), zp);
+      if constexpr (MIX) ld8f(p.sprev + eoff, zp);
+      else P::unpack(ld16(static_cast<const TG*>(p.zprev) + eoff), zp);
 #pragma unroll
       for (int i = 0; i < VEC; ++i)
         zn[i] = 2.f * fmaf(p.alpha, zj[i], -p.beta * acc[i]) - zp[i];
     }
-    const uint4 packed = P::pack(zn);  // zn now holds the stored (rounded) values
-    if (p.flags & F_STORE)
-      st16(static_cast<TZ*>(p.zout) + tile_off + lane * VEC + own, packed);
+    if constexpr (MIX) {
+      // the state keeps FP32; only the gathered copy is rounded
+      if (p.flags & F_STORE) {
+        st8f(p.sout + eoff, zn);
+        float cp[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) cp[i] = zn[i];
+        st16(static_cast<TG*>(p.zout) + eoff, P::pack(cp));
+      }
+    } else {
+      const uint4 packed = P::pack(zn);  // zn now holds the stored (rounded) values
+      if (p.flags & F_STORE) st16(static_cast<TG*>(p.zout) + eoff, packed);
+    }
     if (p.flags & F_MOM) {
       float s1 = 0.f, s2 = 0.f;
 #pragma unroll
@@ -293,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void k_step_batch(StepBatch b) {
 // Z_0 (tiled, iter type) from X (row-major, x_dt); acc = a0 * Z_0 when acc != null.
 template <typename TZ>
 __global__ void k_init(const void* X, int x_dt, int64_t ldx, int64_t n, int w, int wpad, int wt,
-                       TZ* z0, float* acc, float a0) {
+                       TZ* z0, float* acc, float a0, float* s0) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n * wpad) return;
   const int64_t row = idx / wpad;
@@ -306,14 +350,16 @@ __global__ void k_init(const void* X, int x_dt, int64_t ldx, int64_t n, int w, i
     else x = static_cast<float>(static_cast<const double*>(X)[src]);
   }
   const int tile = col / wt, c = col - tile * wt;
+  const int64_t e = static_cast<int64_t>(tile) * n * wt + row * wt + c;
   float stored;
   if constexpr (sizeof(TZ) == 4) {
     stored = x;
-    z0[static_cast<int64_t>(tile) * n * wt + row * wt + c] = stored;
+    z0[e] = stored;
   } else {
     const uint16_t h = f32_to_bf16(x);
-    stored = bf16_to_f32(h);
-    z0[static_cast<int64_t>(tile) * n * wt + row * wt + c] = h;
+    z0[e] = h;
+    stored = s0 ? x : bf16_to_f32(h);  // BF16S: the state keeps the FP32 value
+    if (s0) s0[e] = x;
   }
   if (acc) acc[row * wpad + col] = a0 * stored;
 }
@@ -377,21 +423,48 @@ BatchFn pick_batch(int lpr, csc_dtype val_dt) {
   }
 }
 
+StepFn step_fn(csc_dtype iter_dt, int lpr, csc_dtype val_dt) {
+  if (iter_dt == CSC_F32) return pick_step<float>(lpr, val_dt);
+  if (iter_dt == CSC_BF16S) return pick_step<Bf16S>(lpr, val_dt);
+  return pick_step<uint16_t>(lpr, val_dt);
+}
+
+BatchFn batch_fn(csc_dtype iter_dt, int lpr, csc_dtype val_dt) {
+  if (iter_dt == CSC_F32) return pick_batch<float>(lpr, val_dt);
+  if (iter_dt == CSC_BF16S) return pick_batch<Bf16S>(lpr, val_dt);
+  return pick_batch<uint16_t>(lpr, val_dt);
+}
+
+// Z_0 of the tiled iterates (and of the FP32 state in BF16S mode) from X; acc = a0 Z_0 when
+// acc is given.
+void launch_init(csc_dtype iter_dt, const void* X, csc_dtype x_dt, int64_t ldx, int64_t n, int w,
+                 int wpad, int wt, void* z0, float* acc, float a0, float* s0, hipStream_t s) {
+  const int64_t total = n * wpad;
+  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+  if (iter_dt == CSC_F32)
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w, wpad,
+                       wt, static_cast<float*>(z0), acc, a0, static_cast<float*>(nullptr));
+  else
+    hipLaunchKernelGGL(k_init<uint16_t>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
+                       wpad, wt, static_cast<uint16_t*>(z0), acc, a0,
+                       iter_dt == CSC_BF16S ? s0 : static_cast<float*>(nullptr));
+}
+
 }  // namespace
 
 int num_variants() { return 4; }
 
 StepShape variant_shape(int variant, csc_dtype iter_dt) {
-  const int vec = iter_dt == CSC_BF16 ? 8 : 4;
+  const int vec = iter_dt == CSC_F32 ? 4 : 8;
   if (variant < 0 || variant >= num_variants()) variant = 2;
   return StepShape{kLpr[variant], vec};
 }
 
 int default_variant(const Graph* g, int w, csc_dtype iter_dt) {
-  const int v = iter_dt == CSC_BF16 ? g->variant_bf16 : g->variant_f32;
+  const int v = iter_dt == CSC_F32 ? g->variant_f32 : g->variant_bf16;
   if (v >= 0) return v;
   // widest tile that does not exceed the block width (fewest CSR re-reads)
-  const int vec = iter_dt == CSC_BF16 ? 8 : 4;
+  const int vec = iter_dt == CSC_F32 ? 4 : 8;
   int best = 0;
   for (int i = 0; i < num_variants(); ++i)
     if (kLpr[i] * vec <= std::max(w, kLpr[0] * vec)) best = i;
@@ -413,9 +486,12 @@ FilterPlan make_plan(int64_t n, int w, csc_dtype iter_dt, int variant, int m_for
   const size_t zbytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
   const size_t nb = static_cast<size_t>(pl.row_blocks) * pl.ntiles;
   const int J = m_for_moments >= 1 ? m_for_moments / 2 : 0;
+  const size_t sbytes = align_up(static_cast<size_t>(n) * pl.wpad * state_size(iter_dt));
   size_t off = 0;
   pl.off_z0 = off; off += zbytes;
   pl.off_z1 = off; off += zbytes;
+  pl.off_s0 = off; off += sbytes;
+  pl.off_s1 = off; off += sbytes;
   pl.off_acc = off; off += align_up(static_cast<size_t>(n) * pl.wpad * sizeof(float));
   pl.off_part = off; off += align_up(static_cast<size_t>(J + 1) * 2 * nb * sizeof(double));
   pl.off_mom = off; off += align_up(static_cast<size_t>(J + 1) * 2 * sizeof(double));
@@ -434,11 +510,13 @@ size_t filter_workspace(int64_t n, int w, csc_dtype iter_dt) {
 static double step_bytes(const Graph* g, int64_t n, int w, csc_dtype iter_dt, int flags,
                          csc_dtype y_dt) {
   const double sz = static_cast<double>(dtype_size(iter_dt));
+  const double ss = iter_dt == CSC_BF16S ? 4.0 : sz;  // state element (own-row streams)
   double b = static_cast<double>(g->nnz) * (4.0 + dtype_size(g->val_dt)) + 4.0 * (n + 1);
   const double nw = static_cast<double>(n) * w;
   b += nw * sz;                                   // gather Z_j (each row counted once)
-  if (!(flags & F_FIRST)) b += nw * sz;           // Z_{j-1}
-  if (flags & F_STORE) b += nw * sz;              // Z_{j+1}
+  if ((flags & F_OWN) && iter_dt == CSC_BF16S) b += nw * ss;  // own Z_j from the state
+  if (!(flags & F_FIRST)) b += nw * ss;           // Z_{j-1}
+  if (flags & F_STORE) b += nw * (iter_dt == CSC_BF16S ? ss + sz : sz);  // Z_{j+1}
   if (flags & F_ACC) b += nw * 4.0 + ((flags & F_LAST) ? nw * dtype_size(y_dt) : nw * 4.0);
   return b;
 }
@@ -451,8 +529,7 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
   if (m < 0) return fail(CSC_E_ARG, "m must be >= 0");
   if (w < 1) return fail(CSC_E_ARG, "w must be >= 1");
   if (!(lmax > 0.0)) return fail(CSC_E_ARG, "lmax must be > 0");
-  if (iter_dt != CSC_F32 && iter_dt != CSC_BF16)
-    return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16 or BF16S");
   if (moments && m < 1) return fail(CSC_E_ARG, "moments need m >= 1");
   if (!moments_only && (ldy < w || !Y)) return fail(CSC_E_ARG, "bad Y / ldy");
   if (ldx < w || !X) return fail(CSC_E_ARG, "bad X / ldx");
@@ -471,25 +548,16 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
     return fail(CSC_E_ARG, "workspace too small: need " + std::to_string(pl.total) + " bytes");
   char* base = static_cast<char*>(work);
   void* zb[2] = {base + pl.off_z0, base + pl.off_z1};
+  float* sb[2] = {reinterpret_cast<float*>(base + pl.off_s0), reinterpret_cast<float*>(base + pl.off_s1)};
   float* acc = reinterpret_cast<float*>(base + pl.off_acc);
   double* part = reinterpret_cast<double*>(base + pl.off_part);
   double* msum = reinterpret_cast<double*>(base + pl.off_mom);
   const int wt = pl.shape.wt();
   const bool do_acc = !moments_only;
 
-  {
-    const int64_t total = n * pl.wpad;
-    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
-    const float a0 = static_cast<float>(a ? a[0] : 0.0);
-    if (iter_dt == CSC_F32)
-      hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
-                         pl.wpad, wt, static_cast<float*>(zb[0]), do_acc ? acc : nullptr, a0);
-    else
-      hipLaunchKernelGGL(k_init<uint16_t>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n,
-                         w, pl.wpad, wt, static_cast<uint16_t*>(zb[0]), do_acc ? acc : nullptr,
-                         a0);
-    CSC_HIP(hipGetLastError());
-  }
+  launch_init(iter_dt, X, x_dt, ldx, n, w, pl.wpad, wt, zb[0], do_acc ? acc : nullptr,
+              static_cast<float>(a ? a[0] : 0.0), sb[0], s);
+  CSC_HIP(hipGetLastError());
   if (m == 0) {
     if (do_acc) {
       const int64_t total = n * w;
@@ -500,8 +568,7 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
     return CSC_OK;
   }
 
-  const StepFn fn = iter_dt == CSC_F32 ? pick_step<float>(pl.shape.lpr, g->val_dt)
-                                       : pick_step<uint16_t>(pl.shape.lpr, g->val_dt);
+  const StepFn fn = step_fn(iter_dt, pl.shape.lpr, g->val_dt);
   const int64_t nb = pl.row_blocks * pl.ntiles;
   const int J = moments ? m / 2 : -1;
   const int nsteps = moments_only ? J + 1 : m;
@@ -517,6 +584,9 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
     p.zcur = zb[j & 1];
     p.zprev = zb[(j + 1) & 1];
     p.zout = zb[(j + 1) & 1];
+    p.scur = sb[j & 1];
+    p.sprev = sb[(j + 1) & 1];
+    p.sout = sb[(j + 1) & 1];
     p.acc = acc;
     p.ld_acc = pl.wpad;
     p.w = w;
@@ -827,7 +897,8 @@ csc_status run_backward(const Graph* g, double lmax, int m, const double* a, con
     return CSC_OK;
   };
   hipLaunchKernelGGL(k_init<float>, dim3(eblocks), dim3(256), 0, s, static_cast<const void*>(X),
-                     int(CSC_F32), ldx, n, w, pl.wpad, wt, pp[0], static_cast<float*>(nullptr), 0.f);
+                     int(CSC_F32), ldx, n, w, pl.wpad, wt, pp[0], static_cast<float*>(nullptr), 0.f,
+                     static_cast<float*>(nullptr));
   gdot(pp[0], 0);
   CSC_TRY(keep(0, pp[0]));
   for (int j = 0; j < m; ++j) {
@@ -964,72 +1035,89 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineParams p) {
   }
 }
 
-// Partials of <Z_j, Z_j> and <Z_{j+1}, Z_j> for the doubled moments (tiled layout; padded
-// columns are zero).
+// Direct moments from the kept basis: part[j * gridDim.x + b] = block b's share of
+// <Z_0, Z_j> (FP64, fixed order).  Z_0 is the probe block itself, so the rounding of the
+// stored Z_j enters only through <P, e_j>, which has zero mean; the doubled form
+// 2 <Z_j, Z_j> - mu_0 would instead carry the positive bias 2 ||e_j||^2.  Each thread keeps
+// kDirV 16-byte vectors of Z_0 in registers while it walks the m + 1 slots, so every slot is
+// read once (padded columns are zero in both).
+constexpr int kDirV = 4;
+
 template <typename TZ>
-__global__ __launch_bounds__(kThreads) void k_pair_dots(const TZ* zj, const TZ* zj1, int64_t count,
-                                                        double* part) {
+__global__ __launch_bounds__(kThreads) void k_dir_moments(const TZ* basis, int64_t slot,
+                                                          int64_t nvec, int m, double* part) {
   constexpr int VEC = Pack<TZ>::VEC;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
-  double d1 = 0.0, d2 = 0.0;
-  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t * VEC < count; t += stride) {
-    float a[VEC], b[VEC];
-    Pack<TZ>::unpack(ld16(zj + t * VEC), a);
-    Pack<TZ>::unpack(ld16(zj1 + t * VEC), b);
-    float s1 = 0.f, s2 = 0.f;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kDirV + threadIdx.x;
+  float z0[kDirV][VEC];
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-      s1 = fmaf(a[i], a[i], s1);
-      s2 = fmaf(b[i], a[i], s2);
-    }
-    d1 += s1;
-    d2 += s2;
+  for (int q = 0; q < kDirV; ++q) {
+    const int64_t v = base + q * kThreads;
+    if (v < nvec) Pack<TZ>::unpack(ld16(basis + v * VEC), z0[q]);
+    else
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) z0[q][i] = 0.f;
   }
-  block_reduce2(d1, d2);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = d1;
-    part[gridDim.x + blockIdx.x] = d2;
+  for (int j = 0; j <= m; ++j) {
+    const TZ* zj = basis + static_cast<int64_t>(j) * slot;
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < kDirV; ++q) {
+      const int64_t v = base + q * kThreads;
+      if (v < nvec) {
+        float f[VEC];
+        Pack<TZ>::unpack(ld16(zj + v * VEC), f);
+        float sp = 0.f;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) sp = fmaf(z0[q][i], f[i], sp);
+        d += static_cast<double>(sp);
+      }
+    }
+    double dummy = 0.0;
+    block_reduce2(d, dummy);
+    if (threadIdx.x == 0) part[static_cast<int64_t>(j) * gridDim.x + blockIdx.x] = d;
   }
 }
-
-constexpr int kPairBlocks = 1024;
 
 }  // namespace
 
+// m + 1 slots of the stored iterates, then (BF16S) the two FP32 state buffers.
 size_t basis_bytes(int64_t n, int w, int m, csc_dtype iter_dt, int variant) {
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
-  return static_cast<size_t>(m + 1) * align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
+  return static_cast<size_t>(m + 1) * align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt)) +
+         2 * align_up(static_cast<size_t>(n) * pl.wpad * state_size(iter_dt));
 }
 
-size_t basis_aux_bytes(int64_t n, int m) {
-  const int J = m / 2;
-  return align_up(static_cast<size_t>(J + 1) * 2 * kPairBlocks * sizeof(double)) +
-         align_up(static_cast<size_t>(J + 1) * 2 * sizeof(double)) +
-         align_up(static_cast<size_t>((n * 256 + kThreads - 1) / kThreads + 1) * sizeof(double));
+static int64_t dir_blocks(int64_t n, int w, csc_dtype iter_dt, int variant, int64_t* nvec) {
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
+  const int VEC = iter_dt == CSC_F32 ? 4 : 8;
+  *nvec = n * (pl.wpad / VEC);
+  return std::max<int64_t>(1, (*nvec + kThreads * kDirV - 1) / (kThreads * kDirV));
+}
+
+// Scratch of the recombination dot and of the direct moments.
+size_t basis_aux_bytes(int64_t n, int w, int m, csc_dtype iter_dt, int variant) {
+  int64_t nvec = 0;
+  const int64_t nb = dir_blocks(n, w, iter_dt, variant, &nvec);
+  const size_t moments = align_up(static_cast<size_t>(m + 1) * nb * sizeof(double));
+  const size_t combine = align_up(static_cast<size_t>((nvec + kThreads - 1) / kThreads + 1) * sizeof(double));
+  return std::max(moments, combine);
 }
 
 csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtype x_dt, int64_t ldx,
                      int w, csc_dtype iter_dt, int variant, void* basis, size_t bytes, hipStream_t s) {
   const int64_t n = g->n;
   if (m < 1 || w < 1 || ldx < w || !X) return fail(CSC_E_ARG, "bad basis arguments");
-  if (iter_dt != CSC_F32 && iter_dt != CSC_BF16) return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16 or BF16S");
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
   const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
-  if (!basis || bytes < static_cast<size_t>(m + 1) * slot_bytes) return fail(CSC_E_ARG, "basis buffer too small");
+  const size_t state_bytes = align_up(static_cast<size_t>(n) * pl.wpad * state_size(iter_dt));
+  if (!basis || bytes < basis_bytes(n, w, m, iter_dt, variant)) return fail(CSC_E_ARG, "basis buffer too small");
   char* b = static_cast<char*>(basis);
+  float* st[2] = {reinterpret_cast<float*>(b + static_cast<size_t>(m + 1) * slot_bytes),
+                  reinterpret_cast<float*>(b + static_cast<size_t>(m + 1) * slot_bytes + state_bytes)};
   const int wt = pl.shape.wt();
-  {
-    const int64_t total = n * pl.wpad;
-    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
-    if (iter_dt == CSC_F32)
-      hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w, pl.wpad,
-                         wt, reinterpret_cast<float*>(b), static_cast<float*>(nullptr), 0.f);
-    else
-      hipLaunchKernelGGL(k_init<uint16_t>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
-                         pl.wpad, wt, reinterpret_cast<uint16_t*>(b), static_cast<float*>(nullptr), 0.f);
-  }
-  const StepFn fn = iter_dt == CSC_F32 ? pick_step<float>(pl.shape.lpr, g->val_dt)
-                                       : pick_step<uint16_t>(pl.shape.lpr, g->val_dt);
+  launch_init(iter_dt, X, x_dt, ldx, n, w, pl.wpad, wt, b, nullptr, 0.f, st[0], s);
+  const StepFn fn = step_fn(iter_dt, pl.shape.lpr, g->val_dt);
   const int64_t nb = pl.row_blocks * pl.ntiles;
   const float alpha = static_cast<float>(2.0 / lmax - 1.0);
   const float beta = static_cast<float>(2.0 / lmax);
@@ -1043,6 +1131,9 @@ csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtyp
     p.zcur = b + static_cast<size_t>(j) * slot_bytes;
     p.zprev = j > 0 ? b + static_cast<size_t>(j - 1) * slot_bytes : nullptr;
     p.zout = b + static_cast<size_t>(j + 1) * slot_bytes;
+    p.scur = st[j & 1];
+    p.sprev = st[(j + 1) & 1];
+    p.sout = st[(j + 1) & 1];
     p.w = w;
     p.n = n;
     p.row_blocks = pl.row_blocks;
@@ -1066,7 +1157,7 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
   if (m + 1 > kMaxCombine) return fail(CSC_E_ARG, "combine supports m < 512");
   if (!Y || ldy < w) return fail(CSC_E_ARG, "bad Y");
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
-  const int VEC = iter_dt == CSC_F32 ? 4 : 8;
+  const int VEC = iter_dt == CSC_F32 ? 4 : 8;  // BF16 and BF16S keep BF16 copies
   const int64_t threads = n * (pl.wpad / VEC);
   const unsigned blocks = static_cast<unsigned>((threads + kThreads - 1) / kThreads);
   if (dot && aux_bytes < align_up((blocks + 1) * sizeof(double))) return fail(CSC_E_ARG, "aux too small");
@@ -1096,34 +1187,24 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
   return CSC_OK;
 }
 
-// mu_0..mu_m (device) from the stored basis by the doubling identities.
+// mu_0..mu_m (device) of the stored basis in the direct form mu_j = <Z_0, Z_j>.
 csc_status run_basis_moments(const void* basis, int64_t n, int w, int m, csc_dtype iter_dt,
                              int variant, double* moments, void* aux, size_t aux_bytes,
                              hipStream_t s) {
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
-  const int J = m / 2;
-  const size_t part_bytes = align_up(static_cast<size_t>(J + 1) * 2 * kPairBlocks * sizeof(double));
-  if (aux_bytes < part_bytes + align_up(static_cast<size_t>(J + 1) * 2 * sizeof(double)))
-    return fail(CSC_E_ARG, "aux too small");
+  int64_t nvec = 0;
+  const int64_t nb = dir_blocks(n, w, iter_dt, variant, &nvec);
+  if (aux_bytes < static_cast<size_t>(m + 1) * nb * sizeof(double)) return fail(CSC_E_ARG, "aux too small");
   double* part = static_cast<double*>(aux);
-  double* sums = reinterpret_cast<double*>(static_cast<char*>(aux) + part_bytes);
-  const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
-  const int64_t count = n * pl.wpad;
-  const char* b = static_cast<const char*>(basis);
-  for (int j = 0; j <= J; ++j) {
-    const void* zj = b + static_cast<size_t>(j) * slot_bytes;
-    const void* zj1 = b + static_cast<size_t>(j + 1) * slot_bytes;
-    double* pj = part + static_cast<int64_t>(j) * 2 * kPairBlocks;
-    if (iter_dt == CSC_F32)
-      hipLaunchKernelGGL(k_pair_dots<float>, dim3(kPairBlocks), dim3(kThreads), 0, s,
-                         static_cast<const float*>(zj), static_cast<const float*>(zj1), count, pj);
-    else
-      hipLaunchKernelGGL(k_pair_dots<uint16_t>, dim3(kPairBlocks), dim3(kThreads), 0, s,
-                         static_cast<const uint16_t*>(zj), static_cast<const uint16_t*>(zj1), count, pj);
-  }
-  hipLaunchKernelGGL(k_reduce_rows, dim3(2 * (J + 1)), dim3(kThreads), 0, s, part,
-                     static_cast<int64_t>(kPairBlocks), sums);
-  hipLaunchKernelGGL(k_moments, dim3(1), dim3(64), 0, s, sums, J, m, moments);
+  const int64_t slot = static_cast<int64_t>(align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt)) /
+                                            dtype_size(iter_dt));
+  if (iter_dt == CSC_F32)
+    hipLaunchKernelGGL(k_dir_moments<float>, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s,
+                       static_cast<const float*>(basis), slot, nvec, m, part);
+  else
+    hipLaunchKernelGGL(k_dir_moments<uint16_t>, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s,
+                       static_cast<const uint16_t*>(basis), slot, nvec, m, part);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(m + 1), dim3(kThreads), 0, s, part, nb, moments);
   CSC_HIP(hipGetLastError());
   return CSC_OK;
 }
@@ -1146,24 +1227,19 @@ csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m
     if (graphs[i]->val_dt != graphs[0]->val_dt) return fail(CSC_E_DTYPE, "batched graphs must share the value type");
   }
   if (m < 1 || w < 1 || ldx < w) return fail(CSC_E_ARG, "bad basis arguments");
-  if (iter_dt != CSC_F32 && iter_dt != CSC_BF16) return fail(CSC_E_DTYPE, "iterates must be F32 or BF16");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16 or BF16S");
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
   const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
-  if (bytes < static_cast<size_t>(m + 1) * slot_bytes) return fail(CSC_E_ARG, "basis buffer too small");
+  const size_t state_bytes = align_up(static_cast<size_t>(n) * pl.wpad * state_size(iter_dt));
+  if (bytes < basis_bytes(n, w, m, iter_dt, variant)) return fail(CSC_E_ARG, "basis buffer too small");
   const int wt = pl.shape.wt();
-  const int64_t total = n * pl.wpad;
-  const unsigned iblocks = static_cast<unsigned>((total + 255) / 256);
-  for (int i = 0; i < S; ++i) {
-    if (iter_dt == CSC_F32)
-      hipLaunchKernelGGL(k_init<float>, dim3(iblocks), dim3(256), 0, s, X[i], int(x_dt), ldx, n, w,
-                         pl.wpad, wt, static_cast<float*>(bases[i]), static_cast<float*>(nullptr), 0.f);
-    else
-      hipLaunchKernelGGL(k_init<uint16_t>, dim3(iblocks), dim3(256), 0, s, X[i], int(x_dt), ldx, n, w,
-                         pl.wpad, wt, static_cast<uint16_t*>(bases[i]), static_cast<float*>(nullptr),
-                         0.f);
-  }
-  const BatchFn fn = iter_dt == CSC_F32 ? pick_batch<float>(pl.shape.lpr, graphs[0]->val_dt)
-                                        : pick_batch<uint16_t>(pl.shape.lpr, graphs[0]->val_dt);
+  auto state = [&](int i, int q) {
+    return reinterpret_cast<float*>(static_cast<char*>(bases[i]) + static_cast<size_t>(m + 1) * slot_bytes +
+                                    static_cast<size_t>(q) * state_bytes);
+  };
+  for (int i = 0; i < S; ++i)
+    launch_init(iter_dt, X[i], x_dt, ldx, n, w, pl.wpad, wt, bases[i], nullptr, 0.f, state(i, 0), s);
+  const BatchFn fn = batch_fn(iter_dt, pl.shape.lpr, graphs[0]->val_dt);
   const int64_t per = pl.row_blocks * pl.ntiles;
   const float alpha = static_cast<float>(2.0 / lmax - 1.0);
   const float beta = static_cast<float>(2.0 / lmax);
@@ -1182,6 +1258,9 @@ csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m
       p.zcur = base + static_cast<size_t>(j) * slot_bytes;
       p.zprev = j > 0 ? base + static_cast<size_t>(j - 1) * slot_bytes : nullptr;
       p.zout = base + static_cast<size_t>(j + 1) * slot_bytes;
+      p.scur = state(i, j & 1);
+      p.sprev = state(i, (j + 1) & 1);
+      p.sout = state(i, (j + 1) & 1);
       p.w = w;
       p.n = n;
       p.row_blocks = pl.row_blocks;

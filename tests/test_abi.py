@@ -104,3 +104,26 @@ def test_workspace_queries_are_monotone(pkg):
 
 def test_version(pkg):
     assert pkg.version() >= 10000
+
+
+def test_iterate_mode_codes(pkg):
+    import torch
+
+    from paper_1706_03591_amd import binding
+
+    assert binding._it(torch.float32) == binding.F32
+    assert binding._it(torch.bfloat16) == binding.BF16
+    assert binding._it("bf16s") == binding.BF16S == 3
+    with pytest.raises(ValueError):
+        binding._it("fp8")
+
+
+def test_bf16s_workspace_holds_fp32_state(pkg):
+    lib = pkg.lib
+    n, w = 1000, 64
+    f32 = lib.csc_cheb_filter_workspace_bytes(n, w, 0)
+    b16 = lib.csc_cheb_filter_workspace_bytes(n, w, 1)
+    b16s = lib.csc_cheb_filter_workspace_bytes(n, w, 3)
+    # two BF16 copies plus two FP32 state arrays on top of the BF16 layout
+    assert b16s >= b16 + 2 * n * w * 4
+    assert f32 > 0

@@ -44,9 +44,11 @@ def test_dynamic_matches_oracle(csc, seq, p, d, tau, keep):
         assert agree > 0.99 or c_gpu == pytest.approx(c_orc, rel=1e-3)
 
 
-def test_dynamic_bf16_quality(csc, seq):
+@pytest.mark.parametrize("iters", [torch.float32, torch.bfloat16, "bf16s"])
+def test_dynamic_bf16_quality(csc, seq, iters):
     k, m, d = 4, 40, 64
-    gpu = csc.DynamicCSC(2000, d, k, 0.5, m, seed=54, feat_dtype=torch.bfloat16)
+    say(f"dynamic bf16 features, iterates {iters}")
+    gpu = csc.DynamicCSC(2000, d, k, 0.5, m, seed=54, feat_dtype=torch.bfloat16, iter_dtype=iters)
     for g in seq:
         lab, lam, ref, cnt = gpu.step(csc.Graph.from_workload(g))
     A = oracle_A(seq[-1])
@@ -110,16 +112,18 @@ def test_lmax_estimate_is_upper_bound(csc):
     assert lam[-1] * 0.999 <= est <= 2.0
 
 
-@pytest.mark.parametrize("batch,use_graph", [(1, True), (3, False), (4, True)])
-def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph):
-    say(f"batched dynamic batch={batch} graph={use_graph}")
+@pytest.mark.parametrize("batch,use_graph,iters", [(1, True, torch.float32), (3, False, torch.float32),
+                                                   (4, True, torch.float32), (4, True, "bf16s")])
+def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph, iters):
+    say(f"batched dynamic batch={batch} graph={use_graph} iterates={iters}")
     k, m, d, seed = 4, 40, 32, 62
-    ref = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1)
+    ref = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1,
+                         iter_dtype=iters)
     G_ref = [csc.Graph.from_workload(g) for g in seq]
     ref_out = [ref.step(G) for G in G_ref]
     ref_theta = ref.features()
     bat = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1,
-                         batch=batch, use_graph=use_graph)
+                         batch=batch, use_graph=use_graph, iter_dtype=iters)
     G_bat = [csc.Graph.from_workload(g) for g in seq]
     labels, lams, refs, cnts = bat.steps(G_bat)
     for t in range(len(seq)):

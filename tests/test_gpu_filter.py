@@ -94,6 +94,29 @@ def test_filter_bf16_iterates_and_inputs(csc, c1):
     assert err <= 0.2
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_filter_bf16s_state_is_fp32(csc, c1, variant):
+    """BF16S: BF16 copies are gathered, the recurrence state stays FP32, so the error sits
+    well below that of BF16 iterates and the in-pass moments stay close to FP64."""
+    g, G, A = c1
+    say(f"filter bf16s variant={variant}")
+    X = gaussian_block(g.n, 64, 0.125, seed=10)
+    a = chebyshev.step_coefficients(50, 2.0, 0.43, "jackson")
+    Xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    ref = chebyshev.filter_recurrence(A, 2.0, a, Xb.float().cpu().numpy().astype(np.float64))
+    G.set_variant(variant, "bf16s")
+    G.set_variant(variant, torch.bfloat16)
+    Ys, mu = csc.cheb_filter(G, a, Xb, iter_dtype="bf16s", moments=True)
+    Yb = csc.cheb_filter(G, a, Xb, iter_dtype=torch.bfloat16)
+    es, eb = rel_fro(Ys.cpu().numpy(), ref), rel_fro(Yb.cpu().numpy(), ref)
+    mu_ref = eigcount.moments_direct(A, 2.0, 50, Xb.float().cpu().numpy().astype(np.float64))
+    em = np.max(np.abs(mu.cpu().numpy() - mu_ref)) / np.max(np.abs(mu_ref))
+    say(f"  bf16s rel err {es:.3e} (bf16 iterates {eb:.3e}); moments {em:.3e}")
+    G.set_variant(-1, torch.bfloat16)
+    assert es <= 2e-2 and es < eb
+    assert em <= 1e-3
+
+
 def test_filter_bf16_graph_values(csc):
     g = sbm(2000, 4, 12.0, 0.1, seed=77)
     A = oracle_A(g)
