@@ -105,10 +105,14 @@ def kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(digest: str, form: str):
-    """HBM bytes per step launch from the committed counter summary, if it was taken on
-    this exact kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_step_c3_traffic.json")
+def traffic_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"k_step_{workload}_traffic.json")
+
+
+def load_traffic(digest: str, form: str, workload: str = "c3"):
+    """HBM bytes per step launch from the committed counter summary of this workload, if it
+    was taken on this exact kernel source; else None."""
+    path = traffic_path(workload)
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -177,7 +181,8 @@ def run_probe(args):
     cap = max(g.nnz for g in seq)
     Gs = [csc.Graph(args.n, *(torch.from_numpy(a).to(dev) for a in (g.rowptr, g.colidx, g.w)),
                     val_dtype=vals, validate=False, nnz_capacity=cap) for g in seq]
-    dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(3, "signals"),
+    cid = 5 if args.workload == "c5" else 3
+    dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(cid, "signals"),
                          feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
                          use_graph=graph, keep_iterates=1 if batched else -1)
     dyn.step(Gs[0])
@@ -225,7 +230,7 @@ def traffic_summary(args):
     sel = lambda rows: [v for n, v in rows if kname in n and "<" in n]  # noqa: E731
     stf, stw = sel(fetch), sel(write)
     per_launch = (statistics.mean(stf) * sf + statistics.mean(stw) * sw) * 1024.0
-    path = os.path.join(ROOT, "profiles", "k_step_c3_traffic.json")
+    path = traffic_path(args.workload)
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -392,7 +397,7 @@ def run_dynamic(args):
             log(f"[bench] {form}: error {rec_err}")
 
     head = forms[args.headline]
-    traffic = load_traffic(digest, args.headline)
+    traffic = load_traffic(digest, args.headline, args.workload)
     achieved = head["step_kernel_gbps"]
     out = {
         "metric": "Chebyshev SpMM HBM GB/s (% peak) & ms/dynamic snapshot, BF16 vs FP32 at tol",

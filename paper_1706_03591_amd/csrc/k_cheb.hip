@@ -184,18 +184,19 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
   __syncthreads();
 
   const int64_t row = r0 + threadIdx.x / LPR;
+  const int grp = threadIdx.x / LPR;
   const int lane = threadIdx.x % LPR;
   const int64_t tile_off = tile * p.n * WT;  // elements
   const TG* zc = static_cast<const TG*>(p.zcur) + tile_off + lane * VEC;
   double d1 = 0.0, d2 = 0.0;
 
-  if (row < p.n) {
-    float acc[VEC];
+  float acc[VEC];
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) acc[i] = 0.f;
-    const int32_t rs = p.rowptr[row], re = p.rowptr[row + 1];
-    int32_t e = rs;
-    if (staged) {
+  for (int i = 0; i < VEC; ++i) acc[i] = 0.f;
+  if (staged) {
+    if (row < p.n) {
+      const int32_t rs = p.rowptr[row], re = p.rowptr[row + 1];
+      int32_t e = rs;
       for (; e + 4 <= re; e += 4) {
         const int32_t l = e - e0;
         const int32_t c0 = s_col[l], c1 = s_col[l + 1], c2 = s_col[l + 2], c3 = s_col[l + 3];
@@ -227,17 +228,65 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
 #pragma unroll
         for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v, f[i], acc[i]);
       }
-    } else {
-      for (; e < re; ++e) {
+    }
+  } else {
+    // Heavy block (more CSR entries than the LDS stage holds, e.g. the hubs of a power-law
+    // graph): its rows are taken one at a time by all RPB row groups, group g summing the
+    // entries rs + g, rs + g + RPB, ...; the partial sums meet in LDS (the unused stage) in
+    // group order, so the result does not depend on scheduling.
+    static_assert(kThreads * VEC <= kStageCap, "reduction buffer must fit the stage");
+    float* s_red = reinterpret_cast<float*>(s_col);  // RPB x LPR x VEC = kThreads * VEC floats
+    for (int rr = 0; rr < RPB && r0 + rr < p.n; ++rr) {
+      const int64_t rw = r0 + rr;
+      const int32_t rs = p.rowptr[rw], re = p.rowptr[rw + 1];
+      float part[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) part[i] = 0.f;
+      int32_t e = rs + grp;
+      for (; e + 3 * RPB < re; e += 4 * RPB) {
+        const int32_t c0 = p.colidx[e], c1 = p.colidx[e + RPB], c2 = p.colidx[e + 2 * RPB],
+                      c3 = p.colidx[e + 3 * RPB];
+        const float v0 = val_f<TV>(vals[e]), v1 = val_f<TV>(vals[e + RPB]),
+                    v2 = val_f<TV>(vals[e + 2 * RPB]), v3 = val_f<TV>(vals[e + 3 * RPB]);
+        const uint4 g0 = ld16(zc + static_cast<int64_t>(c0) * WT);
+        const uint4 g1 = ld16(zc + static_cast<int64_t>(c1) * WT);
+        const uint4 g2 = ld16(zc + static_cast<int64_t>(c2) * WT);
+        const uint4 g3 = ld16(zc + static_cast<int64_t>(c3) * WT);
+        float f[VEC];
+        P::unpack(g0, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v0, f[i], part[i]);
+        P::unpack(g1, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v1, f[i], part[i]);
+        P::unpack(g2, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v2, f[i], part[i]);
+        P::unpack(g3, f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v3, f[i], part[i]);
+      }
+      for (; e < re; e += RPB) {
         const uint4 g = ld16(zc + static_cast<int64_t>(p.colidx[e]) * WT);
         float f[VEC];
         P::unpack(g, f);
         const float v = val_f<TV>(vals[e]);
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v, f[i], acc[i]);
+        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v, f[i], part[i]);
       }
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) s_red[(grp * LPR + lane) * VEC + i] = part[i];
+      __syncthreads();
+      if (grp == rr) {
+        for (int g = 0; g < RPB; ++g)
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc[i] += s_red[(g * LPR + lane) * VEC + i];
+      }
+      __syncthreads();
     }
+  }
 
+  if (row < p.n) {
     const int64_t own = row * WT;  // element offset of this row within the tile
     const int64_t eoff = tile_off + lane * VEC + own;
     float zj[VEC];

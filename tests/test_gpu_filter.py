@@ -148,10 +148,20 @@ def test_heavy_rows_isolated_nodes_and_ragged_tail(csc):
     A = oracle_A(g)
     X = gaussian_block(n, 20, 0.3, seed=12)
     a = chebyshev.step_coefficients(30, 2.0, 0.6, "jackson")
+    ref = chebyshev.filter_recurrence(A, 2.0, a, X.astype(np.float64))
+    mu_ref = eigcount.moments_direct(A, 2.0, 30, X.astype(np.float64))
+    Xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    ref_b = chebyshev.filter_recurrence(A, 2.0, a, Xb.float().cpu().numpy().astype(np.float64))
     for variant in range(4):
         G.set_variant(variant)
-        Y = csc.cheb_filter(G, a, torch.from_numpy(X).cuda()).cpu().numpy()
-        assert rel_fro(Y, chebyshev.filter_recurrence(A, 2.0, a, X.astype(np.float64))) <= TOL_F32
+        Y, mu = csc.cheb_filter(G, a, torch.from_numpy(X).cuda(), moments=True)
+        assert rel_fro(Y.cpu().numpy(), ref) <= TOL_F32
+        assert np.max(np.abs(mu.cpu().numpy() - mu_ref)) <= 1e-5 * np.max(np.abs(mu_ref))
+        G.set_variant(variant, "bf16s")
+        Ys = csc.cheb_filter(G, a, Xb, iter_dtype="bf16s").cpu().numpy()
+        assert rel_fro(Ys, ref_b) <= 2e-2
+    G.set_variant(-1)
+    G.set_variant(-1, "bf16s")
 
 
 def test_moments_match_oracle(csc, c1):

@@ -283,15 +283,27 @@ class DynamicSBM:
 # Chung-Lu graph with planted communities
 
 
+def _sample_weighted(cdf: np.ndarray, count: int, rng) -> np.ndarray:
+    """``count`` i.i.d. indices with P(i) = cdf[i] - cdf[i-1] (cdf normalised to end at 1),
+    in random order.  The uniforms are searched in sorted order (NumPy's binary search then
+    starts from the previous hit) and the results shuffled."""
+    u = np.sort(rng.random(count))
+    idx = np.minimum(np.searchsorted(cdf, u, side="right"), cdf.size - 1)
+    return rng.permutation(idx)
+
+
 def chung_lu(n: int, k: int, mean_degree: float, exponent: float, ratio: float,
              seed: int) -> Graph:
     """Power-law expected degrees with planted communities.
 
     Expected-degree weights ``theta_i ∝ (i + i0) ** (-1 / (exponent - 1))`` scaled to the
     requested mean and capped at ``sqrt(sum theta)``; nodes are placed in k equal
-    communities at random.  Endpoints are drawn proportionally to theta and a pair in
-    different communities is kept with probability ``ratio``; duplicates and self-pairs
-    are dropped and the edge count is trimmed to ``n * mean_degree / 2``.
+    communities at random.  Candidate pairs follow P(a, b) ∝ theta_a theta_b w(a, b) with
+    w = 1 inside a community and ``ratio`` across: the within-community share of the
+    candidates is drawn first, then within-community endpoints from each community's
+    weights and cross-community endpoints from all weights (same-community draws redrawn).
+    Duplicates and self-pairs are dropped and the edge count is trimmed to
+    ``n * mean_degree / 2``.
     """
     rng = np.random.default_rng(seed)
     i0 = 10.0
@@ -301,24 +313,37 @@ def chung_lu(n: int, k: int, mean_degree: float, exponent: float, ratio: float,
     theta = np.minimum(theta, cap)
     theta *= mean_degree / theta.mean()
     comm = rng.permutation(np.repeat(np.arange(k, dtype=np.int32), (n + k - 1) // k)[:n])
+    target = int(n * mean_degree / 2)
     cdf = np.cumsum(theta)
     cdf /= cdf[-1]
-    target = int(n * mean_degree / 2)
-    psame = float(np.sum(np.bincount(comm, weights=theta) ** 2) / theta.sum() ** 2)
-    acc_rate = psame + ratio * (1.0 - psame)
+    members = [np.flatnonzero(comm == c) for c in range(k)]
+    ccdf = []
+    for mem in members:
+        w = np.cumsum(theta[mem])
+        ccdf.append(w / w[-1] if w.size else w)
+    S = np.array([theta[mem].sum() for mem in members])
+    m_in = float(np.sum(S * S))
+    m_out = ratio * (float(S.sum()) ** 2 - m_in)
+    p_in = m_in / (m_in + m_out)
     keys = np.zeros(0, dtype=np.int64)
     while keys.size < target:
-        sz = int((target - keys.size) / acc_rate * 1.1) + 1024
+        draw = int((target - keys.size) * 1.05) + 1024
+        n_in = int(rng.binomial(draw, p_in))
         chunks = []
-        step = 1 << 24
-        for s0 in range(0, sz, step):
-            c = min(step, sz - s0)
-            a = np.searchsorted(cdf, rng.random(c), side="right")
-            b = np.searchsorted(cdf, rng.random(c), side="right")
-            a = np.minimum(a, n - 1)
-            b = np.minimum(b, n - 1)
-            keep = (comm[a] == comm[b]) | (rng.random(c) < ratio)
-            chunks.append(_canon_unique(a[keep], b[keep], n))
+        per_c = rng.multinomial(n_in, S * S / m_in)
+        for c, cnt in enumerate(per_c):
+            if cnt == 0 or members[c].size < 2:
+                continue
+            a = members[c][_sample_weighted(ccdf[c], int(cnt), rng)]
+            b = members[c][_sample_weighted(ccdf[c], int(cnt), rng)]
+            chunks.append(_canon_unique(a, b, n))
+        need = draw - n_in
+        while need > 0:
+            a = _sample_weighted(cdf, need, rng)
+            b = _sample_weighted(cdf, need, rng)
+            cross = comm[a] != comm[b]
+            chunks.append(_canon_unique(a[cross], b[cross], n))
+            need -= int(cross.sum())
         keys = np.union1d(keys, np.concatenate(chunks))
     if keys.size > target:
         keys = np.sort(rng.choice(keys, size=target, replace=False))
@@ -348,11 +373,13 @@ def rewire_model_free(g: Graph, frac: float, seed: int, ratio: float) -> Graph:
     new = np.zeros(0, dtype=np.int64)
     while new.size < nrew:
         sz = 4 * (nrew - new.size) + 1024
-        a = np.minimum(np.searchsorted(cdf, rng.random(sz), side="right"), n - 1)
-        b = np.minimum(np.searchsorted(cdf, rng.random(sz), side="right"), n - 1)
+        a = _sample_weighted(cdf, sz, rng)
+        b = _sample_weighted(cdf, sz, rng)
         ok = (comm[a] == comm[b]) | (rng.random(sz) < ratio)
         cand = _canon_unique(a[ok], b[ok], n)
-        cand = cand[~np.isin(cand, keys, assume_unique=True)]
+        # keys is sorted: membership by binary search instead of a re-sort
+        pos = np.minimum(np.searchsorted(keys, cand), keys.size - 1)
+        cand = cand[keys[pos] != cand]
         new = np.union1d(new, cand)
     if new.size > nrew:
         new = rng.choice(new, size=nrew, replace=False)
