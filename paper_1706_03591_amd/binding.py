@@ -158,6 +158,13 @@ def workspace(nbytes: int, device=None) -> torch.Tensor:
     return buf
 
 
+def release_workspace():
+    """Drop the cached scratch buffers and return cached device memory to the driver (the
+    dynamic state sizes its kept basis from the free memory it sees)."""
+    _WS.clear()
+    torch.cuda.empty_cache()
+
+
 def version() -> int:
     return lib.csc_version()
 
@@ -454,6 +461,8 @@ class DynamicCSC:
                        iter_dt=_it(iter_dtype), keep_iterates=keep_iterates, batch=batch,
                        use_graph=int(bool(use_graph)), variant=int(variant))
         h = C.c_void_p()
+        if keep_iterates < 0:
+            release_workspace()
         _check(lib.csc_dyn_create(int(n), int(d), int(k), float(p), int(m), int(damping),
                                   _TORCH_DT[feat_dtype], int(seed), C.byref(opts), C.byref(h)))
         self.h = h

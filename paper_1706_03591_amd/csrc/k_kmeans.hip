@@ -316,7 +316,9 @@ inline size_t mf_lds_bytes(int DP, int kc_max) {
   return static_cast<size_t>(3) * kc_max * (DP + 8) * 2 + static_cast<size_t>(kc_max) * 16;
 }
 
-template <typename TF, int DP>
+// T row tiles per wave (T > 1 when the centroids need several LDS chunks: each staged chunk
+// then serves 64 T rows, dividing the re-staging traffic by T).
+template <typename TF, int DP, int T>
 __global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int64_t n, int d,
                                                    const uint16_t* parts, const double* cn_g,
                                                    const float* C, int k, int kp, int kc_max,
@@ -334,61 +336,67 @@ __global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int
   const int wave = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int nchunks = (kp + kc_max - 1) / kc_max;
-  const int64_t panels = (n + 63) / 64;
+  const int64_t panels = (n + 64 * T - 1) / (64 * T);
   const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
   double objsum = 0.0;
   bool staged = false;
   constexpr int RW = sizeof(TF) / 2;
-  // BF16 rows: the next panel's row is prefetched while the current one is scored (FP32
-  // rows already hold three split parts in registers; a prefetch costs occupancy there)
-  constexpr bool PF = sizeof(TF) == 2;
-  u32x4 raw[NS][RW];
+  // BF16 rows, one tile: the next panel's row is prefetched while the current one is scored
+  // (FP32 rows already hold three split parts in registers; a prefetch costs occupancy there)
+  constexpr bool PF = sizeof(TF) == 2 && T == 1;
+  auto row_of = [&](int64_t panel, int t) -> int64_t {
+    return ((panel * 4 + wave) * T + t) * 16 + li;
+  };
+  u32x4 raw[T][NS][RW];
   if constexpr (PF) {
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      load_raw8<TF>(F, ldf, n, d, (static_cast<int64_t>(blockIdx.x) * 4 + wave) * 16 + li,
-                    s * 32 + lq * 8, raw[s]);
+      load_raw8<TF>(F, ldf, n, d, row_of(blockIdx.x, 0), s * 32 + lq * 8, raw[0][s]);
   }
   for (int64_t panel = blockIdx.x; panel < panels; panel += gridDim.x) {
-    const int64_t row0 = (panel * 4 + wave) * 16;
-    const int64_t row = row0 + li;  // the row this lane scores (with the other three lanes lq)
-    const bool valid = row < n;
     if constexpr (!PF) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) load_raw8<TF>(F, ldf, n, d, row, s * 32 + lq * 8, raw[s]);
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          load_raw8<TF>(F, ldf, n, d, row_of(panel, t), s * 32 + lq * 8, raw[t][s]);
     }
-    double bl3[3] = {INFINITY, INFINITY, INFINITY};  // three smallest lower ends
-    int bi3[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
-    double um = INFINITY;                             // smallest upper end
+    double bl3[T][3], um[T], fnl[T];  // three smallest lower ends, smallest upper end, ||f||
+    int bi3[T][3];
     // B operand: row li, eight consecutive columns per step from 8 lq
-    bf16x8 a[NP][NS];
-    float fs = 0.f;
+    bf16x8 a[T][NP][NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      float v[8];
-      raw8_to_f<TF>(raw[s], v);
+    for (int t = 0; t < T; ++t) {
+      um[t] = INFINITY;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        fs = fmaf(v[e], v[e], fs);
-        if constexpr (NP == 1) {
-          a[0][s][e] = __builtin_bit_cast(__bf16, f32_to_bf16(v[e]));
-        } else {
-          uint16_t h, m, l;
-          split3(v[e], h, m, l);
-          a[0][s][e] = __builtin_bit_cast(__bf16, h);
-          a[1][s][e] = __builtin_bit_cast(__bf16, m);
-          a[2][s][e] = __builtin_bit_cast(__bf16, l);
+      for (int q = 0; q < 3; ++q) { bl3[t][q] = INFINITY; bi3[t][q] = 0x7fffffff; }
+      float fs = 0.f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        float v[8];
+        raw8_to_f<TF>(raw[t][s], v);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          fs = fmaf(v[e], v[e], fs);
+          if constexpr (NP == 1) {
+            a[t][0][s][e] = __builtin_bit_cast(__bf16, f32_to_bf16(v[e]));
+          } else {
+            uint16_t h, m, l;
+            split3(v[e], h, m, l);
+            a[t][0][s][e] = __builtin_bit_cast(__bf16, h);
+            a[t][1][s][e] = __builtin_bit_cast(__bf16, m);
+            a[t][2][s][e] = __builtin_bit_cast(__bf16, l);
+          }
         }
       }
+      fs += __shfl_xor(fs, 16, 64);
+      fs += __shfl_xor(fs, 32, 64);
+      fnl[t] = sqrt(static_cast<double>(fs)) * (1.0 + 0x1p-16);
     }
-    fs += __shfl_xor(fs, 16, 64);
-    fs += __shfl_xor(fs, 32, 64);
-    const double fnl = sqrt(static_cast<double>(fs)) * (1.0 + 0x1p-16);  // ||f|| of the row
     if (PF && panel + gridDim.x < panels) {
 #pragma unroll
       for (int s = 0; s < NS; ++s)
-        load_raw8<TF>(F, ldf, n, d, ((panel + gridDim.x) * 4 + wave) * 16 + li, s * 32 + lq * 8,
-                      raw[s]);
+        load_raw8<TF>(F, ldf, n, d, row_of(panel + gridDim.x, 0), s * 32 + lq * 8, raw[0][s]);
     }
     for (int chunk = 0; chunk < nchunks; ++chunk) {
       const int c0 = chunk * kc_max;
@@ -415,103 +423,115 @@ __global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int
       }
       for (int ct = 0; ct < kc / 16; ++ct) {
         // A operand: centroid ct*16 + li; output register r of lane (li, lq) is centroid
-        // ct*16 + 4 lq + r against row row0 + li
-        double dot[4] = {0.0, 0.0, 0.0, 0.0};
-        f32x4 small = zero4;
+        // ct*16 + 4 lq + r against row li of the tile
         const uint16_t* cb = s_cb + (ct * 16 + li) * SB + lq * 8;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          const bf16x8 ch = lds_bf8(cb + s * 32);
-          const bf16x8 cm = lds_bf8(cb + kc_max * SB + s * 32);
-          const bf16x8 cl = lds_bf8(cb + 2 * kc_max * SB + s * 32);
-          const f32x4 main = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[0][s], zero4, 0, 0, 0);
-          small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[0][s], small, 0, 0, 0);
-          small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[0][s], small, 0, 0, 0);
-          if constexpr (NP == 3) {
-            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[1][s], small, 0, 0, 0);
-            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[1][s], small, 0, 0, 0);
-            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[2][s], small, 0, 0, 0);
+        for (int t = 0; t < T; ++t) {
+          double dot[4] = {0.0, 0.0, 0.0, 0.0};
+          f32x4 small = zero4;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const bf16x8 ch = lds_bf8(cb + s * 32);
+            const bf16x8 cm = lds_bf8(cb + kc_max * SB + s * 32);
+            const bf16x8 cl = lds_bf8(cb + 2 * kc_max * SB + s * 32);
+            const f32x4 main = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][0][s], zero4, 0, 0, 0);
+            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][0][s], small, 0, 0, 0);
+            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[t][0][s], small, 0, 0, 0);
+            if constexpr (NP == 3) {
+              small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][1][s], small, 0, 0, 0);
+              small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][1][s], small, 0, 0, 0);
+              small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][2][s], small, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dot[r] += static_cast<double>(main[r]);
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) dot[r] += static_cast<double>(main[r]);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int lc = ct * 16 + mf_drow(r, lq);
-          const int cent = c0 + lc;
-          if (cent < k) {
-            const double cnv = s_cn[lc];
-            const double crv = s_cr[lc];
-            const double sc = cnv - 2.0 * (dot[r] + static_cast<double>(small[r]));
-            const double e = E2 * fnl * crv + 1e-13 * (cnv + fnl * crv);
-            um = fmin(um, sc + e);
-            // centroids arrive in increasing index order within a lane: strict < keeps ties
-            // on the lower index
-            const double lo = sc - e;
-            if (lo < bl3[2]) {
-              if (lo < bl3[1]) {
-                bl3[2] = bl3[1]; bi3[2] = bi3[1];
-                if (lo < bl3[0]) { bl3[1] = bl3[0]; bi3[1] = bi3[0]; bl3[0] = lo; bi3[0] = cent; }
-                else { bl3[1] = lo; bi3[1] = cent; }
-              } else {
-                bl3[2] = lo; bi3[2] = cent;
+          for (int r = 0; r < 4; ++r) {
+            const int lc = ct * 16 + mf_drow(r, lq);
+            const int cent = c0 + lc;
+            if (cent < k) {
+              const double cnv = s_cn[lc];
+              const double crv = s_cr[lc];
+              const double sc = cnv - 2.0 * (dot[r] + static_cast<double>(small[r]));
+              const double e = E2 * fnl[t] * crv + 1e-13 * (cnv + fnl[t] * crv);
+              um[t] = fmin(um[t], sc + e);
+              // centroids arrive in increasing index order within a lane: strict < keeps
+              // ties on the lower index
+              const double lo = sc - e;
+              double* b = bl3[t];
+              int* ix = bi3[t];
+              if (lo < b[2]) {
+                if (lo < b[1]) {
+                  b[2] = b[1]; ix[2] = ix[1];
+                  if (lo < b[0]) { b[1] = b[0]; ix[1] = ix[0]; b[0] = lo; ix[0] = cent; }
+                  else { b[1] = lo; ix[1] = cent; }
+                } else {
+                  b[2] = lo; ix[2] = cent;
+                }
               }
             }
           }
         }
       }
     }
-    // merge over the four lanes of the row (lq), in (value, index) order
 #pragma unroll
-    for (int off = 16; off < 64; off <<= 1) {
-      double ob[3];
-      int oi[3];
+    for (int t = 0; t < T; ++t) {
+      const int64_t row = row_of(panel, t);
+      const bool valid = row < n;
+      double* b = bl3[t];
+      int* ix = bi3[t];
+      // merge over the four lanes of the row (lq), in (value, index) order
 #pragma unroll
-      for (int q = 0; q < 3; ++q) { ob[q] = __shfl_xor(bl3[q], off, 64); oi[q] = __shfl_xor(bi3[q], off, 64); }
+      for (int off = 16; off < 64; off <<= 1) {
+        double ob[3];
+        int oi[3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) top3_insert(bl3, bi3, ob[q], oi[q]);
-      um = fmin(um, __shfl_xor(um, off, 64));
-    }
-    // candidates: lower end not above the smallest upper end (the first always is)
-    const bool certain = !valid || bi3[1] >= k || bl3[1] > um;
-    const bool pair = !certain && (bi3[2] >= k || bl3[2] > um);
-    int lab = bi3[0] < k ? bi3[0] : 0;  // (no candidate only with NaN features)
-    double best = 0.0;
-    if (!certain) {
-      // FP64 direct form against the candidates (the two best, else every centroid); the
-      // four lanes of the row split the columns
-      const int nc = pair ? 2 : k;
-      double be = INFINITY;
-      int bl = 0x7fffffff;
-      for (int q = 0; q < nc; ++q) {
-        const int c = pair ? (q == 0 ? bi3[0] : bi3[1]) : q;
+        for (int q = 0; q < 3; ++q) { ob[q] = __shfl_xor(b[q], off, 64); oi[q] = __shfl_xor(ix[q], off, 64); }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) top3_insert(b, ix, ob[q], oi[q]);
+        um[t] = fmin(um[t], __shfl_xor(um[t], off, 64));
+      }
+      // candidates: lower end not above the smallest upper end (the first always is)
+      const bool certain = !valid || ix[1] >= k || b[1] > um[t];
+      const bool pair = !certain && (ix[2] >= k || b[2] > um[t]);
+      int lab = ix[0] < k ? ix[0] : 0;  // (no candidate only with NaN features)
+      double best = 0.0;
+      if (!certain) {
+        // FP64 direct form against the candidates (the two best, else every centroid); the
+        // four lanes of the row split the columns
+        const int nc = pair ? 2 : k;
+        double be = INFINITY;
+        int bl = 0x7fffffff;
+        for (int q = 0; q < nc; ++q) {
+          const int c = pair ? (q == 0 ? ix[0] : ix[1]) : q;
+          double e = 0.0;
+          for (int col = lq; col < d; col += 4) {
+            const double tv = static_cast<double>(to_f<TF>(F[row * ldf + col])) -
+                              static_cast<double>(C[static_cast<int64_t>(c) * d + col]);
+            e += tv * tv;
+          }
+          e += __shfl_xor(e, 16, 64);
+          e += __shfl_xor(e, 32, 64);
+          if (sc_less(e, c, be, bl)) { be = e; bl = c; }
+        }
+        lab = bl;
+        best = be;
+      } else if (valid && (best_d2 || obj_part)) {
         double e = 0.0;
         for (int col = lq; col < d; col += 4) {
           const double tv = static_cast<double>(to_f<TF>(F[row * ldf + col])) -
-                            static_cast<double>(C[static_cast<int64_t>(c) * d + col]);
+                            static_cast<double>(C[static_cast<int64_t>(lab) * d + col]);
           e += tv * tv;
         }
         e += __shfl_xor(e, 16, 64);
         e += __shfl_xor(e, 32, 64);
-        if (sc_less(e, c, be, bl)) { be = e; bl = c; }
+        best = e;
       }
-      lab = bl;
-      best = be;
-    } else if (valid && (best_d2 || obj_part)) {
-      double e = 0.0;
-      for (int col = lq; col < d; col += 4) {
-        const double tv = static_cast<double>(to_f<TF>(F[row * ldf + col])) -
-                          static_cast<double>(C[static_cast<int64_t>(lab) * d + col]);
-        e += tv * tv;
+      if (valid && lq == 0) {
+        labels[row] = lab;
+        if (best_d2) best_d2[row] = static_cast<float>(best);
+        objsum += best;
       }
-      e += __shfl_xor(e, 16, 64);
-      e += __shfl_xor(e, 32, 64);
-      best = e;
-    }
-    if (valid && lq == 0) {
-      labels[row] = lab;
-      if (best_d2) best_d2[row] = static_cast<float>(best);
-      objsum += best;
     }
   }
   if (obj_part) {
@@ -648,18 +668,39 @@ __global__ void k_pp_first(const TF* F, int64_t ldf, int64_t n, int d, const dou
   for (int t = threadIdx.x; t < d; t += blockDim.x) C[t] = to_f<TF>(F[i * ldf + t]);
 }
 
-// d2[i] = min(d2[i], ||f_i - Cj||^2) in FP64 (first round: the distance itself).  Block b
-// covers the contiguous rows [b * kThreads * kRIT, ...) and writes their sum to bsum[b].
-// Sixteen lanes share a row so that each load instruction reads whole rows (16-byte pieces
-// of four rows per wave); the lanes' partial sums meet in a fixed shuffle tree.
+// cd[a] = ||C_cj - C_a||^2 (FP64) for the earlier centres a < cj; one thread per centre.
+__global__ void k_pp_cdist(const float* C, int d, int cj, double* cd) {
+  for (int a = threadIdx.x; a < cj; a += blockDim.x) {
+    double q = 0.0;
+    for (int t = 0; t < d; ++t) {
+      const double v = static_cast<double>(C[static_cast<int64_t>(cj) * d + t]) -
+                       static_cast<double>(C[static_cast<int64_t>(a) * d + t]);
+      q += v * v;
+    }
+    cd[a] = q;
+  }
+}
+
+// d2[i] = min(d2[i], ||f_i - C_cj||^2) in FP64 (first round: the distance itself), owner[i]
+// = the centre that attains it.  Block b covers the contiguous rows [b * kThreads * kRIT, ...)
+// and writes their sum to bsum[b].  A row is skipped without reading it when
+// ||C_cj - C_owner||^2 >= 4 d2 (1 + 1e-9): by the triangle inequality the new centre is then
+// no closer, so the result equals the unpruned pass (the margin covers the FP64 rounding of
+// both sides).  Sixteen lanes share a row so that each load instruction reads whole rows; the
+// lanes' partial sums meet in a fixed shuffle tree.
 template <typename TF, bool VEC, int NPC>
 __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, int64_t n, int d,
-                                                      int dp, const float* Cj, int first,
+                                                      int dp, const float* C, int cj, int first,
+                                                      const double* cd, int32_t* owner,
                                                       double* d2, double* bsum) {
   constexpr int V = 16 / sizeof(TF);  // values per 16-byte piece; a lane reads NPC pieces
   constexpr int U = VEC ? 8 : 2;      // rows per group in flight
   __shared__ float s_cj[256];
+  __shared__ double s_cd[256];
+  const float* Cj = C + static_cast<int64_t>(cj) * d;
   for (int t = threadIdx.x; t < dp; t += kThreads) s_cj[t] = t < d ? Cj[t] : 0.f;
+  if (!first)
+    for (int t = threadIdx.x; t < cj; t += kThreads) s_cd[t] = cd[t];
   __syncthreads();
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kRIT;
   const int l16 = threadIdx.x & 15;
@@ -667,19 +708,27 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
   double local = 0.0;
   for (int q0 = 0; q0 < kThreads * kRIT / 16; q0 += U) {
     uint4 raw[U][NPC];
+    bool need[U];
+    double dold[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t row = base + (q0 + u) * 16 + grp;
+      need[u] = row < n;
+      dold[u] = 0.0;
+      if (!first && row < n) {
+        dold[u] = d2[row];
+        need[u] = !(s_cd[owner[row]] >= 4.0 * dold[u] * (1.0 + 1e-9));
+      }
       const TF* rowp = F + (row < n ? row : 0) * ldf;
 #pragma unroll
       for (int pc = 0; pc < NPC; ++pc) {
         const int c0 = (pc * 16 + l16) * V;
-        if (row < n && VEC && c0 + V <= d) {
+        if (need[u] && VEC && c0 + V <= d) {
           raw[u][pc] = *reinterpret_cast<const uint4*>(rowp + c0);
         } else {
           TF tmp[V];
 #pragma unroll
-          for (int i = 0; i < V; ++i) tmp[i] = (row < n && c0 + i < d) ? rowp[c0 + i] : TF(0);
+          for (int i = 0; i < V; ++i) tmp[i] = (need[u] && c0 + i < d) ? rowp[c0 + i] : TF(0);
           __builtin_memcpy(&raw[u][pc], tmp, 16);
         }
       }
@@ -688,34 +737,44 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
     for (int u = 0; u < U; ++u) {
       const int64_t row = base + (q0 + u) * 16 + grp;
       double s = 0.0;
+      if (need[u]) {
 #pragma unroll
-      for (int pc = 0; pc < NPC; ++pc) {
-        const int c0 = (pc * 16 + l16) * V;
-        const uint32_t w[4] = {raw[u][pc].x, raw[u][pc].y, raw[u][pc].z, raw[u][pc].w};
-        float f[V];
-        if constexpr (sizeof(TF) == 4) {
+        for (int pc = 0; pc < NPC; ++pc) {
+          const int c0 = (pc * 16 + l16) * V;
+          const uint32_t w[4] = {raw[u][pc].x, raw[u][pc].y, raw[u][pc].z, raw[u][pc].w};
+          float f[V];
+          if constexpr (sizeof(TF) == 4) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(w[i]);
-        } else {
+            for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(w[i]);
+          } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            f[2 * i] = __uint_as_float(w[i] << 16);
-            f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+            for (int i = 0; i < 4; ++i) {
+              f[2 * i] = __uint_as_float(w[i] << 16);
+              f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+            }
           }
-        }
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          if (c0 + i < d) {
-            const double t = static_cast<double>(f[i]) - static_cast<double>(s_cj[c0 + i]);
-            s += t * t;
+          for (int i = 0; i < V; ++i) {
+            if (c0 + i < d) {
+              const double t = static_cast<double>(f[i]) - static_cast<double>(s_cj[c0 + i]);
+              s += t * t;
+            }
           }
         }
       }
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 16);
       if (row < n && l16 == 0) {
-        const double v = first ? s : fmin(d2[row], s);
-        d2[row] = v;
+        double v = dold[u];
+        if (first) {
+          v = s;
+          d2[row] = v;
+          owner[row] = 0;
+        } else if (need[u] && s < v) {
+          v = s;
+          d2[row] = v;
+          owner[row] = cj;
+        }
         local += v;
       }
     }
@@ -824,7 +883,7 @@ int64_t assign_blocks(int64_t n) {
 
 struct KmLayout {
   size_t off_u, off_d2, off_bsum, off_sums, off_cnt, off_max, off_obj, off_objv, off_sel, off_cp,
-      total;
+      off_own, off_cd, total;
 };
 
 int padded_k(int k) { return (k + kKG - 1) / kKG * kKG; }
@@ -843,6 +902,8 @@ KmLayout km_layout(int64_t n, int d, int k) {
   L.off_objv = off; off += align_up(static_cast<size_t>(1024 + 1) * 8);
   L.off_sel = off; off += 256;
   L.off_cp = off; off += align_up(assign_scratch_bytes(k, d));
+  L.off_own = off; off += align_up(static_cast<size_t>(n) * 4);
+  L.off_cd = off; off += align_up(static_cast<size_t>(k) * 8);
   L.total = off;
   return L;
 }
@@ -900,15 +961,16 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
 size_t kmeans_workspace(int64_t n, int d, int k) { return km_layout(n, d, k).total; }
 
 // Launch plan of the MFMA assignment for (n, d, k); DP == 0 when it does not apply (d > 256).
-// Chunks of kc centroids fill at most 64 KiB of LDS; one 16-row tile per wave (T = 1: two
-// tiles in flight spill registers at DP = 256).
+// Chunks of kc centroids fill at most 64 KiB of LDS.  One 16-row tile per wave when all
+// centroids fit one chunk (staged once per block); two when they do not (BF16 rows), so that
+// each re-staged chunk serves 128 rows.
 struct MfPlan {
   int DP = 0, kp = 0, kc = 0, T = 1;
   size_t lds = 0;
   int64_t blocks = 1;
 };
 
-MfPlan mf_plan(int64_t n, int d, int k) {
+MfPlan mf_plan(int64_t n, int d, int k, bool bf16_rows = false) {
   MfPlan P;
   if (d > 256) return P;
   int DP = 32;
@@ -919,7 +981,7 @@ MfPlan mf_plan(int64_t n, int d, int k) {
   P.DP = DP;
   P.kp = kp;
   P.kc = kc;
-  P.T = 1;
+  P.T = (bf16_rows && kc < kp) ? 2 : 1;
   P.lds = mf_lds_bytes(DP, kc);
   const int64_t panels = (n + 64 * P.T - 1) / (64 * P.T);
   const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / static_cast<int64_t>(P.lds)));
@@ -939,14 +1001,14 @@ size_t assign_scratch_bytes(int k, int d) {
 }
 
 int64_t assign_parts(int64_t n, int d, int k, const void* F, csc_dtype f_dt, int64_t ldf) {
-  const MfPlan P = mf_plan(n, d, k);
+  const MfPlan P = mf_plan(n, d, k, f_dt == CSC_BF16);
   return (P.DP && rows_aligned(F, f_dt, ldf)) ? P.blocks : assign_blocks(n);
 }
 
 static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                               const float* C, int k, int32_t* labels, float* best_d2,
                               double* obj_part, float* Cp, hipStream_t s) {
-  const MfPlan P = mf_plan(n, d, k);
+  const MfPlan P = mf_plan(n, d, k, f_dt == CSC_BF16);
   if (P.DP && rows_aligned(F, f_dt, ldf)) {
     auto* parts = reinterpret_cast<uint16_t*>(Cp);
     auto* cn = reinterpret_cast<double*>(reinterpret_cast<char*>(Cp) +
@@ -956,7 +1018,7 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
     hipLaunchKernelGGL(k_centroid_norms, dim3((P.kp + 63) / 64), dim3(64), 0, s, C, k, d, P.kp, cn);
     const unsigned blocks = static_cast<unsigned>(P.blocks);
 #define CSC_MF(TF, DPV, TV)                                                                        \
-  hipLaunchKernelGGL((k_assign_mf<TF, DPV>), dim3(blocks), dim3(256), P.lds, s,                   \
+  hipLaunchKernelGGL((k_assign_mf<TF, DPV, TV>), dim3(blocks), dim3(256), P.lds, s,               \
                      static_cast<const TF*>(F), ldf, n, d, parts, cn, C, k, P.kp, P.kc, labels,   \
                      best_d2, obj_part)
 #define CSC_MF_DP(TF, TV)                    \
@@ -966,7 +1028,9 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
     case 128: CSC_MF(TF, 128, TV); break;    \
     default: CSC_MF(TF, 256, TV); break;     \
   }
-    if (f_dt == CSC_F32) { CSC_MF_DP(float, 1) } else { CSC_MF_DP(uint16_t, 1) }
+    if (f_dt == CSC_F32) { CSC_MF_DP(float, 1) }
+    else if (P.T == 1) { CSC_MF_DP(uint16_t, 1) }
+    else { CSC_MF_DP(uint16_t, 2) }
 #undef CSC_MF_DP
 #undef CSC_MF
     CSC_HIP(hipGetLastError());
@@ -1043,7 +1107,7 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   const int npc = (d + (f32 ? 63 : 127)) / (f32 ? 64 : 128);  // 16-byte pieces per lane
 #define CSC_PPD_N(TF, V, NP)                                                                       \
   hipLaunchKernelGGL((k_pp_dist<TF, V, NP>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), 0, \
-                     s, static_cast<const TF*>(F), ldf, n, d, dp, Cj, first, d2, bsum)
+                     s, static_cast<const TF*>(F), ldf, n, d, dp, C, j - 1, first, cd, own, d2, bsum)
 #define CSC_PPD(TF, V)                               \
   switch (npc) {                                     \
     case 1: CSC_PPD_N(TF, V, 1); break;              \
@@ -1053,9 +1117,11 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   }
 #define CSC_PPD16(V)                                 \
   if (npc == 1) { CSC_PPD_N(uint16_t, V, 1); } else { CSC_PPD_N(uint16_t, V, 2); }
+  int32_t* own = reinterpret_cast<int32_t*>(base + L.off_own);
+  double* cd = reinterpret_cast<double*>(base + L.off_cd);
   for (int j = 1; j < k; ++j) {
-    const float* Cj = C + static_cast<int64_t>(j - 1) * d;
     const int first = j == 1 ? 1 : 0;
+    if (!first) hipLaunchKernelGGL(k_pp_cdist, dim3(1), dim3(256), 0, s, C, d, j - 1, cd);
     if (f32) {
       if (vec) { CSC_PPD(float, true) } else { CSC_PPD(float, false) }
       hipLaunchKernelGGL(k_pp_pick<float>, dim3(1), dim3(1024), 0, s, static_cast<const float*>(F), ldf,

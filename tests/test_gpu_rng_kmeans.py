@@ -63,10 +63,14 @@ def test_assign_exact_ties_lowest_index(csc):
     assert lab.cpu().tolist() == [1, 0, 0]
 
 
-def test_assign_bf16_features(csc):
-    F = _mixture(4000, 64, 8, seed=3)
+@pytest.mark.parametrize("n,d,k", [(4000, 64, 8), (20011, 128, 50), (3000, 256, 200), (9001, 48, 150)])
+def test_assign_bf16_features(csc, n, d, k):
+    # (3000, 256, 200) and (9001, 48, 150) need several LDS chunks of centroids (two row tiles
+    # per wave)
+    say(f"kmeans assign bf16 n={n} d={d} k={k}")
+    F = _mixture(n, d, max(k, 2), seed=3)
     Fb = torch.from_numpy(F).cuda().to(torch.bfloat16)
-    C = F[:8].copy()
+    C = F[np.random.default_rng(4).choice(n, size=k, replace=False)] + 0.01
     lab, _ = csc.kmeans_assign(Fb, torch.from_numpy(C).cuda())
     F64 = Fb.double().cpu().numpy()
     ref, _ = okm.assign(F64, C.astype(np.float64))
