@@ -558,10 +558,16 @@ def run_adjoint(args):
     # backward: checkpointed forward (3 streams + G read per step), segment recompute (same),
     # adjoint steps (2 gathers + 2 streams + G read + one dA read-modify-write per entry)
     bwd = args.m * (nnz * 8 + nw * 16) * 2 + args.m * (nnz * 16 + nw * 20)
+    rate = (fwd + bwd) / wall / 1e9
     _line(args, "Chebyshev filter forward+backward: algorithmic GB/s & ms per pair",
-          (fwd + bwd) / wall / 1e9, "GB/s", wall * 1e3,
+          rate, "GB/s", wall * 1e3,
           {"config": {"workload": f"SBM N={args.n}, k={args.k}, degree 20; w={args.d}, m={args.m}, "
-                                  f"checkpoint every 8 iterates; dX, da and dA", "nnz": nnz}})
+                                  f"checkpoint every 8 iterates; dX, da and dA", "nnz": nnz},
+           "roofline": {"bound": "hbm", "kernel": "forward steps + checkpointed recompute + fused "
+                                                  "adjoint (whole pair)",
+                        "achieved": round(rate, 1), "peak": PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(rate / PEAK_GBPS, 4), "traffic": None,
+                        "algorithmic_bytes": round(fwd + bwd)}})
 
 
 if __name__ == "__main__":

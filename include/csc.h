@@ -201,8 +201,9 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  * race.  Asynchronous.
  *
  * csc_kmeans_update: C[c] = mean of the rows labelled c; an empty cluster keeps its
- * previous centroid (C is read and overwritten); counts: device int32[k] or NULL.
- * Fixed-order reduction.  work: csc_kmeans_workspace_bytes(n, d, k).  Asynchronous.
+ * previous centroid (C is read and overwritten); rows whose label is outside [0, k) are
+ * ignored; counts: device int32[k] or NULL.  Sums in 64-bit fixed point (order-independent,
+ * bit-reproducible).  work: csc_kmeans_workspace_bytes(n, d, k).  Asynchronous.
  *
  * csc_kmeans_seed: k-means++ (Arthur and Vassilvitskii, 2007) driven by the device
  * uniforms u[0..k-1]: the first centre is row floor(u[0] n); centre j is the first row

@@ -210,17 +210,18 @@ __global__ void k_prep_centroids(const float* C, int k, int d, int kp, int DP, u
   parts[2 * static_cast<int64_t>(kp) * DP + t] = l;
 }
 
-// cn[c] = ||C_c||^2 in FP64 for c < k, +inf for the padding up to kp.
+// cn[c] = ||C_c||^2 in FP64 for c < k, +inf for the padding up to kp; one wave per centroid.
 __global__ void k_centroid_norms(const float* C, int k, int d, int kp, double* cn) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= kp) return;
+  const int c = blockIdx.x;
   double q = 0.0;
   if (c < k)
-    for (int col = 0; col < d; ++col) {
+    for (int col = threadIdx.x; col < d; col += 64) {
       const double v = static_cast<double>(C[static_cast<int64_t>(c) * d + col]);
       q += v * v;
     }
-  cn[c] = c < k ? q : INFINITY;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+  if (threadIdx.x == 0) cn[c] = c < k ? q : INFINITY;
 }
 
 // eight consecutive values of row `row` from column col (zeros past d or n)
@@ -583,51 +584,131 @@ __global__ void k_maxabs(const TF* F, int64_t ldf, int64_t n, int d, uint32_t* o
   if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
-// Block (b, y): rows [b * rpb, ...), columns [y * cw, y * cw + cw).  LDS holds the k x cw
-// fixed-point sums; thread groups take interleaved rows; integer atomics make the result
-// independent of the order.
+// Block (b, y): rows [b * rpb, ...), columns [y * cw, y * cw + cw).  The
+// block first orders its rows by label in LDS (counting sort), then each group of cw lanes
+// walks a contiguous stretch of that order, summing runs of equal labels in registers and
+// adding each run to the LDS sums with one integer atomic per column.  The sums are 64-bit
+// fixed point, so neither the order inside a label nor the order of the atomics changes them.
+constexpr int kUpdRows = 1024;
+
 template <typename TF>
 __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, int64_t n, int d,
                                                       const int32_t* labels, int k, int64_t rpb,
                                                       int cw, const uint32_t* maxabs,
                                                       unsigned long long* gsums, int32_t* gcnt) {
-  extern __shared__ unsigned long long s_acc[];  // k * cw, then k ints
+  // LDS: k * cw sums, then k counts, k offsets, rpb labels, rpb row order
+  extern __shared__ unsigned long long s_acc[];
   int32_t* s_cnt = reinterpret_cast<int32_t*>(s_acc + static_cast<size_t>(k) * cw);
+  int32_t* s_off = s_cnt + k;
+  int32_t* s_lab = s_off + k;
+  int32_t* s_perm = s_lab + rpb;
   for (int t = threadIdx.x; t < k * cw; t += kThreads) s_acc[t] = 0ull;
   for (int t = threadIdx.x; t < k; t += kThreads) s_cnt[t] = 0;
   __syncthreads();
   const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
-  const int groups = kThreads / cw;
-  const int g = threadIdx.x / cw;
-  const int cl = threadIdx.x % cw;
-  const int col = blockIdx.y * cw + cl;
-  const bool colok = col < d;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rpb;
-  const int64_t r1 = min(r0 + rpb, n);
-  const bool counter = cl == 0 && blockIdx.y == 0;
-  int64_t r = r0 + g;
-  for (; r + 3 * groups < r1; r += 4 * groups) {
+  const int nr = static_cast<int>(max<int64_t>(0, min(r0 + rpb, n) - r0));
+  __shared__ int s_nv;
+  for (int i = threadIdx.x; i < nr; i += kThreads) {
+    int lb = labels[r0 + i];
+    if (lb < 0 || lb >= k) lb = -1;  // out-of-range labels are ignored
+    s_lab[i] = lb;
+    if (lb >= 0) atomicAdd(&s_cnt[lb], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int c = 0; c < k; ++c) { s_off[c] = run; run += s_cnt[c]; }
+    s_nv = run;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr; i += kThreads)
+    if (s_lab[i] >= 0) s_perm[atomicAdd(&s_off[s_lab[i]], 1)] = i;
+  __syncthreads();
+  const int nv = s_nv;
+  // a lane owns 8 consecutive columns; LR lanes cover the block's cw columns of one row, and
+  // the kThreads / LR row slots split the label-ordered rows into contiguous stretches
+  const int LR = cw / 8;
+  const int slots = kThreads / LR;
+  const int slot = threadIdx.x / LR;
+  const int c8 = (threadIdx.x % LR) * 8;
+  const int col0 = blockIdx.y * cw + c8;
+  const bool vec = sizeof(TF) * 8 % 16 == 0 && col0 + 8 <= d &&
+                   reinterpret_cast<uintptr_t>(F) % 16 == 0 && (ldf * sizeof(TF)) % 16 == 0;
+  const int per = (nv + slots - 1) / slots;
+  const int q0 = slot * per, q1 = min(nv, q0 + per);
+  int cur = -1;
+  long long run[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) run[i] = 0;
+  auto flush = [&]() {
+    if (cur < 0) return;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (run[i] != 0 && c8 + i < cw)
+        atomicAdd(&s_acc[cur * cw + c8 + i], static_cast<unsigned long long>(run[i]));
+  };
+  auto load8v = [&](int ii, float* v) {
+    const TF* rp = F + (r0 + ii) * ldf + col0;
+    if (vec) {
+      if constexpr (sizeof(TF) == 4) {
+        const uint4 u0 = reinterpret_cast<const uint4*>(rp)[0];
+        const uint4 u1 = reinterpret_cast<const uint4*>(rp)[1];
+        v[0] = __uint_as_float(u0.x); v[1] = __uint_as_float(u0.y);
+        v[2] = __uint_as_float(u0.z); v[3] = __uint_as_float(u0.w);
+        v[4] = __uint_as_float(u1.x); v[5] = __uint_as_float(u1.y);
+        v[6] = __uint_as_float(u1.z); v[7] = __uint_as_float(u1.w);
+      } else {
+        const uint4 u = reinterpret_cast<const uint4*>(rp)[0];
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          v[2 * i] = __uint_as_float(w[i] << 16);
+          v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = col0 + i < d ? to_f<TF>(rp[i]) : 0.f;
+    }
+  };
+  int q = q0;
+  for (; q + 4 <= q1; q += 4) {
     int lb[4];
-    float v[4];
+    float v[4][8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      lb[q] = labels[r + q * groups];
-      v[q] = colok ? to_f<TF>(F[(r + q * groups) * ldf + col]) : 0.f;
+    for (int u = 0; u < 4; ++u) {
+      const int ii = s_perm[q + u];
+      lb[u] = s_lab[ii];
+      load8v(ii, v[u]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long long fx = llrint(ldexp(static_cast<double>(v[q]), S));
-      atomicAdd(&s_acc[lb[q] * cw + cl], static_cast<unsigned long long>(fx));
-      if (counter) atomicAdd(&s_cnt[lb[q]], 1);
+    for (int u = 0; u < 4; ++u) {
+      if (lb[u] != cur) {
+        flush();
+        cur = lb[u];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) run[i] = 0;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[u][i]), S));
     }
   }
-  for (; r < r1; r += groups) {
-    const int lb = labels[r];
-    const float v = colok ? to_f<TF>(F[r * ldf + col]) : 0.f;
-    const long long fx = llrint(ldexp(static_cast<double>(v), S));
-    atomicAdd(&s_acc[lb * cw + cl], static_cast<unsigned long long>(fx));
-    if (counter) atomicAdd(&s_cnt[lb], 1);
+  for (; q < q1; ++q) {
+    const int ii = s_perm[q];
+    const int lb = s_lab[ii];
+    float v[8];
+    load8v(ii, v);
+    if (lb != cur) {
+      flush();
+      cur = lb;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) run[i] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[i]), S));
   }
+  flush();
   __syncthreads();
   for (int t = threadIdx.x; t < k * cw; t += kThreads) {
     const int c = t / cw, cc = t % cw;
@@ -668,17 +749,19 @@ __global__ void k_pp_first(const TF* F, int64_t ldf, int64_t n, int d, const dou
   for (int t = threadIdx.x; t < d; t += blockDim.x) C[t] = to_f<TF>(F[i * ldf + t]);
 }
 
-// cd[a] = ||C_cj - C_a||^2 (FP64) for the earlier centres a < cj; one thread per centre.
+// cd[a] = ||C_cj - C_a||^2 (FP64) for the earlier centres a < cj; one wave per centre,
+// lanes over the columns, fixed shuffle tree.
 __global__ void k_pp_cdist(const float* C, int d, int cj, double* cd) {
-  for (int a = threadIdx.x; a < cj; a += blockDim.x) {
-    double q = 0.0;
-    for (int t = 0; t < d; ++t) {
-      const double v = static_cast<double>(C[static_cast<int64_t>(cj) * d + t]) -
-                       static_cast<double>(C[static_cast<int64_t>(a) * d + t]);
-      q += v * v;
-    }
-    cd[a] = q;
+  const int a = blockIdx.x;
+  double q = 0.0;
+  for (int t = threadIdx.x; t < d; t += 64) {
+    const double v = static_cast<double>(C[static_cast<int64_t>(cj) * d + t]) -
+                     static_cast<double>(C[static_cast<int64_t>(a) * d + t]);
+    q += v * v;
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+  if (threadIdx.x == 0) cd[a] = q;
 }
 
 // d2[i] = min(d2[i], ||f_i - C_cj||^2) in FP64 (first round: the distance itself), owner[i]
@@ -940,9 +1023,12 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
                          static_cast<const uint16_t*>(F), ldf, n, d, mx);
   }
   const int cw = k <= 112 ? 64 : 32;
-  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(2048, (n + 511) / 512));
-  const int64_t rpb = (n + nblk - 1) / nblk;
-  const size_t lds = static_cast<size_t>(k) * cw * 8 + static_cast<size_t>(k) * 4;
+  // rows per block: up to kUpdRows, within 64 KiB of LDS next to the k x cw sums
+  const size_t fixed_lds = static_cast<size_t>(k) * cw * 8 + static_cast<size_t>(k) * 8;
+  const int64_t cap = std::min<int64_t>(kUpdRows, static_cast<int64_t>((64 * 1024 - fixed_lds) / 8));
+  const int64_t nblk = std::max<int64_t>(1, (n + cap - 1) / cap);
+  const int64_t rpb = (n + nblk - 1) / nblk;  // <= cap
+  const size_t lds = fixed_lds + static_cast<size_t>(rpb) * 8;
   const dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>((d + cw - 1) / cw));
   if (f_dt == CSC_F32)
     hipLaunchKernelGGL(k_upd_acc<float>, grid, dim3(kThreads), lds, s, static_cast<const float*>(F),
@@ -1015,7 +1101,7 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
                                          align_up(static_cast<size_t>(3) * P.kp * P.DP * 2));
     hipLaunchKernelGGL(k_prep_centroids, dim3((P.kp * P.DP + 255) / 256), dim3(256), 0, s, C, k, d,
                        P.kp, P.DP, parts);
-    hipLaunchKernelGGL(k_centroid_norms, dim3((P.kp + 63) / 64), dim3(64), 0, s, C, k, d, P.kp, cn);
+    hipLaunchKernelGGL(k_centroid_norms, dim3(P.kp), dim3(64), 0, s, C, k, d, P.kp, cn);
     const unsigned blocks = static_cast<unsigned>(P.blocks);
 #define CSC_MF(TF, DPV, TV)                                                                        \
   hipLaunchKernelGGL((k_assign_mf<TF, DPV, TV>), dim3(blocks), dim3(256), P.lds, s,               \
@@ -1121,7 +1207,7 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   double* cd = reinterpret_cast<double*>(base + L.off_cd);
   for (int j = 1; j < k; ++j) {
     const int first = j == 1 ? 1 : 0;
-    if (!first) hipLaunchKernelGGL(k_pp_cdist, dim3(1), dim3(256), 0, s, C, d, j - 1, cd);
+    if (!first) hipLaunchKernelGGL(k_pp_cdist, dim3(j - 1), dim3(64), 0, s, C, d, j - 1, cd);
     if (f32) {
       if (vec) { CSC_PPD(float, true) } else { CSC_PPD(float, false) }
       hipLaunchKernelGGL(k_pp_pick<float>, dim3(1), dim3(1024), 0, s, static_cast<const float*>(F), ldf,

@@ -81,6 +81,32 @@ def test_adjoint_matches_oracle(csc, m, w, ckpt):
         assert np.all(dA.cpu().numpy() == 0)
 
 
+def test_adjoint_c4_full_size_sampled_columns(csc):
+    """C4 at full size (SBM N=200k, degree 20, w=64, m=60, checkpoints every 8 iterates):
+    the adjoint is column-separable, so the 64-column run is checked on two sampled columns
+    against a two-column run, and that run against the FP64 oracle."""
+    from workloads import seed_for
+    say("adjoint C4 full size, sampled columns")
+    g = sbm(200_000, 20, 20.0, 0.1, seed=seed_for(4, "graph"))
+    A = oracle_A(g)
+    G = csc.Graph.from_workload(g)
+    X = gaussian_block(g.n, 64, 0.125, seed=seed_for(4, "signals"))
+    Gr = gaussian_block(g.n, 64, 1.0, seed=seed_for(4, "probes"))
+    a = chebyshev.step_coefficients(60, 2.0, 0.5, "jackson")
+    dX, da, dA = csc.filter_backward(G, a, torch.from_numpy(X).cuda(), torch.from_numpy(Gr).cuda(),
+                                     ckpt_every=8)
+    cols = [5, 40]
+    Xs, Gs = np.ascontiguousarray(X[:, cols]), np.ascontiguousarray(Gr[:, cols])
+    dXs, das, dAs = csc.filter_backward(G, a, torch.from_numpy(Xs).cuda(), torch.from_numpy(Gs).cuda(),
+                                        ckpt_every=8)
+    assert np.allclose(dX.cpu().numpy()[:, cols], dXs.cpu().numpy(), rtol=1e-6, atol=1e-9)
+    rX, rda, rdA = adjoint.filter_backward(A, 2.0, a, Xs.astype(np.float64), Gs.astype(np.float64))
+    assert rel_fro(dXs.cpu().numpy(), rX) <= 1e-5
+    assert rel_fro(das.cpu().numpy(), rda) <= 1e-5
+    assert rel_fro(dAs.cpu().numpy(), rdA) <= 1e-5
+    assert np.all(np.isfinite(da.cpu().numpy())) and np.all(np.isfinite(dA.cpu().numpy()))
+
+
 def test_autograd_function(csc):
     from paper_1706_03591_amd import cheb_filter_autograd
     g = sbm(800, 3, 10.0, 0.1, seed=58)
