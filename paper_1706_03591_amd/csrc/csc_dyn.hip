@@ -35,10 +35,15 @@ struct csc_dyn_s {
   void* basis = nullptr;      // batch x (m + 1) iterate slots of the fresh blocks, or null
   size_t basis_bytes = 0;     // per snapshot
   int batch = 1;              // snapshots whose recurrences advance together
+  int nbuf = 1;               // 2: two batches of slots, so the next batch's recurrence runs
+                              // on `fs` while the current batch's k-means runs on the caller's
+                              // stream
   bool use_graph = false;     // replay the recurrence launches from a captured HIP graph
   hipStream_t cap = nullptr;
-  hipGraphExec_t exec = nullptr;
-  const void* exec_key[9] = {};
+  hipStream_t fs = nullptr;
+  hipEvent_t ev_start = nullptr, ev_basis[2] = {}, ev_free[2] = {};
+  hipGraphExec_t exec[2] = {};
+  const void* exec_key[2][10] = {};
   void* aux = nullptr;
   size_t aux_bytes = 0;
   int variant = 0;
@@ -60,8 +65,14 @@ void free_dyn(csc_dyn st) {
   for (void* p : {st->theta, st->sig, static_cast<void*>(st->C), static_cast<void*>(st->prev),
                   static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork, st->basis, st->aux})
     if (p) (void)hipFree(p);
-  if (st->exec) (void)hipGraphExecDestroy(st->exec);
+  for (int b = 0; b < 2; ++b) {
+    if (st->exec[b]) (void)hipGraphExecDestroy(st->exec[b]);
+    if (st->ev_basis[b]) (void)hipEventDestroy(st->ev_basis[b]);
+    if (st->ev_free[b]) (void)hipEventDestroy(st->ev_free[b]);
+  }
+  if (st->ev_start) (void)hipEventDestroy(st->ev_start);
   if (st->cap) (void)hipStreamDestroy(st->cap);
+  if (st->fs) (void)hipStreamDestroy(st->fs);
   delete st;
 }
 
@@ -121,7 +132,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   st->kwork_bytes = kmeans_workspace(n, d, k);
   st->dwork_bytes = dot_workspace(n);
   bool ok = hipMalloc(&st->theta, es * n * d) == hipSuccess &&
-            hipMalloc(&st->sig, es * n * std::max(d, st->batch * qd)) == hipSuccess &&
+            hipMalloc(&st->sig, es * n * std::max(d, (st->batch > 1 ? 2 : 1) * st->batch * qd)) == hipSuccess &&
             hipMalloc(&st->C, sizeof(float) * k * d) == hipSuccess &&
             hipMalloc(&st->prev, sizeof(int32_t) * n) == hipSuccess &&
             hipMalloc(&st->scal, sizeof(double) * (m + 2)) == hipSuccess &&
@@ -145,7 +156,15 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     (void)hipMemGetInfo(&free_b, &total_b);
     const size_t margin = size_t(4) << 30;
     const size_t want = st->basis_bytes * st->batch;
-    if (keep == 1 || want + st->aux_bytes + margin <= free_b) {
+    // a second batch of slots when batching and it fits: recurrence and k-means overlap
+    if (st->batch > 1 && 2 * want + st->aux_bytes + margin <= free_b &&
+        hipMalloc(&st->basis, 2 * want) == hipSuccess) {
+      st->nbuf = 2;
+      if (hipMalloc(&st->aux, st->aux_bytes) != hipSuccess) {
+        free_dyn(st);
+        return fail(CSC_E_NOMEM, "cannot allocate the basis scratch");
+      }
+    } else if (keep == 1 || want + st->aux_bytes + margin <= free_b) {
       if (hipMalloc(&st->basis, want) != hipSuccess ||
           hipMalloc(&st->aux, st->aux_bytes) != hipSuccess) {
         if (keep == 1) {
@@ -165,6 +184,19 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   if (st->use_graph && hipStreamCreate(&st->cap) != hipSuccess) {
     free_dyn(st);
     return fail(CSC_E_HIP, "cannot create the capture stream");
+  }
+  if (st->nbuf == 2) {
+    // non-blocking: callers often work on the null stream, which would otherwise serialise
+    // with it; the order between the two streams comes only from the events below
+    bool ev_ok = hipStreamCreateWithFlags(&st->fs, hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&st->ev_start, hipEventDisableTiming) == hipSuccess;
+    for (int b = 0; b < 2 && ev_ok; ++b)
+      ev_ok = hipEventCreateWithFlags(&st->ev_basis[b], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&st->ev_free[b], hipEventDisableTiming) == hipSuccess;
+    if (!ev_ok) {
+      free_dyn(st);
+      return fail(CSC_E_HIP, "cannot create the recurrence stream and its events");
+    }
   }
   *out = st;
   return CSC_OK;
@@ -187,26 +219,28 @@ void* basis_slot(csc_dyn st, int slot) {
   return static_cast<char*>(st->basis) + st->basis_bytes * static_cast<size_t>(slot);
 }
 
-// The recurrences of S snapshots (slots 0..S-1), replayed from a captured graph when enabled.
-csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s) {
+// The recurrences of S snapshots (slots buf * batch + 0..S-1), replayed from a captured graph
+// when enabled (one cached graph per buffer, re-captured when the graphs change).
+csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s, int buf = 0) {
   const void* X[8];
   void* B[8];
   for (int i = 0; i < S; ++i) {
-    X[i] = sig_slot(st, i);
-    B[i] = basis_slot(st, i);
+    X[i] = sig_slot(st, buf * st->batch + i);
+    B[i] = basis_slot(st, buf * st->batch + i);
   }
   if (!st->use_graph)
     return run_basis_batch(gs, S, st->lmax, st->m, X, st->feat_dt, st->qd, st->qd, st->iter_dt,
                            st->variant, B, st->basis_bytes, s, true);
-  const void* key[9] = {};
+  const void* key[10] = {};
   key[0] = reinterpret_cast<const void*>(static_cast<intptr_t>(S));
   for (int i = 0; i < S; ++i) key[1 + i] = gs[i];
-  bool same = st->exec != nullptr;
-  for (int i = 0; i < 9 && same; ++i) same = key[i] == st->exec_key[i];
+  hipGraphExec_t& exec = st->exec[buf];
+  bool same = exec != nullptr;
+  for (int i = 0; i < 10 && same; ++i) same = key[i] == st->exec_key[buf][i];
   if (!same) {
-    if (st->exec) {
-      (void)hipGraphExecDestroy(st->exec);
-      st->exec = nullptr;
+    if (exec) {
+      (void)hipGraphExecDestroy(exec);
+      exec = nullptr;
     }
     hipGraph_t graph = nullptr;
     CSC_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeRelaxed));
@@ -218,16 +252,16 @@ csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s)
       return cs;
     }
     if (e != hipSuccess) return fail(CSC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-    const hipError_t ie = hipGraphInstantiate(&st->exec, graph, nullptr, nullptr, 0);
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) {
-      st->exec = nullptr;
+      exec = nullptr;
       return fail(CSC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
     }
-    for (int i = 0; i < 9; ++i) st->exec_key[i] = key[i];
+    for (int i = 0; i < 10; ++i) st->exec_key[buf][i] = key[i];
   }
   timing_begin(s);
-  CSC_HIP(hipGraphLaunch(st->exec, s));
+  CSC_HIP(hipGraphLaunch(exec, s));
   timing_end(s, st->m, basis_batch_bytes(gs, S, st->m, st->qd, st->iter_dt));
   return CSC_OK;
 }
@@ -351,7 +385,10 @@ csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t,
 // S snapshots in order.  After the first snapshot of the sequence, the fresh blocks of up to
 // `batch` snapshots are drawn and their recurrences advanced together (one launch per step);
 // the cut-off decisions, refinements and k-means then run snapshot by snapshot as in
-// Algorithm 1, so the results equal those of S calls to dyn_step.
+// Algorithm 1, so the results equal those of S calls to dyn_step.  The recurrences do not
+// depend on earlier snapshots' results, so with two buffers the next batch's recurrence is
+// issued on the state's own stream before the current batch's decisions and k-means run on
+// the caller's stream; events order the buffers' reuse.
 csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
                      double* lambdas, int* refined, double* counts, void* stream) {
   if (!st || !graphs || !labels || S < 0) return fail(CSC_E_ARG, "null argument");
@@ -365,25 +402,50 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
     return std::make_tuple(lambdas ? lambdas + j : nullptr, refined ? refined + j : nullptr,
                            counts ? counts + j : nullptr);
   };
-  while (i < S) {
-    if (st->t == 0 || !st->basis) {
-      auto [l, r, c] = out(i);
-      CSC_TRY(step_impl(st, &graphs[i]->g, 0, false, labels[i], l, r, c, s));
-      ++i;
-      continue;
-    }
-    const int nb = std::min(st->batch, S - i);
+  // the first snapshot, or no kept iterates: one at a time
+  while (i < S && (st->t == 0 || !st->basis)) {
+    auto [l, r, c] = out(i);
+    CSC_TRY(step_impl(st, &graphs[i]->g, 0, false, labels[i], l, r, c, s));
+    ++i;
+  }
+  if (i >= S) return CSC_OK;
+  const int i0 = i;
+  const int t0 = st->t;  // snapshot i has index t0 + 1 + (i - i0)
+  const int nbatch = (S - i0 + st->batch - 1) / st->batch;
+  const bool pipe = st->nbuf == 2;
+  hipStream_t fs = pipe ? st->fs : s;
+  if (pipe) {
+    // the recurrence stream sees everything the caller enqueued before (graph updates)
+    CSC_HIP(hipEventRecord(st->ev_start, s));
+    CSC_HIP(hipStreamWaitEvent(fs, st->ev_start, 0));
+  }
+  auto issue = [&](int b) -> csc_status {
+    const int j = i0 + b * st->batch;
+    const int nb = std::min(st->batch, S - j);
+    const int buf = pipe ? (b & 1) : 0;
+    if (pipe && b >= 2) CSC_HIP(hipStreamWaitEvent(fs, st->ev_free[buf], 0));
     const Graph* gs[8];
     for (int q = 0; q < nb; ++q) {
-      gs[q] = &graphs[i + q]->g;
-      CSC_TRY(draw_signals(st, st->t + 1 + q, q, s));
+      gs[q] = &graphs[j + q]->g;
+      CSC_TRY(draw_signals(st, t0 + 1 + (j - i0) + q, buf * st->batch + q, fs));
     }
-    CSC_TRY(batch_basis(st, gs, nb, s));
+    CSC_TRY(batch_basis(st, gs, nb, fs, buf));
+    if (pipe) CSC_HIP(hipEventRecord(st->ev_basis[buf], fs));
+    return CSC_OK;
+  };
+  CSC_TRY(issue(0));
+  for (int b = 0; b < nbatch; ++b) {
+    if (pipe && b + 1 < nbatch) CSC_TRY(issue(b + 1));
+    const int j = i0 + b * st->batch;
+    const int nb = std::min(st->batch, S - j);
+    const int buf = pipe ? (b & 1) : 0;
+    if (pipe) CSC_HIP(hipStreamWaitEvent(s, st->ev_basis[buf], 0));
     for (int q = 0; q < nb; ++q) {
-      auto [l, r, c] = out(i + q);
-      CSC_TRY(step_impl(st, gs[q], q, true, labels[i + q], l, r, c, s));
+      auto [l, r, c] = out(j + q);
+      CSC_TRY(step_impl(st, &graphs[j + q]->g, buf * st->batch + q, true, labels[j + q], l, r, c, s));
     }
-    i += nb;
+    if (pipe) CSC_HIP(hipEventRecord(st->ev_free[buf], s));
+    if (!pipe && b + 1 < nbatch) CSC_TRY(issue(b + 1));
   }
   return CSC_OK;
 }
