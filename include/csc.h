@@ -247,7 +247,9 @@ csc_status csc_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
  *    result replaces the oldest block of Theta; k-means on Theta gives the labels.
  * Random draws: Philox streams 16 t + 1 (signals, variance 1/d) and 16 t + 2 (k-means++
  * uniforms), key `seed`.  feat_dt: storage of Theta and of the fresh signals (F32 or
- * BF16); iterates follow opts->iter_dt.  (1 - p) d must divide d.
+ * BF16); iterates follow opts->iter_dt.  q d = round((1 - p) d) must lie in [1, d]; the
+ * fresh block replaces the q d oldest columns, taken cyclically from a cursor that advances
+ * by q d mod d, so any p works (a block that wraps past column d is staged and copied).
  * csc_dynamic_step writes labels (device int32[n]) and returns lambda_t, whether the
  * filter was refined and the eigencount of the fresh columns.  Synchronising.
  */

@@ -13,9 +13,10 @@ combined features.
 
 Readings where the paper is silent or leaves a choice
   * snapshot 1 uses the d feature columns themselves as eigencount probes;
-  * the d columns form d / (q d) blocks used as a FIFO ring: the block filtered longest
-    ago is replaced (for p <= 1/2 the kept block always comes from G_{t-1}, as the
-    paper assumes; for p > 1/2 blocks live ceil(p / q) snapshots);
+  * the d columns form a FIFO ring at column granularity: the q d columns filtered longest
+    ago are replaced, starting at a cursor that advances by q d modulo d (a block may wrap
+    around the last column); for p <= 1/2 the kept columns always come from G_{t-1}, as
+    the paper assumes, and for p > 1/2 columns live for up to ceil(p / q) snapshots;
   * acceptance |c - k| <= tau with tau = max(0.5, 2 sqrt(2 k / (q d)));
   * refinement bisects [lambda_{t-1}, lmax] when c < k and [0, lambda_{t-1}] otherwise;
   * random draws come from Philox4x32-10 with stream id 16 t + purpose (signals 1,
@@ -68,9 +69,8 @@ class DynamicCSC:
                  storage=np.float64):
         self.n, self.d, self.k, self.p, self.m = n, d, k, p, m
         self.qd = int(round((1.0 - p) * d))
-        if self.qd < 1 or d % self.qd != 0:
-            raise ValueError("(1 - p) d must be a positive divisor of d")
-        self.nblocks = d // self.qd
+        if self.qd < 1 or self.qd > d:
+            raise ValueError("need 1 <= (1 - p) d <= d")
         self.seed = seed
         self.lmax = lmax
         self.damping = damping
@@ -83,7 +83,7 @@ class DynamicCSC:
         self.theta = np.zeros((n, d))
         self.t = 0
         self.lam = None
-        self.next_block = 0
+        self.cursor = 0
         self.labels = None
 
     def _signals(self, w: int, t: int) -> np.ndarray:
@@ -122,9 +122,9 @@ class DynamicCSC:
                 a = chebyshev.step_coefficients(self.m, self.lmax, lam, self.damping)
                 Y = chebyshev.filter_recurrence(A, self.lmax, a, R)
                 refined = True
-            b = self.next_block
-            self.theta[:, b * self.qd:(b + 1) * self.qd] = Y
-            self.next_block = (b + 1) % self.nblocks
+            cols = (self.cursor + np.arange(self.qd)) % self.d
+            self.theta[:, cols] = Y
+            self.cursor = (self.cursor + self.qd) % self.d
         self.lam = lam
         lab, C, obj = run_kmeans(self.theta, self.k, self.lloyd_iters, self.seed, t,
                                  self.init, self.labels)

@@ -13,7 +13,7 @@
 
 struct csc_dyn_s {
   int64_t n = 0;
-  int d = 0, k = 0, m = 0, qd = 0, nblocks = 0;
+  int d = 0, k = 0, m = 0, qd = 0;
   double p = 0.0;
   csc_damping damp = CSC_DAMP_JACKSON;
   csc_dtype feat_dt = CSC_F32;
@@ -49,7 +49,8 @@ struct csc_dyn_s {
   int variant = 0;
   int t = 0;
   double lam = 0.0;
-  int next_block = 0;
+  int cursor = 0;             // first column of Theta the next fresh block replaces
+  void* wrap = nullptr;       // n x qd staging of a fresh block that wraps past column d
 };
 
 namespace csc {
@@ -63,7 +64,8 @@ uint64_t stream_id(int t, uint64_t purpose) { return 16ull * static_cast<uint64_
 void free_dyn(csc_dyn st) {
   if (!st) return;
   for (void* p : {st->theta, st->sig, static_cast<void*>(st->C), static_cast<void*>(st->prev),
-                  static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork, st->basis, st->aux})
+                  static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork, st->basis, st->aux,
+                  st->wrap})
     if (p) (void)hipFree(p);
   for (int b = 0; b < 2; ++b) {
     if (st->exec[b]) (void)hipGraphExecDestroy(st->exec[b]);
@@ -92,7 +94,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   if (!(p >= 0.0 && p < 1.0)) return fail(CSC_E_ARG, "need 0 <= p < 1");
   if (feat_dt != CSC_F32 && feat_dt != CSC_BF16) return fail(CSC_E_DTYPE, "features must be F32 or BF16");
   const int qd = static_cast<int>(std::lround((1.0 - p) * d));
-  if (qd < 1 || d % qd != 0) return fail(CSC_E_ARG, "(1 - p) d must be a positive divisor of d");
+  if (qd < 1 || qd > d) return fail(CSC_E_ARG, "need 1 <= (1 - p) d <= d");
   auto* st = new csc_dyn_s();
   st->n = n;
   st->d = d;
@@ -100,7 +102,6 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   st->m = m;
   st->p = p;
   st->qd = qd;
-  st->nblocks = d / qd;
   st->damp = damp;
   st->feat_dt = feat_dt;
   st->seed = seed;
@@ -138,7 +139,8 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
             hipMalloc(&st->scal, sizeof(double) * (m + 2)) == hipSuccess &&
             hipMalloc(&st->fwork, st->fwork_bytes) == hipSuccess &&
             hipMalloc(&st->kwork, st->kwork_bytes) == hipSuccess &&
-            hipMalloc(&st->dwork, st->dwork_bytes) == hipSuccess;
+            hipMalloc(&st->dwork, st->dwork_bytes) == hipSuccess &&
+            (d % qd == 0 || hipMalloc(&st->wrap, es * n * qd) == hipSuccess);
   if (!ok) {
     free_dyn(st);
     return fail(CSC_E_NOMEM, "device allocation failed in csc_dyn_create");
@@ -298,12 +300,17 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
     CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->d, st->theta,
                        st->feat_dt, st->d, st->d, st->iter_dt, nullptr, 0, st->fwork,
                        st->fwork_bytes, s));
-    st->next_block = 0;
+    st->cursor = 0;
     ref = 1;
   } else {
     // Steps 4-7: fresh q d columns filtered with h^{t-1}, eigencount, optional refinement.
-    const int b = st->next_block;
-    char* blk = static_cast<char*>(st->theta) + es * static_cast<size_t>(b) * st->qd;
+    // the fresh block replaces columns cursor .. cursor + qd - 1 (mod d) of Theta; a block
+    // that wraps past the last column is written to a staging buffer and copied in two parts
+    const int c0 = st->cursor;
+    const bool wraps = c0 + st->qd > st->d;
+    char* blk = wraps ? static_cast<char*>(st->wrap)
+                      : static_cast<char*>(st->theta) + es * static_cast<size_t>(c0);
+    const int64_t ldb = wraps ? st->qd : st->d;
     void* sig = sig_slot(st, slot);
     void* basis = st->basis ? basis_slot(st, slot) : nullptr;
     if (!pre_basis) CSC_TRY(draw_signals(st, t, slot, s));
@@ -312,13 +319,13 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
     if (kept) {
       if (!pre_basis) CSC_TRY(batch_basis(st, &g, 1, s));
       CSC_TRY(run_combine(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
-                          st->feat_dt, st->d, sig, st->feat_dt, st->qd, st->scal, st->aux,
+                          st->feat_dt, ldb, sig, st->feat_dt, st->qd, st->scal, st->aux,
                           st->aux_bytes, s));
     } else {
       CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
-                         st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
+                         st->feat_dt, ldb, st->qd, st->iter_dt, nullptr, 0, st->fwork,
                          st->fwork_bytes, s));
-      CSC_TRY(launch_dot(sig, st->feat_dt, st->qd, blk, st->feat_dt, st->d, st->n, st->qd,
+      CSC_TRY(launch_dot(sig, st->feat_dt, st->qd, blk, st->feat_dt, ldb, st->n, st->qd,
                          st->scal, st->dwork, st->dwork_bytes, s));
     }
     double dot = 0.0;
@@ -341,15 +348,23 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
       cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
       if (kept)
         CSC_TRY(run_combine(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
-                            st->feat_dt, st->d, nullptr, st->feat_dt, 0, nullptr, st->aux,
+                            st->feat_dt, ldb, nullptr, st->feat_dt, 0, nullptr, st->aux,
                             st->aux_bytes, s));
       else
         CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
-                           st->feat_dt, st->d, st->qd, st->iter_dt, nullptr, 0, st->fwork,
+                           st->feat_dt, ldb, st->qd, st->iter_dt, nullptr, 0, st->fwork,
                            st->fwork_bytes, s));
       ref = 1;
     }
-    st->next_block = (b + 1) % st->nblocks;
+    if (wraps) {
+      const int first = st->d - c0;  // columns c0 .. d-1, then 0 .. qd - first - 1
+      char* th = static_cast<char*>(st->theta);
+      CSC_HIP(hipMemcpy2DAsync(th + es * static_cast<size_t>(c0), es * st->d, blk, es * st->qd,
+                               es * first, st->n, hipMemcpyDeviceToDevice, s));
+      CSC_HIP(hipMemcpy2DAsync(th, es * st->d, blk + es * static_cast<size_t>(first), es * st->qd,
+                               es * (st->qd - first), st->n, hipMemcpyDeviceToDevice, s));
+    }
+    st->cursor = (c0 + st->qd) % st->d;
   }
 
   // Step 8: k-means on Theta_t.

@@ -83,9 +83,10 @@ def test_host_argument_errors(pkg):
     assert b"n must be" in lib.csc_last_error()
     opts = pkg.binding.DynOpts(lmax=0, tau=0, n_cand=0, lloyd_iters=-1, init=0, iter_dt=0,
                                keep_iterates=0)
-    # p = 1 leaves no fresh columns; (1 - p) d must divide d
+    # p = 1 leaves no fresh columns, p < 0 is meaningless, and p close to 1 rounds q d to 0
     assert lib.csc_dyn_create(100, 8, 2, 1.0, 10, 1, 0, 1, ctypes.byref(opts), ctypes.byref(out)) == 1
-    assert lib.csc_dyn_create(100, 8, 2, 0.3, 10, 1, 0, 1, ctypes.byref(opts), ctypes.byref(out)) == 1
+    assert lib.csc_dyn_create(100, 8, 2, -0.1, 10, 1, 0, 1, ctypes.byref(opts), ctypes.byref(out)) == 1
+    assert lib.csc_dyn_create(100, 8, 2, 0.95, 10, 1, 0, 1, ctypes.byref(opts), ctypes.byref(out)) == 1
     assert lib.csc_dyn_create(100, 8, 2, 0.5, 10, 1, 5, 1, ctypes.byref(opts), ctypes.byref(out)) == 3
     # null handles
     assert lib.csc_cheb_filter(None, 2.0, 3, None, None, 0, 1, None, 0, 1, 1, 0, None, None, 0, None) == 1

@@ -19,7 +19,8 @@ def seq():
 
 
 @pytest.mark.parametrize("keep", [0, 1])
-@pytest.mark.parametrize("p,d,tau", [(0.5, 32, 1e-12), (0.5, 64, None), (0.75, 64, None), (0.0, 16, None)])
+@pytest.mark.parametrize("p,d,tau", [(0.5, 32, 1e-12), (0.5, 64, None), (0.75, 64, None), (0.0, 16, None),
+                                     (0.3, 40, None), (0.3, 40, 1e-12)])
 def test_dynamic_matches_oracle(csc, seq, p, d, tau, keep):
     say(f"dynamic parity p={p} d={d} tau={tau} keep_iterates={keep}")
     k, m, seed = 4, 40, 53
@@ -138,17 +139,20 @@ def test_lmax_estimate_is_upper_bound(csc):
     assert lam[-1] * 0.999 <= est <= 2.0
 
 
-@pytest.mark.parametrize("batch,use_graph,iters", [(1, True, torch.float32), (3, False, torch.float32),
-                                                   (4, True, torch.float32), (4, True, "bf16s")])
-def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph, iters):
-    say(f"batched dynamic batch={batch} graph={use_graph} iterates={iters}")
-    k, m, d, seed = 4, 40, 32, 62
-    ref = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1,
+@pytest.mark.parametrize("batch,use_graph,iters,p,d", [(1, True, torch.float32, 0.5, 32),
+                                                       (3, False, torch.float32, 0.5, 32),
+                                                       (4, True, torch.float32, 0.5, 32),
+                                                       (4, True, "bf16s", 0.5, 32),
+                                                       (4, True, torch.float32, 0.3, 40)])
+def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph, iters, p, d):
+    say(f"batched dynamic batch={batch} graph={use_graph} iterates={iters} p={p} d={d}")
+    k, m, seed = 4, 40, 62
+    ref = csc.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10, keep_iterates=1,
                          iter_dtype=iters)
     G_ref = [csc.Graph.from_workload(g) for g in seq]
     ref_out = [ref.step(G) for G in G_ref]
     ref_theta = ref.features()
-    bat = csc.DynamicCSC(2000, d, k, 0.5, m, seed=seed, lloyd_iters=10, keep_iterates=1,
+    bat = csc.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10, keep_iterates=1,
                          batch=batch, use_graph=use_graph, iter_dtype=iters)
     G_bat = [csc.Graph.from_workload(g) for g in seq]
     labels, lams, refs, cnts = bat.steps(G_bat)

@@ -14,16 +14,20 @@ def seq():
     return [g0] + [dyn.step(0.01, 0.005) for _ in range(3)]
 
 
-def test_reused_columns_are_bit_identical(seq):
-    run = dynamic.DynamicCSC(600, 16, 3, 0.5, 30, seed=43, lloyd_iters=5)
+@pytest.mark.parametrize("p", [0.5, 0.3, 0.75])
+def test_reused_columns_are_bit_identical(seq, p):
+    """Exactly the q d columns at the ring cursor (modulo d) are replaced each snapshot; the
+    p d others are the previous snapshot's columns, bit for bit (p = 0.3 wraps around)."""
+    run = dynamic.DynamicCSC(600, 16, 3, p, 30, seed=43, lloyd_iters=5)
     run.step(seq[0])
     prev = run.theta.copy()
     for t in range(1, 4):
-        b_replaced = run.next_block
+        repl = (run.cursor + np.arange(run.qd)) % 16
         run.step(seq[t])
-        kept = 1 - b_replaced
-        q = run.qd
-        assert np.array_equal(run.theta[:, kept * q:(kept + 1) * q], prev[:, kept * q:(kept + 1) * q])
+        kept = np.setdiff1d(np.arange(16), repl)
+        assert kept.size == 16 - run.qd
+        assert np.array_equal(run.theta[:, kept], prev[:, kept])
+        assert not np.any(np.all(run.theta[:, repl] == prev[:, repl], axis=0))
         prev = run.theta.copy()
 
 
