@@ -52,6 +52,10 @@ typedef enum { CSC_F32 = 0, CSC_BF16 = 1, CSC_F64 = 2, CSC_BF16S = 3 } csc_dtype
 
 typedef enum { CSC_DAMP_NONE = 0, CSC_DAMP_JACKSON = 1 } csc_damping;
 
+/* The two Laplacians of Sec. 2.1: normalized L = I - D^{-1/2} W D^{-1/2}, spectrum in
+ * [0, 2]; combinatorial L = D - W, spectrum in [0, max over edges (i, j) of d_i + d_j]. */
+typedef enum { CSC_LAP_NORMALIZED = 0, CSC_LAP_COMBINATORIAL = 1 } csc_laplacian;
+
 typedef struct csc_graph_s* csc_graph;
 typedef struct csc_dyn_s* csc_dyn;
 
@@ -61,10 +65,15 @@ const char* csc_last_error(void);
 int csc_version(void);
 
 /* ---------------------------------------------------------------------------------
- * Graph operator (Sec. 2.1).  From the symmetric weight matrix W in CSR form, builds the
- * normalized adjacency A = D^{-1/2} W D^{-1/2} on the device, so that the normalized
- * Laplacian is L = I - A.  An isolated node (degree 0) gets D^{-1/2} = 0, i.e. an
- * identity row in L and eigenvalue 1; their number is reported by csc_graph_info.
+ * Graph operator (Sec. 2.1).  From the symmetric weight matrix W in CSR form, builds on
+ * the device either
+ *  - lap = CSC_LAP_NORMALIZED: the normalized adjacency A = D^{-1/2} W D^{-1/2}, so that
+ *    L = I - A.  An isolated node (degree 0) gets D^{-1/2} = 0, i.e. an identity row in L
+ *    and eigenvalue 1; or
+ *  - lap = CSC_LAP_COMBINATORIAL: W itself and the degrees D, so that L = D - W (an
+ *    isolated node is a zero row, eigenvalue 0).  The spectrum bound of csc_lmax is
+ *    computed here, so create and update synchronise `stream` for such a graph.
+ * The number of isolated nodes is reported by csc_graph_info.
  *
  * rowptr_d: device int64[n + 1]; colidx_d: device int32[nnz], sorted strictly increasing
  * within each row; w_d: device double[nnz], all > 0.  No self-loops; W symmetric (entry
@@ -78,8 +87,8 @@ int csc_version(void);
  */
 csc_status csc_graph_create(int64_t n, int64_t nnz, int64_t nnz_capacity,
                             const int64_t* rowptr_d, const int32_t* colidx_d,
-                            const double* w_d, csc_dtype val_dt, int validate,
-                            void* stream, csc_graph* out);
+                            const double* w_d, csc_dtype val_dt, csc_laplacian lap,
+                            int validate, void* stream, csc_graph* out);
 /* Rebuild the operator of an existing handle from a new W with the same n and
  * nnz <= nnz_capacity (a new snapshot of a dynamic graph).  Allocates nothing. */
 csc_status csc_graph_update(csc_graph g, int64_t nnz, const int64_t* rowptr_d,
@@ -96,11 +105,12 @@ csc_status csc_graph_arrays(csc_graph g, const int32_t** rowptr, const int32_t**
                             const int32_t** mirror);
 
 /* Upper bound of the spectrum of L used to map [0, lmax] onto [-1, 1] (Sec. 3.2 gives
- * none).  iters == 0 returns 2, the exact bound of the normalized Laplacian.  iters > 0
- * runs that many power iterations on L from a fixed pseudo-random start and returns
- * 1.01 (rho + r), clamped to at most 2, where rho is the last Rayleigh quotient and r the
- * norm of its residual L x - rho x (|x| = 1).  Allocates temporary device memory.
- * Synchronising. */
+ * none).  iters == 0 returns the graph's fixed bound: 2 for the normalized Laplacian; for
+ * the combinatorial one, max over stored entries (i, j) of d_i + d_j (Anderson and Morley,
+ * 1985), computed in FP64, or 1 for a graph without edges.  iters > 0 runs that many power
+ * iterations on L from a fixed pseudo-random start and returns 1.01 (rho + r), clamped to
+ * at most the fixed bound, where rho is the last Rayleigh quotient and r the norm of its
+ * residual L x - rho x (|x| = 1).  Allocates temporary device memory.  Synchronising. */
 csc_status csc_lmax(csc_graph g, int iters, double* lmax, void* stream);
 
 /* ---------------------------------------------------------------------------------
@@ -243,7 +253,8 @@ csc_status csc_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
  *  - Each later call (steps 4-8): draws q d fresh signals, filters them on G_t with the
  *    previous filter, estimates their eigencount c = <R, h(L) R> / (sigma2 q d); when
  *    |c - k| > tau it computes their moments, bisects from the previous cut-off
- *    ([lambda, lmax] when c < k, [0, lambda] otherwise) and filters them again; the
+ *    ([lambda, lmax] when c < k, [0, lambda] otherwise, lambda clipped to this snapshot's
+ *    lmax) and filters them again; the
  *    result replaces the oldest block of Theta; k-means on Theta gives the labels.
  * Random draws: Philox streams 16 t + 1 (signals, variance 1/d) and 16 t + 2 (k-means++
  * uniforms), key `seed`.  feat_dt: storage of Theta and of the fresh signals (F32 or
@@ -254,7 +265,7 @@ csc_status csc_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
  * filter was refined and the eigencount of the fresh columns.  Synchronising.
  */
 typedef struct {
-  double lmax;        /* spectrum bound, 0 -> 2 */
+  double lmax;        /* spectrum bound; 0 -> each graph's own (csc_lmax, iters 0) */
   double tau;         /* acceptance half-width, <= 0 -> max(0.5, 2 sqrt(2 k / (q d))) */
   int n_cand;         /* dichotomy steps, 0 -> 16 */
   int lloyd_iters;    /* Lloyd rounds after seeding, < 0 -> 20 */
@@ -301,7 +312,8 @@ csc_status csc_dyn_destroy(csc_dyn st);
  * by the reverse recurrence Zb_j = a_j G + 2 L~^T Zb_{j+1} - Zb_{j+2}, with the forward
  * iterates recomputed from checkpoints taken every ckpt_every steps (0 -> ceil(sqrt(m))).
  * X: device float n x w (ldx).  work: csc_cheb_backward_workspace_bytes(n, w, m,
- * ckpt_every).  Asynchronous.
+ * ckpt_every).  Asynchronous.  Defined for the normalized Laplacian; a combinatorial
+ * graph returns CSC_E_ARG.
  */
 size_t csc_cheb_backward_workspace_bytes(int64_t n, int w, int m, int ckpt_every);
 csc_status csc_cheb_filter_backward(csc_graph g, double lmax, int m, const double* a,

@@ -22,7 +22,10 @@ Readings where the paper is silent or leaves a choice
   * random draws come from Philox4x32-10 with stream id 16 t + purpose (signals 1,
     k-means uniforms 2), see :mod:`oracle.philox`;
   * k-means: k-means++ seeding then a fixed number of Lloyd rounds, or a warm start
-    from the previous labels (means of the new features under the old labels).
+    from the previous labels (means of the new features under the old labels);
+  * with the combinatorial Laplacian D - W and no lmax given, each snapshot maps its own
+    spectrum bound (Anderson-Morley, :mod:`oracle.operator`) onto [-1, 1]; lambda_{t-1}
+    is an absolute cut-off, clipped to the new bound where a bracket needs it.
 """
 
 from __future__ import annotations
@@ -64,13 +67,16 @@ def run_kmeans(F: np.ndarray, k: int, iters: int, seed: int, t: int, init: str,
 
 class DynamicCSC:
     def __init__(self, n: int, d: int, k: int, p: float, m: int, seed: int,
-                 lmax: float = 2.0, damping: str = "jackson", n_cand: int = 16,
+                 lmax: float | None = None, damping: str = "jackson", n_cand: int = 16,
                  lloyd_iters: int = 20, tau: float | None = None, init: str = "kmeans++",
-                 storage=np.float64):
+                 storage=np.float64, laplacian: str = "normalized"):
         self.n, self.d, self.k, self.p, self.m = n, d, k, p, m
         self.qd = int(round((1.0 - p) * d))
         if self.qd < 1 or self.qd > d:
             raise ValueError("need 1 <= (1 - p) d <= d")
+        if laplacian not in ("normalized", "combinatorial"):
+            raise ValueError(laplacian)
+        self.laplacian = laplacian
         self.seed = seed
         self.lmax = lmax
         self.damping = damping
@@ -93,34 +99,41 @@ class DynamicCSC:
 
     def step(self, g) -> StepResult:
         """Process the next snapshot, given as a CSR weight matrix (workloads.Graph)."""
-        A, _ = operator.normalized_adjacency(g.n, g.rowptr, g.colidx, g.w)
+        if self.laplacian == "normalized":
+            A, _ = operator.normalized_adjacency(g.n, g.rowptr, g.colidx, g.w)
+            lmax = self.lmax if self.lmax is not None else 2.0
+        else:
+            A = operator.combinatorial_laplacian(g.n, g.rowptr, g.colidx, g.w)
+            lmax = self.lmax if self.lmax is not None else \
+                operator.anderson_morley_bound(g.n, g.rowptr, g.colidx, g.w)
         self.t += 1
         t = self.t
         sigma2 = self.sigma ** 2
         if t == 1:
             R = self._signals(self.d, t)
-            mu = eigcount.moments_direct(A, self.lmax, self.m, R)
-            lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, self.lmax, self.damping,
+            mu = eigcount.moments_direct(A, lmax, self.m, R)
+            lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, lmax, self.damping,
                                                    sigma2, self.d, self.k, self.n_cand,
-                                                   0.0, self.lmax)
-            a = chebyshev.step_coefficients(self.m, self.lmax, lam, self.damping)
-            self.theta = chebyshev.filter_recurrence(A, self.lmax, a, R)
+                                                   0.0, lmax)
+            a = chebyshev.step_coefficients(self.m, lmax, lam, self.damping)
+            self.theta = chebyshev.filter_recurrence(A, lmax, a, R)
             refined = True
         else:
             R = self._signals(self.qd, t)
-            a = chebyshev.step_coefficients(self.m, self.lmax, self.lam, self.damping)
-            Y = chebyshev.filter_recurrence(A, self.lmax, a, R)
+            a = chebyshev.step_coefficients(self.m, lmax, self.lam, self.damping)
+            Y = chebyshev.filter_recurrence(A, lmax, a, R)
             cnt = float(np.sum(R * Y) / (sigma2 * self.qd))
             lam = self.lam
             refined = False
             if abs(cnt - self.k) > self.tau:
-                mu = eigcount.moments_direct(A, self.lmax, self.m, R)
-                lo, hi = (self.lam, self.lmax) if cnt < self.k else (0.0, self.lam)
-                lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, self.lmax, self.damping,
+                mu = eigcount.moments_direct(A, lmax, self.m, R)
+                prev = min(self.lam, lmax)
+                lo, hi = (prev, lmax) if cnt < self.k else (0.0, prev)
+                lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, lmax, self.damping,
                                                        sigma2, self.qd, self.k, self.n_cand,
                                                        lo, hi)
-                a = chebyshev.step_coefficients(self.m, self.lmax, lam, self.damping)
-                Y = chebyshev.filter_recurrence(A, self.lmax, a, R)
+                a = chebyshev.step_coefficients(self.m, lmax, lam, self.damping)
+                Y = chebyshev.filter_recurrence(A, lmax, a, R)
                 refined = True
             cols = (self.cursor + np.arange(self.qd)) % self.d
             self.theta[:, cols] = Y

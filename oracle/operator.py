@@ -5,8 +5,17 @@ Laplacian is L = I - D^{-1/2} W D^{-1/2} with D the diagonal degree matrix.  An 
 node has degree 0; its D^{-1/2} entry is taken to be 0 (the paper does not cover this
 case), so that its row of L is the identity row and its eigenvalue is 1.
 
-Parity pins: the cycle graph (eigenvalues 1 - cos(2 pi j / n)) and disjoint cliques
-(eigenvalue 0 with multiplicity k) in tests/test_oracle_operator.py.
+The combinatorial Laplacian L = D - W (Sec. 2.1 names it beside the normalized one) has
+no fixed spectral bound; the bound used with it is Anderson and Morley's
+lambda_max(L) <= max over edges (i, j) of d_i + d_j (Linear Multilinear Algebra 18, 1985).
+
+Every function of the oracle that takes the normalized adjacency A (L = I - A) also takes
+an ExplicitLaplacian, which carries L itself.
+
+Parity pins (tests/test_oracle_chebyshev.py, tests/test_oracle_laplacian.py): the cycle
+graph (normalized eigenvalues 1 - cos(2 pi j / n), combinatorial 2 - 2 cos(2 pi j / n)),
+disjoint cliques (eigenvalue 0 with multiplicity k; combinatorial eigenvalue s on the rest),
+the star graph and regular bipartite graphs where the Anderson-Morley bound is attained.
 """
 
 from __future__ import annotations
@@ -43,19 +52,46 @@ def normalized_adjacency(n, rowptr, colidx, w) -> tuple[sp.csr_matrix, np.ndarra
     return A, dis
 
 
-def laplacian(A: sp.csr_matrix) -> sp.csr_matrix:
-    """L = I - A."""
+class ExplicitLaplacian:
+    """A Laplacian given as a matrix, accepted in place of the normalized adjacency."""
+
+    def __init__(self, L: sp.csr_matrix):
+        self.L = sp.csr_matrix(L, dtype=np.float64)
+        self.shape = self.L.shape
+
+
+def combinatorial_laplacian(n, rowptr, colidx, w) -> ExplicitLaplacian:
+    """L = D - W."""
+    W = weight_matrix(n, rowptr, colidx, w)
+    return ExplicitLaplacian((sp.diags(degrees(W)) - W).tocsr())
+
+
+def anderson_morley_bound(n, rowptr, colidx, w) -> float:
+    """max over stored entries (i, j) of d_i + d_j, an upper bound of lambda_max(D - W); 0
+    for a graph without edges."""
+    W = weight_matrix(n, rowptr, colidx, w)
+    if W.nnz == 0:
+        return 0.0
+    deg = degrees(W)
+    rows = np.repeat(np.arange(n), np.diff(W.indptr))
+    return float(np.max(deg[rows] + deg[W.indices]))
+
+
+def laplacian(A) -> sp.csr_matrix:
+    """L = I - A, or the matrix an ExplicitLaplacian carries."""
+    if isinstance(A, ExplicitLaplacian):
+        return A.L
     n = A.shape[0]
     return (sp.identity(n, format="csr") - A).tocsr()
 
 
-def scaled_laplacian(A: sp.csr_matrix, lmax: float) -> sp.csr_matrix:
+def scaled_laplacian(A, lmax: float) -> sp.csr_matrix:
     """L~ = (2 / lmax) L - I, which maps the spectrum [0, lmax] onto [-1, 1]."""
     n = A.shape[0]
     return ((2.0 / lmax) * laplacian(A) - sp.identity(n, format="csr")).tocsr()
 
 
-def dense_spectrum(A: sp.csr_matrix) -> tuple[np.ndarray, np.ndarray]:
+def dense_spectrum(A) -> tuple[np.ndarray, np.ndarray]:
     """Eigenvalues (ascending) and orthonormal eigenvectors of L, by dense symmetric eigh."""
     L = laplacian(A).toarray()
     L = 0.5 * (L + L.T)

@@ -21,6 +21,7 @@ F32, BF16, F64, BF16S = 0, 1, 2, 3
 # basis, FP32 recurrence state)
 BF16S_ITER = "bf16s"
 DAMP_NONE, DAMP_JACKSON = 0, 1
+LAP_NORMALIZED, LAP_COMBINATORIAL = 0, 1
 
 _TORCH_DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
 _DT_TORCH = {F32: torch.float32, BF16: torch.bfloat16, F64: torch.float64}
@@ -63,7 +64,7 @@ class DynOpts(C.Structure):
 _SIGS = {
     "csc_last_error": ([], C.c_char_p),
     "csc_version": ([], C.c_int),
-    "csc_graph_create": ([i64, i64, i64, vp, vp, vp, i32, i32, vp, C.POINTER(vp)], i32),
+    "csc_graph_create": ([i64, i64, i64, vp, vp, vp, i32, i32, i32, vp, C.POINTER(vp)], i32),
     "csc_graph_update": ([vp, i64, vp, vp, vp, i32, vp], i32),
     "csc_graph_destroy": ([vp], i32),
     "csc_graph_info": ([vp, pi64, pi64, pi64], i32),
@@ -174,19 +175,22 @@ def version() -> int:
 
 
 class Graph:
-    """Device operator A = D^{-1/2} W D^{-1/2} of a CSR weight matrix W."""
+    """Device operator of a CSR weight matrix W: the normalized adjacency
+    A = D^{-1/2} W D^{-1/2} (L = I - A), or with laplacian=LAP_COMBINATORIAL, W and D
+    (L = D - W)."""
 
     def __init__(self, n: int, rowptr, colidx, w, val_dtype=torch.float32, validate: bool = True,
-                 nnz_capacity: int | None = None, stream=None):
+                 nnz_capacity: int | None = None, stream=None, laplacian: int = 0):
         self.n = int(n)
         self.val_dtype = val_dtype
+        self.laplacian = int(laplacian)
         rp, ci, ww = self._to_device(rowptr, colidx, w)
         nnz = int(ci.numel())
         cap = int(nnz_capacity if nnz_capacity is not None else nnz)
         h = C.c_void_p()
         _check(lib.csc_graph_create(self.n, nnz, cap, _ptr(rp), _ptr(ci), _ptr(ww),
-                                    _TORCH_DT[val_dtype], int(validate), _stream(stream),
-                                    C.byref(h)))
+                                    _TORCH_DT[val_dtype], self.laplacian, int(validate),
+                                    _stream(stream), C.byref(h)))
         self.h = h
         self.nnz = nnz
         self._src = (rp, ci, ww)
@@ -314,10 +318,12 @@ def cheb_coeffs(m: int, lmax: float, lambda_c: float, damping: int = DAMP_JACKSO
 
 
 def cheb_filter(g: Graph, a, X: torch.Tensor, out: torch.Tensor | None = None,
-                out_dtype=torch.float32, iter_dtype=torch.float32, lmax: float = 2.0,
+                out_dtype=torch.float32, iter_dtype=torch.float32, lmax: float | None = None,
                 moments: bool = False, stream=None):
-    """Y = sum_j a_j T_j(L~) X (row-major blocks).  Returns Y, or (Y, moments) if asked."""
+    """Y = sum_j a_j T_j(L~) X (row-major blocks).  Returns Y, or (Y, moments) if asked.
+    lmax None: the graph's own spectrum bound."""
     n, w = X.shape
+    lmax = g.lmax() if lmax is None else lmax
     if out is None:
         out = torch.empty((n, w), dtype=out_dtype, device=X.device)
     a = np.asarray(a, dtype=np.float64)
@@ -331,9 +337,10 @@ def cheb_filter(g: Graph, a, X: torch.Tensor, out: torch.Tensor | None = None,
     return (out, mom) if moments else out
 
 
-def cheb_moments(g: Graph, m: int, P: torch.Tensor, iter_dtype=torch.float32, lmax: float = 2.0,
-                 stream=None) -> torch.Tensor:
+def cheb_moments(g: Graph, m: int, P: torch.Tensor, iter_dtype=torch.float32,
+                 lmax: float | None = None, stream=None) -> torch.Tensor:
     n, w = P.shape
+    lmax = g.lmax() if lmax is None else lmax
     mom = torch.empty(m + 1, dtype=torch.float64, device=P.device)
     need = lib.csc_cheb_filter_workspace_bytes(n, w, _it(iter_dtype))
     ws = workspace(need, P.device)
@@ -345,9 +352,10 @@ def cheb_moments(g: Graph, m: int, P: torch.Tensor, iter_dtype=torch.float32, lm
 
 def eigcount(g: Graph, m: int, P: torch.Tensor, sigma2: float, k: float, n_cand: int = 16,
              lo: float = 0.0, hi: float | None = None, damping: int = DAMP_JACKSON,
-             lmax: float = 2.0, iter_dtype=torch.float32, stream=None):
+             lmax: float | None = None, iter_dtype=torch.float32, stream=None):
     """Returns (lambda_c, count, trace (n_cand x 2), moments)."""
     n, w = P.shape
+    lmax = g.lmax() if lmax is None else lmax
     hi = lmax if hi is None else hi
     need = lib.csc_cheb_filter_workspace_bytes(n, w, _it(iter_dtype)) + (m + 1) * 8 + 512
     ws = workspace(need, P.device)
@@ -454,7 +462,7 @@ def kmeans(F: torch.Tensor, k: int, iters: int = 20, seed: int = 0, stream_id: i
 class DynamicCSC:
     def __init__(self, n: int, d: int, k: int, p: float, m: int, seed: int,
                  damping: int = DAMP_JACKSON, feat_dtype=torch.float32, iter_dtype=torch.float32,
-                 lmax: float = 2.0, tau: float = 0.0, n_cand: int = 16, lloyd_iters: int = 20,
+                 lmax: float = 0.0, tau: float = 0.0, n_cand: int = 16, lloyd_iters: int = 20,
                  init: int = 0, keep_iterates: int = -1, batch: int = 1, use_graph: bool = False,
                  variant: int = -1):
         opts = DynOpts(lmax=lmax, tau=tau, n_cand=n_cand, lloyd_iters=lloyd_iters, init=init,
@@ -524,11 +532,12 @@ class DynamicCSC:
 # adjoint
 
 
-def filter_backward(g: Graph, a, X: torch.Tensor, G: torch.Tensor, lmax: float = 2.0,
+def filter_backward(g: Graph, a, X: torch.Tensor, G: torch.Tensor, lmax: float | None = None,
                     ckpt_every: int = 0, want_dx: bool = True, want_da: bool = True,
                     want_dA: bool = True, stream=None):
     """(dX, da, dA) of l = <G, sum_j a_j T_j(L~) X>; FP32 in, FP32/FP64 out."""
     n, w = X.shape
+    lmax = g.lmax() if lmax is None else lmax
     a = np.asarray(a, dtype=np.float64)
     m = len(a) - 1
     dX = torch.empty((n, w), dtype=torch.float32, device=X.device) if want_dx else None

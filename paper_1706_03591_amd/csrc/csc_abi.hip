@@ -142,7 +142,8 @@ int csc_version(void) { return 10000; }
 
 csc_status csc_graph_create(int64_t n, int64_t nnz, int64_t nnz_capacity,
                             const int64_t* rowptr_d, const int32_t* colidx_d, const double* w_d,
-                            csc_dtype val_dt, int validate, void* stream, csc_graph* out) {
+                            csc_dtype val_dt, csc_laplacian lap, int validate, void* stream,
+                            csc_graph* out) {
   if (!out) return fail(CSC_E_ARG, "out is null");
   *out = nullptr;
   if (n < 1 || n >= (int64_t(1) << 31)) return fail(CSC_E_ARG, "n must be in [1, 2^31)");
@@ -150,17 +151,23 @@ csc_status csc_graph_create(int64_t n, int64_t nnz, int64_t nnz_capacity,
     return fail(CSC_E_ARG, "need 0 <= nnz <= nnz_capacity < 2^31");
   if (!rowptr_d || (nnz > 0 && (!colidx_d || !w_d))) return fail(CSC_E_ARG, "null CSR array");
   if (val_dt != CSC_F32 && val_dt != CSC_BF16) return fail(CSC_E_DTYPE, "values must be F32 or BF16");
+  if (lap != CSC_LAP_NORMALIZED && lap != CSC_LAP_COMBINATORIAL)
+    return fail(CSC_E_ARG, "unknown Laplacian kind");
   auto* h = new csc_graph_s();
   Graph& g = h->g;
   g.n = n;
   g.cap = std::max<int64_t>(nnz_capacity, 1);
   g.val_dt = val_dt;
+  g.lap = lap;
+  const bool comb = lap == CSC_LAP_COMBINATORIAL;
   bool ok = hipMalloc(&g.rowptr, sizeof(int32_t) * (n + 1)) == hipSuccess &&
             hipMalloc(&g.colidx, sizeof(int32_t) * g.cap) == hipSuccess &&
             hipMalloc(&g.vals, dtype_size(val_dt) * g.cap) == hipSuccess &&
             hipMalloc(&g.dinv, sizeof(double) * n) == hipSuccess &&
             hipMalloc(&g.mirror, sizeof(int32_t) * g.cap) == hipSuccess &&
-            hipMalloc(&g.flags, sizeof(int32_t) * 4) == hipSuccess;
+            hipMalloc(&g.flags, sizeof(int32_t) * 4) == hipSuccess &&
+            (!comb || (hipMalloc(&g.diag, sizeof(float) * n) == hipSuccess &&
+                       hipMalloc(&g.deg, sizeof(double) * n) == hipSuccess));
   if (!ok) {
     csc_graph_destroy(h);
     return fail(CSC_E_NOMEM, "device allocation failed in csc_graph_create");
@@ -193,6 +200,8 @@ csc_status csc_graph_destroy(csc_graph h) {
   if (g.dinv) (void)hipFree(g.dinv);
   if (g.mirror) (void)hipFree(g.mirror);
   if (g.flags) (void)hipFree(g.flags);
+  if (g.diag) (void)hipFree(g.diag);
+  if (g.deg) (void)hipFree(g.deg);
   delete h;
   return CSC_OK;
 }
@@ -230,13 +239,13 @@ csc_status csc_graph_arrays(csc_graph h, const int32_t** rowptr, const int32_t**
 csc_status csc_lmax(csc_graph h, int iters, double* lmax, void* stream) {
   if (!h || !lmax) return fail(CSC_E_ARG, "null argument");
   if (iters < 0) return fail(CSC_E_ARG, "iters must be >= 0");
+  const Graph& g = h->g;
   if (iters == 0) {
-    *lmax = 2.0;
+    *lmax = g.lmax_bound;
     return CSC_OK;
   }
-  const Graph& g = h->g;
   hipStream_t s = as_stream(stream);
-  // Power iteration on L = I - A.  One application of L is the degree-1 filter
+  // Power iteration on L.  One application of L is the degree-1 filter
   // a0 T_0 + a1 T_1(L~) with lmax = 2 (L~ = L - I) and a0 = a1 = 1.
   const size_t fw = filter_workspace(g.n, 1, CSC_F32);
   const size_t dw = dot_workspace(g.n);
@@ -286,7 +295,7 @@ csc_status csc_lmax(csc_graph h, int iters, double* lmax, void* stream) {
   (void)hipStreamSynchronize(s);
   (void)hipFree(buf);
   if (st != CSC_OK) return st;
-  *lmax = std::min(2.0, 1.01 * (rq + resid));
+  *lmax = std::min(g.lmax_bound, 1.01 * (rq + resid));
   return CSC_OK;
 }
 
@@ -457,6 +466,8 @@ csc_status csc_cheb_filter_backward(csc_graph h, double lmax, int m, const doubl
                                     int ckpt_every, void* work, size_t work_bytes,
                                     void* stream) {
   if (!h || !a || !X || !G) return fail(CSC_E_ARG, "null argument");
+  if (h->g.lap != CSC_LAP_NORMALIZED)
+    return fail(CSC_E_ARG, "the adjoint is defined for the normalized Laplacian");
   CSC_TRY(graph_ensure_mirror(&h->g, as_stream(stream)));
   return run_backward(&h->g, lmax, m, a, X, ldx, G, ldg, w, dX, lddx, da, dA, ckpt_every, work,
                       work_bytes, as_stream(stream));

@@ -18,7 +18,7 @@ struct csc_dyn_s {
   csc_damping damp = CSC_DAMP_JACKSON;
   csc_dtype feat_dt = CSC_F32;
   uint64_t seed = 0;
-  double lmax = 2.0, tau = 0.0;
+  double lmax = 0.0, tau = 0.0;  // lmax 0: each snapshot uses its graph's spectrum bound
   int n_cand = 16, lloyd = 20, init = 0;
   csc_dtype iter_dt = CSC_F32;
   void* theta = nullptr;      // n x d, feat_dt
@@ -44,6 +44,7 @@ struct csc_dyn_s {
   hipEvent_t ev_start = nullptr, ev_basis[2] = {}, ev_free[2] = {};
   hipGraphExec_t exec[2] = {};
   const void* exec_key[2][10] = {};
+  double exec_lmax[2][8] = {};
   void* aux = nullptr;
   size_t aux_bytes = 0;
   int variant = 0;
@@ -108,7 +109,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   if (opts) {
     st->batch = opts->batch >= 1 ? opts->batch : 1;
     st->use_graph = opts->use_graph != 0;
-    st->lmax = opts->lmax > 0.0 ? opts->lmax : 2.0;
+    st->lmax = opts->lmax > 0.0 ? opts->lmax : 0.0;  // 0: each graph's own bound
     st->tau = opts->tau;
     st->n_cand = opts->n_cand > 0 ? opts->n_cand : 16;
     st->lloyd = opts->lloyd_iters >= 0 ? opts->lloyd_iters : 20;
@@ -221,6 +222,9 @@ void* basis_slot(csc_dyn st, int slot) {
   return static_cast<char*>(st->basis) + st->basis_bytes * static_cast<size_t>(slot);
 }
 
+// Spectrum bound a snapshot maps onto [-1, 1]: the fixed option, else the graph's own.
+double lmax_for(csc_dyn st, const Graph* g) { return st->lmax > 0.0 ? st->lmax : g->lmax_bound; }
+
 // The recurrences of S snapshots (slots buf * batch + 0..S-1), replayed from a captured graph
 // when enabled (one cached graph per buffer, re-captured when the graphs change).
 csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s, int buf = 0) {
@@ -234,11 +238,16 @@ csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s,
     return run_basis_batch(gs, S, st->lmax, st->m, X, st->feat_dt, st->qd, st->qd, st->iter_dt,
                            st->variant, B, st->basis_bytes, s, true);
   const void* key[10] = {};
+  double lms[8] = {};
   key[0] = reinterpret_cast<const void*>(static_cast<intptr_t>(S));
-  for (int i = 0; i < S; ++i) key[1 + i] = gs[i];
+  for (int i = 0; i < S; ++i) {
+    key[1 + i] = gs[i];
+    lms[i] = lmax_for(st, gs[i]);  // a graph update may change a combinatorial bound
+  }
   hipGraphExec_t& exec = st->exec[buf];
   bool same = exec != nullptr;
   for (int i = 0; i < 10 && same; ++i) same = key[i] == st->exec_key[buf][i];
+  for (int i = 0; i < 8 && same; ++i) same = lms[i] == st->exec_lmax[buf][i];
   if (!same) {
     if (exec) {
       (void)hipGraphExecDestroy(exec);
@@ -261,6 +270,7 @@ csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s,
       return fail(CSC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
     }
     for (int i = 0; i < 10; ++i) st->exec_key[buf][i] = key[i];
+    for (int i = 0; i < 8; ++i) st->exec_lmax[buf][i] = lms[i];
   }
   timing_begin(s);
   CSC_HIP(hipGraphLaunch(exec, s));
@@ -285,19 +295,20 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
   double cnt = 0.0;
   int ref = 0;
   double* mu_d = st->scal + 1;
+  const double lm = lmax_for(st, g);
 
   if (t == 1) {
     // Algorithm 1, steps 1-2: static CSC on G_1 with the d signals as eigencount probes.
     CSC_TRY(launch_randn(st->sig, st->feat_dt, st->n, st->d, st->d, 0, st->seed,
                          stream_id(t, kSignals), sigma, s));
-    CSC_TRY(run_filter(g, st->lmax, st->m, nullptr, st->sig, st->feat_dt, st->d, nullptr, CSC_F32,
+    CSC_TRY(run_filter(g, lm, st->m, nullptr, st->sig, st->feat_dt, st->d, nullptr, CSC_F32,
                        0, st->d, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
     CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
     CSC_HIP(hipStreamSynchronize(s));
-    bisect_moments(mu.data(), st->m, st->lmax, st->damp, sigma2, st->d, st->k, st->n_cand, 0.0,
-                   st->lmax, &st->lam, &cnt, nullptr);
-    cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
-    CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), st->sig, st->feat_dt, st->d, st->theta,
+    bisect_moments(mu.data(), st->m, lm, st->damp, sigma2, st->d, st->k, st->n_cand, 0.0,
+                   lm, &st->lam, &cnt, nullptr);
+    cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
+    CSC_TRY(run_filter(g, lm, st->m, a.data(), st->sig, st->feat_dt, st->d, st->theta,
                        st->feat_dt, st->d, st->d, st->iter_dt, nullptr, 0, st->fwork,
                        st->fwork_bytes, s));
     st->cursor = 0;
@@ -314,7 +325,7 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
     void* sig = sig_slot(st, slot);
     void* basis = st->basis ? basis_slot(st, slot) : nullptr;
     if (!pre_basis) CSC_TRY(draw_signals(st, t, slot, s));
-    cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
+    cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
     const bool kept = st->basis != nullptr;
     if (kept) {
       if (!pre_basis) CSC_TRY(batch_basis(st, &g, 1, s));
@@ -322,7 +333,7 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
                           st->feat_dt, ldb, sig, st->feat_dt, st->qd, st->scal, st->aux,
                           st->aux_bytes, s));
     } else {
-      CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
+      CSC_TRY(run_filter(g, lm, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
                          st->feat_dt, ldb, st->qd, st->iter_dt, nullptr, 0, st->fwork,
                          st->fwork_bytes, s));
       CSC_TRY(launch_dot(sig, st->feat_dt, st->qd, blk, st->feat_dt, ldb, st->n, st->qd,
@@ -337,21 +348,22 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
         CSC_TRY(run_basis_moments(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, mu_d,
                                   st->aux, st->aux_bytes, s));
       else
-        CSC_TRY(run_filter(g, st->lmax, st->m, nullptr, sig, st->feat_dt, st->qd, nullptr,
+        CSC_TRY(run_filter(g, lm, st->m, nullptr, sig, st->feat_dt, st->qd, nullptr,
                            CSC_F32, 0, st->qd, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
       CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
       CSC_HIP(hipStreamSynchronize(s));
-      const double lo = cnt < st->k ? st->lam : 0.0;
-      const double hi = cnt < st->k ? st->lmax : st->lam;
-      bisect_moments(mu.data(), st->m, st->lmax, st->damp, sigma2, st->qd, st->k, st->n_cand, lo,
+      const double prev = std::min(st->lam, lm);  // a combinatorial bound may shrink
+      const double lo = cnt < st->k ? prev : 0.0;
+      const double hi = cnt < st->k ? lm : prev;
+      bisect_moments(mu.data(), st->m, lm, st->damp, sigma2, st->qd, st->k, st->n_cand, lo,
                      hi, &st->lam, &cnt, nullptr);
-      cheb_coeffs(st->m, st->lmax, st->lam, st->damp, a.data());
+      cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
       if (kept)
         CSC_TRY(run_combine(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
                             st->feat_dt, ldb, nullptr, st->feat_dt, 0, nullptr, st->aux,
                             st->aux_bytes, s));
       else
-        CSC_TRY(run_filter(g, st->lmax, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
+        CSC_TRY(run_filter(g, lm, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
                            st->feat_dt, ldb, st->qd, st->iter_dt, nullptr, 0, st->fwork,
                            st->fwork_bytes, s));
       ref = 1;

@@ -77,6 +77,10 @@ struct Graph {
   int32_t* colidx = nullptr;  // cap
   void* vals = nullptr;       // cap, val_dt
   double* dinv = nullptr;     // n
+  csc_laplacian lap = CSC_LAP_NORMALIZED;
+  float* diag = nullptr;      // combinatorial only: degrees d_r (the diagonal of L)
+  double* deg = nullptr;      // combinatorial only: FP64 degrees, for the spectrum bound
+  double lmax_bound = 2.0;    // fixed spectrum bound (host copy)
   int32_t* mirror = nullptr;  // cap
   int32_t* flags = nullptr;   // validation / counters (device, 4 ints)
   int variant_f32 = -1;       // step-kernel shape chosen by the autotuner (-1 = default)

@@ -4,7 +4,9 @@
 //     acc      = sum_{c in row r} A_rc Z_j[c, :]                       (sparse gather)
 //     Z_{j+1}  = 2 (alpha Z_j[r] - beta acc) - Z_{j-1}[r]               (three-term step)
 //     Y[r]    += a_{j+1} Z_{j+1}[r]                                     (coefficient accumulate)
-// with L~ = alpha I - beta A (alpha = 2 / lmax - 1, beta = 2 / lmax).  Z_{j+1} overwrites
+// with L~ = alpha I - beta A (alpha = 2 / lmax - 1, beta = 2 / lmax) for the normalized
+// Laplacian; for the combinatorial one A is W and alpha becomes the per-row
+// 2 d_r / lmax - 1 (L~ = (2 / lmax)(D - W) - I).  Z_{j+1} overwrites
 // Z_{j-1} in place: row r reads its own Z_{j-1} row before writing it and no other row
 // reads Z_{j-1}.  Optionally the per-row dot products <Z_j, Z_j> and <Z_{j+1}, Z_j> are
 // reduced (FP64, fixed order) for the doubled Chebyshev moments.
@@ -126,9 +128,31 @@ struct StepParams {
   int64_t n;
   int64_t row_blocks;
   float alpha, beta, coef;
+  float gam;           // combinatorial: own-row factor alpha + gam d_r
+  const float* diag;   // combinatorial: d_r; null for the normalized Laplacian
   int flags;
   double* mom_part;  // [2][gridDim.x]
 };
+
+// L~ = (2 / lmax) L - I written as diag(alpha + gam d) - beta S, with S the stored matrix:
+// normalized (S = A): alpha = 2 / lmax - 1, gam = 0; combinatorial (S = W): alpha = -1,
+// gam = beta = 2 / lmax.
+struct OpScale {
+  float alpha, beta, gam;
+  const float* diag;
+  bool own() const { return alpha != 0.f || diag != nullptr; }
+};
+inline OpScale op_scale(const Graph* g, double lmax) {
+  const float b = static_cast<float>(2.0 / lmax);
+  if (g->lap == CSC_LAP_COMBINATORIAL) return {-1.f, b, b, g->diag};
+  return {static_cast<float>(2.0 / lmax - 1.0), b, 0.f, nullptr};
+}
+inline void set_op(StepParams& p, const OpScale& o) {
+  p.alpha = o.alpha;
+  p.beta = o.beta;
+  p.gam = o.gam;
+  p.diag = o.diag;
+}
 
 __device__ inline void store_out(void* y, int dt, int64_t idx, float v) {
   if (dt == CSC_F32) static_cast<float*>(y)[idx] = v;
@@ -297,17 +321,18 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
 #pragma unroll
       for (int i = 0; i < VEC; ++i) zj[i] = 0.f;
     }
+    const float al = p.diag ? fmaf(p.gam, p.diag[row], p.alpha) : p.alpha;
     float zn[VEC];
     if (p.flags & F_FIRST) {
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) zn[i] = fmaf(p.alpha, zj[i], -p.beta * acc[i]);
+      for (int i = 0; i < VEC; ++i) zn[i] = fmaf(al, zj[i], -p.beta * acc[i]);
     } else {
       float zp[VEC];
       if constexpr (MIX) ld8f(p.sprev + eoff, zp);
       else P::unpack(ld16(static_cast<const TG*>(p.zprev) + eoff), zp);
 #pragma unroll
       for (int i = 0; i < VEC; ++i)
-        zn[i] = 2.f * fmaf(p.alpha, zj[i], -p.beta * acc[i]) - zp[i];
+        zn[i] = 2.f * fmaf(al, zj[i], -p.beta * acc[i]) - zp[i];
     }
     if constexpr (MIX) {
       // the state keeps FP32; only the gathered copy is rounded
@@ -561,6 +586,7 @@ static double step_bytes(const Graph* g, int64_t n, int w, csc_dtype iter_dt, in
   const double sz = static_cast<double>(dtype_size(iter_dt));
   const double ss = iter_dt == CSC_BF16S ? 4.0 : sz;  // state element (own-row streams)
   double b = static_cast<double>(g->nnz) * (4.0 + dtype_size(g->val_dt)) + 4.0 * (n + 1);
+  if (g->diag) b += 4.0 * n;                      // degrees (combinatorial)
   const double nw = static_cast<double>(n) * w;
   b += nw * sz;                                   // gather Z_j (each row counted once)
   if ((flags & F_OWN) && iter_dt == CSC_BF16S) b += nw * ss;  // own Z_j from the state
@@ -621,8 +647,7 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
   const int64_t nb = pl.row_blocks * pl.ntiles;
   const int J = moments ? m / 2 : -1;
   const int nsteps = moments_only ? J + 1 : m;
-  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
-  const float beta = static_cast<float>(2.0 / lmax);
+  const OpScale op = op_scale(g, lmax);
   double bytes = 0.0;
   timing_begin(s);
   for (int j = 0; j < nsteps; ++j) {
@@ -641,8 +666,7 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
     p.w = w;
     p.n = n;
     p.row_blocks = pl.row_blocks;
-    p.alpha = alpha;
-    p.beta = beta;
+    set_op(p, op);
     p.coef = static_cast<float>(do_acc ? a[j + 1] : 0.0);
     const bool last = j == nsteps - 1;
     const bool mom = moments && j <= J;
@@ -660,7 +684,7 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
       p.mom_part = part + static_cast<int64_t>(j) * 2 * nb;
     }
     if (!last) flags |= F_STORE;
-    if (mom || alpha != 0.f) flags |= F_OWN;
+    if (mom || op.own()) flags |= F_OWN;
     p.flags = flags;
     hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, p);
     bytes += step_bytes(g, n, w, iter_dt, flags, y_dt);
@@ -894,8 +918,10 @@ csc_status run_backward(const Graph* g, double lmax, int m, const double* a, con
   double* part = reinterpret_cast<double*>(base + L.off_part);
   const size_t tiled_bytes = static_cast<size_t>(n) * pl.wpad * sizeof(float);
   const unsigned eblocks = static_cast<unsigned>((n * pl.wpad + 255) / 256);
-  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
-  const float beta = static_cast<float>(2.0 / lmax);
+  if (g->lap != CSC_LAP_NORMALIZED) return fail(CSC_E_ARG, "the adjoint is defined for the normalized Laplacian");
+  const OpScale op = op_scale(g, lmax);
+  const float alpha = op.alpha;
+  const float beta = op.beta;
   const int64_t nb = pl.row_blocks * pl.ntiles;
   const StepFn fstep = pick_step<float>(pl.shape.lpr, g->val_dt);
   const int gblocks = static_cast<int>(std::min<int64_t>(kGdotBlocks, std::max<int64_t>(1, (n * w + kThreads - 1) / kThreads)));
@@ -926,9 +952,8 @@ csc_status run_backward(const Graph* g, double lmax, int m, const double* a, con
     p.n = n;
     p.w = w;
     p.row_blocks = pl.row_blocks;
-    p.alpha = alpha;
-    p.beta = beta;
-    p.flags = F_STORE | (first ? F_FIRST : 0) | (alpha != 0.f ? F_OWN : 0);
+    set_op(p, op);
+    p.flags = F_STORE | (first ? F_FIRST : 0) | (op.own() ? F_OWN : 0);
     hipLaunchKernelGGL(fstep, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, p);
   };
   auto gdot = [&](const float* Z, int j) {
@@ -1168,8 +1193,7 @@ csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtyp
   launch_init(iter_dt, X, x_dt, ldx, n, w, pl.wpad, wt, b, nullptr, 0.f, st[0], s);
   const StepFn fn = step_fn(iter_dt, pl.shape.lpr, g->val_dt);
   const int64_t nb = pl.row_blocks * pl.ntiles;
-  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
-  const float beta = static_cast<float>(2.0 / lmax);
+  const OpScale op = op_scale(g, lmax);
   double bytes_alg = 0.0;
   timing_begin(s);
   for (int j = 0; j < m; ++j) {
@@ -1186,9 +1210,8 @@ csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtyp
     p.w = w;
     p.n = n;
     p.row_blocks = pl.row_blocks;
-    p.alpha = alpha;
-    p.beta = beta;
-    p.flags = F_STORE | (j == 0 ? F_FIRST : 0) | (alpha != 0.f ? F_OWN : 0);
+    set_op(p, op);
+    p.flags = F_STORE | (j == 0 ? F_FIRST : 0) | (op.own() ? F_OWN : 0);
     hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, p);
     bytes_alg += step_bytes(g, n, w, iter_dt, p.flags, CSC_F32);
   }
@@ -1290,8 +1313,6 @@ csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m
     launch_init(iter_dt, X[i], x_dt, ldx, n, w, pl.wpad, wt, bases[i], nullptr, 0.f, state(i, 0), s);
   const BatchFn fn = batch_fn(iter_dt, pl.shape.lpr, graphs[0]->val_dt);
   const int64_t per = pl.row_blocks * pl.ntiles;
-  const float alpha = static_cast<float>(2.0 / lmax - 1.0);
-  const float beta = static_cast<float>(2.0 / lmax);
   double bytes_alg = 0.0;
   if (timed) timing_begin(s);
   for (int j = 0; j < m; ++j) {
@@ -1313,9 +1334,9 @@ csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m
       p.w = w;
       p.n = n;
       p.row_blocks = pl.row_blocks;
-      p.alpha = alpha;
-      p.beta = beta;
-      p.flags = F_STORE | (j == 0 ? F_FIRST : 0) | (alpha != 0.f ? F_OWN : 0);
+      const OpScale op = op_scale(g, lmax > 0.0 ? lmax : g->lmax_bound);
+      set_op(p, op);
+      p.flags = F_STORE | (j == 0 ? F_FIRST : 0) | (op.own() ? F_OWN : 0);
       bytes_alg += step_bytes(g, n, w, iter_dt, p.flags, CSC_F32);
     }
     hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(per * S)), dim3(kThreads), 0, s, b);

@@ -1,7 +1,10 @@
-// Operator build (Sec. 2.1): A = D^{-1/2} W D^{-1/2} from the CSR weight matrix W, on the
-// device, with optional validation of the CSR input (sorted rows, indices in range, no
-// self-loops, positive weights, symmetry).  All accesses are bounds-checked, so an invalid
-// input yields an error flag, never an out-of-range read.
+// Operator build (Sec. 2.1), on the device, from the CSR weight matrix W: the normalized
+// adjacency A = D^{-1/2} W D^{-1/2} (L = I - A), or W and the degrees (L = D - W), with
+// optional validation of the CSR input (sorted rows, indices in range, no self-loops,
+// positive weights, symmetry).  All accesses are bounds-checked, so an invalid input
+// yields an error flag, never an out-of-range read.
+#include <cstring>
+
 #include "csc_internal.h"
 
 namespace csc {
@@ -66,7 +69,7 @@ __global__ void k_rowptr32(const int64_t* rowptr, int32_t* out, int64_t n) {
 constexpr int kLPR = 8;
 
 __global__ void k_degrees(const int64_t* rowptr, const double* w, int64_t n, double* dinv,
-                          int32_t* isolated) {
+                          double* deg_out, float* diag_out, int32_t* isolated) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t r = t / kLPR;
   const int lane = static_cast<int>(t % kLPR);
@@ -81,8 +84,29 @@ __global__ void k_degrees(const int64_t* rowptr, const double* w, int64_t n, dou
   for (int off = 1; off < kLPR; off <<= 1) deg += __shfl_xor(deg, off, kLPR);
   if (r < n && lane == 0) {
     dinv[r] = deg > 0.0 ? 1.0 / sqrt(deg) : 0.0;
+    if (deg_out) deg_out[r] = deg;
+    if (diag_out) diag_out[r] = static_cast<float>(deg);
     if (re == rs) atomicAdd(isolated, 1);
   }
+}
+
+// Anderson-Morley bound max over stored entries (r, c) of d_r + d_c.  The sums are
+// non-negative doubles, whose bit patterns order like the values, so an integer atomic
+// maximum on the bits finds the largest.
+__global__ void k_am_bound(const int64_t* rowptr, const int32_t* colidx, const double* deg,
+                           int64_t n, unsigned long long* out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = t / kLPR;
+  const int lane = static_cast<int>(t % kLPR);
+  double best = 0.0;
+  if (r < n) {
+    const double dr = deg[r];
+    for (int64_t i = rowptr[r] + lane; i < rowptr[r + 1]; i += kLPR)
+      best = fmax(best, dr + deg[colidx[i]]);
+  }
+#pragma unroll
+  for (int off = 1; off < kLPR; off <<= 1) best = fmax(best, __shfl_xor(best, off, kLPR));
+  if (r < n && lane == 0 && best > 0.0) atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(best)));
 }
 
 template <typename TV>
@@ -94,6 +118,7 @@ __device__ inline uint16_t to_val<uint16_t>(double x) {
   return f32_to_bf16(static_cast<float>(x));
 }
 
+// Stored values: w_rc d_r^{-1/2} d_c^{-1/2} (normalized), or w_rc itself (dinv null).
 template <typename TV>
 __global__ void k_values(const int64_t* rowptr, const int32_t* colidx, const double* w,
                          const double* dinv, int64_t n, int32_t* colidx_out, TV* vals) {
@@ -101,11 +126,11 @@ __global__ void k_values(const int64_t* rowptr, const int32_t* colidx, const dou
   const int64_t r = t / kLPR;
   const int lane = static_cast<int>(t % kLPR);
   if (r >= n) return;
-  const double dr = dinv[r];
+  const double dr = dinv ? dinv[r] : 1.0;
   for (int64_t i = rowptr[r] + lane; i < rowptr[r + 1]; i += kLPR) {
     const int32_t c = colidx[i];
     colidx_out[i] = c;
-    vals[i] = to_val<TV>(w[i] * dr * dinv[c]);
+    vals[i] = to_val<TV>(dinv ? w[i] * dr * dinv[c] : w[i]);
   }
 }
 
@@ -167,16 +192,33 @@ csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32
   }
   g->nnz = nnz;
   hipLaunchKernelGGL(k_rowptr32, dim3(blocks_for(n + 1)), dim3(256), 0, s, rowptr, g->rowptr, n);
+  const bool comb = g->lap == CSC_LAP_COMBINATORIAL;
   hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n * kLPR)), dim3(256), 0, s, rowptr, w, n, g->dinv,
-                     g->flags + 1);
+                     comb ? g->deg : nullptr, comb ? g->diag : nullptr, g->flags + 1);
+  const double* scale = comb ? nullptr : g->dinv;
   if (g->val_dt == CSC_F32)
     hipLaunchKernelGGL(k_values<float>, dim3(blocks_for(n * kLPR)), dim3(256), 0, s, rowptr, colidx,
-                       w, g->dinv, n, g->colidx, static_cast<float*>(g->vals));
+                       w, scale, n, g->colidx, static_cast<float*>(g->vals));
   else
     hipLaunchKernelGGL(k_values<uint16_t>, dim3(blocks_for(n * kLPR)), dim3(256), 0, s, rowptr,
-                       colidx, w, g->dinv, n, g->colidx, static_cast<uint16_t*>(g->vals));
+                       colidx, w, scale, n, g->colidx, static_cast<uint16_t*>(g->vals));
   g->mirror_valid = false;
   CSC_HIP(hipGetLastError());
+  if (comb) {
+    // flags[2..3] hold the bound's bits (zeroed with the flags above)
+    auto* bits = reinterpret_cast<unsigned long long*>(g->flags + 2);
+    hipLaunchKernelGGL(k_am_bound, dim3(blocks_for(n * kLPR)), dim3(256), 0, s, rowptr, colidx,
+                       g->deg, n, bits);
+    CSC_HIP(hipGetLastError());
+    unsigned long long b = 0;
+    CSC_HIP(hipMemcpyAsync(&b, bits, sizeof(b), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    double v = 0.0;
+    std::memcpy(&v, &b, sizeof(v));
+    g->lmax_bound = v > 0.0 ? v : 1.0;
+  } else {
+    g->lmax_bound = 2.0;
+  }
   return CSC_OK;
 }
 

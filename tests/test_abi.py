@@ -79,8 +79,14 @@ def test_host_argument_errors(pkg):
         pkg.eigcount_from_moments(np.ones(5), 4, 1.0, 4, 2, 8, lo=1.5, hi=1.0)
     lib = pkg.lib
     out = ctypes.c_void_p()
-    assert lib.csc_graph_create(0, 0, 0, None, None, None, 0, 1, None, ctypes.byref(out)) == 1
+    assert lib.csc_graph_create(0, 0, 0, None, None, None, 0, 0, 1, None, ctypes.byref(out)) == 1
     assert b"n must be" in lib.csc_last_error()
+    assert lib.csc_graph_create(4, 0, 0, None, None, None, 0, 0, 1, None, ctypes.byref(out)) == 1
+    assert b"null CSR" in lib.csc_last_error()
+    # the Laplacian kind is checked before anything touches the (here fake) device pointer
+    fake = ctypes.c_void_p(256)
+    assert lib.csc_graph_create(4, 0, 0, fake, None, None, 0, 7, 1, None, ctypes.byref(out)) == 1
+    assert b"Laplacian kind" in lib.csc_last_error()
     opts = pkg.binding.DynOpts(lmax=0, tau=0, n_cand=0, lloyd_iters=-1, init=0, iter_dt=0,
                                keep_iterates=0)
     # p = 1 leaves no fresh columns, p < 0 is meaningless, and p close to 1 rounds q d to 0
