@@ -25,7 +25,13 @@ Readings where the paper is silent or leaves a choice
     from the previous labels (means of the new features under the old labels);
   * with the combinatorial Laplacian D - W and no lmax given, each snapshot maps its own
     spectrum bound (Anderson-Morley, :mod:`oracle.operator`) onto [-1, 1]; lambda_{t-1}
-    is an absolute cut-off, clipped to the new bound where a bracket needs it.
+    is an absolute cut-off, clipped to the new bound where a bracket needs it;
+  * similarity (Sec. 4 metrics): each snapshot t >= 2 reports ||L_t - L_{t-1}||_F and, with
+    sim_probes = s > 0, the estimate rho_hat of the spectral distance from the first s fresh
+    signals filtered with h^{t-1} on both graphs (:mod:`oracle.similarity`); with a
+    refresh budget, a snapshot where p * rho_hat exceeds it is processed as static CSC (all d
+    columns drawn from its signal stream, the ring restarts).  Thm 4.1 bounds the reuse term
+    by (1 + delta) p rho; the rule keeps that term under the budget.
 """
 
 from __future__ import annotations
@@ -34,7 +40,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import chebyshev, eigcount, kmeans, operator, philox
+from . import chebyshev, eigcount, kmeans, operator, philox, similarity
 
 SIGNALS = 1
 KMEANS = 2
@@ -53,6 +59,9 @@ class StepResult:
     labels: np.ndarray
     centroids: np.ndarray
     objective: list = field(default_factory=list)
+    rho_edge: float = -1.0      # ||L_t - L_{t-1}||_F (t >= 2)
+    rho_hat: float = -1.0       # filtered-signal estimate of the spectral distance, if asked
+    refreshed: bool = False     # all d columns recomputed by the refresh rule
 
 
 def run_kmeans(F: np.ndarray, k: int, iters: int, seed: int, t: int, init: str,
@@ -69,7 +78,8 @@ class DynamicCSC:
     def __init__(self, n: int, d: int, k: int, p: float, m: int, seed: int,
                  lmax: float | None = None, damping: str = "jackson", n_cand: int = 16,
                  lloyd_iters: int = 20, tau: float | None = None, init: str = "kmeans++",
-                 storage=np.float64, laplacian: str = "normalized"):
+                 storage=np.float64, laplacian: str = "normalized",
+                 sim_probes: int = 0, refresh_budget: float | None = None):
         self.n, self.d, self.k, self.p, self.m = n, d, k, p, m
         self.qd = int(round((1.0 - p) * d))
         if self.qd < 1 or self.qd > d:
@@ -77,6 +87,11 @@ class DynamicCSC:
         if laplacian not in ("normalized", "combinatorial"):
             raise ValueError(laplacian)
         self.laplacian = laplacian
+        if not 0 <= sim_probes <= self.qd:
+            raise ValueError("need 0 <= sim_probes <= (1 - p) d")
+        self.sim_probes = sim_probes
+        self.refresh_budget = refresh_budget
+        self.prev = None            # (operator, lmax) of G_{t-1}
         self.seed = seed
         self.lmax = lmax
         self.damping = damping
@@ -109,14 +124,10 @@ class DynamicCSC:
         self.t += 1
         t = self.t
         sigma2 = self.sigma ** 2
+        rho_edge = rho_hat = -1.0
+        refreshed = False
         if t == 1:
-            R = self._signals(self.d, t)
-            mu = eigcount.moments_direct(A, lmax, self.m, R)
-            lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, lmax, self.damping,
-                                                   sigma2, self.d, self.k, self.n_cand,
-                                                   0.0, lmax)
-            a = chebyshev.step_coefficients(self.m, lmax, lam, self.damping)
-            self.theta = chebyshev.filter_recurrence(A, lmax, a, R)
+            lam, cnt = self._static(A, lmax, t)
             refined = True
         else:
             R = self._signals(self.qd, t)
@@ -125,22 +136,53 @@ class DynamicCSC:
             cnt = float(np.sum(R * Y) / (sigma2 * self.qd))
             lam = self.lam
             refined = False
-            if abs(cnt - self.k) > self.tau:
-                mu = eigcount.moments_direct(A, lmax, self.m, R)
-                prev = min(self.lam, lmax)
-                lo, hi = (prev, lmax) if cnt < self.k else (0.0, prev)
-                lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, lmax, self.damping,
-                                                       sigma2, self.qd, self.k, self.n_cand,
-                                                       lo, hi)
-                a = chebyshev.step_coefficients(self.m, lmax, lam, self.damping)
-                Y = chebyshev.filter_recurrence(A, lmax, a, R)
-                refined = True
-            cols = (self.cursor + np.arange(self.qd)) % self.d
-            self.theta[:, cols] = Y
-            self.cursor = (self.cursor + self.qd) % self.d
+            # similarity of G_t to G_{t-1} (Sec. 4 metrics), and the refresh rule of Thm 4.1:
+            # the reuse term grows like p * rho, so a snapshot whose estimated spectral
+            # distance exceeds budget / p recomputes every feature
+            A_prev, lmax_prev = self.prev
+            rho_edge = similarity.edge_distance(A_prev, A)
+            if self.sim_probes > 0:
+                s_ = self.sim_probes
+                a_prev = chebyshev.step_coefficients(self.m, lmax_prev, min(self.lam, lmax_prev),
+                                                     self.damping)
+                Y_prev = chebyshev.filter_recurrence(A_prev, lmax_prev, a_prev, R[:, :s_])
+                rho_hat = float(np.sqrt(np.sum((Y[:, :s_] - Y_prev) ** 2) / (sigma2 * s_)))
+            if (self.refresh_budget is not None and rho_hat >= 0.0
+                    and self.p * rho_hat > self.refresh_budget):
+                lam, cnt = self._static(A, lmax, t)
+                refined = refreshed = True
+            else:
+                if abs(cnt - self.k) > self.tau:
+                    mu = eigcount.moments_direct(A, lmax, self.m, R)
+                    prev = min(self.lam, lmax)
+                    lo, hi = (prev, lmax) if cnt < self.k else (0.0, prev)
+                    lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, lmax, self.damping,
+                                                           sigma2, self.qd, self.k, self.n_cand,
+                                                           lo, hi)
+                    a = chebyshev.step_coefficients(self.m, lmax, lam, self.damping)
+                    Y = chebyshev.filter_recurrence(A, lmax, a, R)
+                    refined = True
+                cols = (self.cursor + np.arange(self.qd)) % self.d
+                self.theta[:, cols] = Y
+                self.cursor = (self.cursor + self.qd) % self.d
         self.lam = lam
+        self.prev = (A, lmax)
         lab, C, obj = run_kmeans(self.theta, self.k, self.lloyd_iters, self.seed, t,
                                  self.init, self.labels)
         self.labels = lab
         return StepResult(t=t, lam=lam, count=cnt, refined=refined, labels=lab,
-                          centroids=C, objective=obj)
+                          centroids=C, objective=obj, rho_edge=rho_edge, rho_hat=rho_hat,
+                          refreshed=refreshed)
+
+    def _static(self, A, lmax: float, t: int):
+        """Static CSC on this snapshot: d signals, their moments as eigencount probes, the
+        dichotomy on [0, lmax], the filter at the found cut-off; the ring restarts."""
+        sigma2 = self.sigma ** 2
+        R = self._signals(self.d, t)
+        mu = eigcount.moments_direct(A, lmax, self.m, R)
+        lam, cnt, _ = eigcount.eigcount_bisect(mu, self.m, lmax, self.damping, sigma2, self.d,
+                                               self.k, self.n_cand, 0.0, lmax)
+        a = chebyshev.step_coefficients(self.m, lmax, lam, self.damping)
+        self.theta = chebyshev.filter_recurrence(A, lmax, a, R)
+        self.cursor = 0
+        return lam, cnt
