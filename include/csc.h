@@ -113,6 +113,13 @@ csc_status csc_graph_arrays(csc_graph g, const int32_t** rowptr, const int32_t**
  * residual L x - rho x (|x| = 1).  Allocates temporary device memory.  Synchronising. */
 csc_status csc_lmax(csc_graph g, int iters, double* lmax, void* stream);
 
+/* Edge similarity of two snapshots (Sec. 4, the metrics of graph similarity):
+ * *rho = ||L(g2) - L(g1)||_F, summed in FP64 over the union of the two sparsity patterns
+ * from the stored values (plus the degrees for L = D - W).  Both graphs must have the same
+ * n and Laplacian kind (CSC_E_ARG otherwise).  With BF16 values the result carries their
+ * rounding.  Allocates temporary device memory.  Synchronising. */
+csc_status csc_graph_distance(csc_graph g1, csc_graph g2, double* rho, void* stream);
+
 /* ---------------------------------------------------------------------------------
  * Chebyshev coefficients of the ideal low-pass (Sec. 3.2): h(lambda) = sum_{j=0..m}
  * a[j] T_j(2 lambda / lmax - 1) approximates the step 1[lambda <= lambda_c] of the
@@ -282,6 +289,17 @@ typedef struct {
   int variant;        /* recurrence kernel shape (row group x column tile) for the fresh
                          block, e.g. the one csc_autotune picked on the first snapshot;
                          -1: the widest tile not wider than (1 - p) d */
+  int track_similarity; /* non-zero: keep a device copy of the previous snapshot's operator
+                         and report ||L_t - L_{t-1}||_F per snapshot (csc_dyn_similarity) */
+  int sim_probes;     /* s in [0, (1 - p) d]: also estimate the spectral distance
+                         ||H_k^t - H_k^{t-1}||_F as ||h(L_t) R_s - h(L_{t-1}) R_s||_F /
+                         sqrt(s / d), with R_s the first s fresh signals and h the previous
+                         filter on both graphs (one extra filter of s columns) */
+  double refresh_budget; /* > 0 (needs sim_probes > 0): a snapshot where p times the estimate
+                         exceeds the budget (the reuse term of Thm 4.1) is processed as static
+                         CSC: all d columns drawn from its signal stream, a dichotomy on
+                         [0, lmax], the ring restarted.  Any of the three similarity options
+                         makes csc_dynamic_steps process snapshots one at a time. */
 } csc_dyn_opts;
 
 csc_status csc_dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp,
@@ -297,6 +315,11 @@ csc_status csc_dynamic_step(csc_dyn st, csc_graph g_t, int32_t* labels, double* 
  * Synchronising. */
 csc_status csc_dynamic_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
                              double* lambdas, int* refined, double* counts, void* stream);
+/* Similarity record of snapshot t (1-based, already processed): the edge distance and the
+ * spectral-distance estimate (-1 where not computed: t = 1 or the option off) and whether
+ * the refresh rule fired.  Host call, no device work. */
+csc_status csc_dyn_similarity(csc_dyn st, int t, double* rho_edge, double* rho_hat,
+                              int* refreshed);
 /* Device view of Theta (n x d, type *dt, leading dimension *ld) and the centroids
  * (float[k * d]).  Valid until destroy. */
 csc_status csc_dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,

@@ -58,7 +58,8 @@ class DynOpts(C.Structure):
     _fields_ = [("lmax", C.c_double), ("tau", C.c_double), ("n_cand", C.c_int),
                 ("lloyd_iters", C.c_int), ("init", C.c_int), ("iter_dt", C.c_int),
                 ("keep_iterates", C.c_int), ("batch", C.c_int), ("use_graph", C.c_int),
-                ("variant", C.c_int)]
+                ("variant", C.c_int), ("track_similarity", C.c_int), ("sim_probes", C.c_int),
+                ("refresh_budget", C.c_double)]
 
 
 _SIGS = {
@@ -71,6 +72,7 @@ _SIGS = {
     "csc_graph_arrays": ([vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), pint, C.POINTER(vp),
                           C.POINTER(vp)], i32),
     "csc_lmax": ([vp, i32, pdbl, vp], i32),
+    "csc_graph_distance": ([vp, vp, pdbl, vp], i32),
     "csc_cheb_coeffs": ([i32, dbl, dbl, i32, pdbl], i32),
     "csc_cheb_filter_workspace_bytes": ([i64, i32, i32], sz),
     "csc_cheb_filter": ([vp, dbl, i32, pdbl, vp, i32, i64, vp, i32, i64, i32, i32, vp, vp, sz,
@@ -95,6 +97,7 @@ _SIGS = {
     "csc_dynamic_step": ([vp, vp, vp, pdbl, pint, pdbl, vp], i32),
     "csc_dynamic_steps": ([vp, C.POINTER(vp), i32, C.POINTER(vp), pdbl, pint, pdbl, vp], i32),
     "csc_dyn_features": ([vp, C.POINTER(vp), pint, pi64, C.POINTER(vp)], i32),
+    "csc_dyn_similarity": ([vp, i32, pdbl, pdbl, pint], i32),
     "csc_dyn_destroy": ([vp], i32),
     "csc_cheb_backward_workspace_bytes": ([i64, i32, i32, i32], sz),
     "csc_cheb_filter_backward": ([vp, dbl, i32, pdbl, vp, i64, vp, i64, i32, vp, i64, vp, vp, i32,
@@ -262,6 +265,12 @@ class Graph:
     def lmax(self, iters: int = 0, stream=None) -> float:
         v = C.c_double()
         _check(lib.csc_lmax(self.h, int(iters), C.byref(v), _stream(stream)))
+        return v.value
+
+    def distance(self, other: "Graph", stream=None) -> float:
+        """Edge similarity ||L(other) - L(self)||_F."""
+        v = C.c_double()
+        _check(lib.csc_graph_distance(self.h, other.h, C.byref(v), _stream(stream)))
         return v.value
 
     def autotune(self, w: int, iter_dtype=torch.float32, stream=None) -> int:
@@ -464,10 +473,13 @@ class DynamicCSC:
                  damping: int = DAMP_JACKSON, feat_dtype=torch.float32, iter_dtype=torch.float32,
                  lmax: float = 0.0, tau: float = 0.0, n_cand: int = 16, lloyd_iters: int = 20,
                  init: int = 0, keep_iterates: int = -1, batch: int = 1, use_graph: bool = False,
-                 variant: int = -1):
+                 variant: int = -1, track_similarity: bool = False, sim_probes: int = 0,
+                 refresh_budget: float = 0.0):
         opts = DynOpts(lmax=lmax, tau=tau, n_cand=n_cand, lloyd_iters=lloyd_iters, init=init,
                        iter_dt=_it(iter_dtype), keep_iterates=keep_iterates, batch=batch,
-                       use_graph=int(bool(use_graph)), variant=int(variant))
+                       use_graph=int(bool(use_graph)), variant=int(variant),
+                       track_similarity=int(bool(track_similarity)), sim_probes=int(sim_probes),
+                       refresh_budget=float(refresh_budget))
         h = C.c_void_p()
         if keep_iterates < 0:
             release_workspace()
@@ -499,6 +511,12 @@ class DynamicCSC:
         cnt = (C.c_double * S)()
         _check(lib.csc_dynamic_steps(self.h, gh, S, lp, lam, ref, cnt, _stream(stream)))
         return labels, list(lam), [bool(x) for x in ref], list(cnt)
+
+    def similarity(self, t: int):
+        """(rho_edge, rho_hat, refreshed) of snapshot t (1-based); -1 where not computed."""
+        re_, rh, rf = C.c_double(), C.c_double(), C.c_int()
+        _check(lib.csc_dyn_similarity(self.h, int(t), C.byref(re_), C.byref(rh), C.byref(rf)))
+        return re_.value, rh.value, bool(rf.value)
 
     def features(self) -> torch.Tensor:
         th, dt, ld, cp = C.c_void_p(), C.c_int(), C.c_int64(), C.c_void_p()

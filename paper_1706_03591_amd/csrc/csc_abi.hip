@@ -120,6 +120,7 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
                      double* lambdas, int* refined, double* counts, void* stream);
 csc_status dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,
                         const float** centroids);
+csc_status dyn_similarity(csc_dyn st, int t, double* rho_edge, double* rho_hat, int* refreshed);
 csc_status dyn_destroy(csc_dyn st);
 size_t backward_workspace(int64_t n, int w, int m, int ckpt);
 csc_status run_backward(const Graph* g, double lmax, int m, const double* a, const float* X,
@@ -234,6 +235,24 @@ csc_status csc_graph_arrays(csc_graph h, const int32_t** rowptr, const int32_t**
   if (dinv) *dinv = h->g.dinv;
   if (mirror) *mirror = h->g.mirror;
   return CSC_OK;
+}
+
+csc_status csc_graph_distance(csc_graph g1, csc_graph g2, double* rho, void* stream) {
+  if (!g1 || !g2 || !rho) return fail(CSC_E_ARG, "null argument");
+  hipStream_t s = as_stream(stream);
+  const size_t wb = distance_workspace(g1->g.n) + 256;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, wb) != hipSuccess) return fail(CSC_E_NOMEM, "csc_graph_distance: allocation failed");
+  double* out = static_cast<double*>(buf);
+  csc_status st = graph_distance2(&g1->g, &g2->g, out, static_cast<char*>(buf) + 256, wb - 256, s);
+  double v = 0.0;
+  if (st == CSC_OK && (hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                       hipStreamSynchronize(s) != hipSuccess))
+    st = fail(CSC_E_HIP, "csc_graph_distance: copy failed");
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (st == CSC_OK) *rho = std::sqrt(v);
+  return st;
 }
 
 csc_status csc_lmax(csc_graph h, int iters, double* lmax, void* stream) {
@@ -449,6 +468,11 @@ csc_status csc_dynamic_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t
 csc_status csc_dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,
                             const float** centroids) {
   return dyn_features(st, theta, dt, ld, centroids);
+}
+
+csc_status csc_dyn_similarity(csc_dyn st, int t, double* rho_edge, double* rho_hat,
+                              int* refreshed) {
+  return dyn_similarity(st, t, rho_edge, rho_hat, refreshed);
 }
 
 csc_status csc_dyn_destroy(csc_dyn st) { return dyn_destroy(st); }

@@ -52,6 +52,17 @@ struct csc_dyn_s {
   double lam = 0.0;
   int cursor = 0;             // first column of Theta the next fresh block replaces
   void* wrap = nullptr;       // n x qd staging of a fresh block that wraps past column d
+  // similarity of consecutive snapshots (Sec. 4 metrics) and the refresh rule
+  bool track = false;
+  int sim_probes = 0;
+  double budget = 0.0;
+  csc::Graph pg{};            // device copy of the previous snapshot's operator
+  bool have_prev = false;
+  float* simbuf = nullptr;    // n x sim_probes: h^{t-1}(L_{t-1}) applied to the first probes
+  double* simd = nullptr;     // device: [0] ||dL||_F^2, [1..3] <Y,Y>, <Y,Yp>, <Yp,Yp>
+  void* simwork = nullptr;
+  size_t simwork_bytes = 0;
+  std::vector<double> hist;   // per snapshot: rho_edge, rho_hat, refreshed
 };
 
 namespace csc {
@@ -66,7 +77,9 @@ void free_dyn(csc_dyn st) {
   if (!st) return;
   for (void* p : {st->theta, st->sig, static_cast<void*>(st->C), static_cast<void*>(st->prev),
                   static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork, st->basis, st->aux,
-                  st->wrap})
+                  st->wrap, static_cast<void*>(st->simbuf), static_cast<void*>(st->simd),
+                  st->simwork, static_cast<void*>(st->pg.rowptr), static_cast<void*>(st->pg.colidx),
+                  st->pg.vals, static_cast<void*>(st->pg.diag), static_cast<void*>(st->pg.deg)})
     if (p) (void)hipFree(p);
   for (int b = 0; b < 2; ++b) {
     if (st->exec[b]) (void)hipGraphExecDestroy(st->exec[b]);
@@ -115,6 +128,13 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     st->lloyd = opts->lloyd_iters >= 0 ? opts->lloyd_iters : 20;
     st->init = opts->init;
     st->iter_dt = opts->iter_dt;
+    st->sim_probes = opts->sim_probes;
+    st->budget = opts->refresh_budget;
+    st->track = opts->track_similarity != 0 || opts->sim_probes > 0 || opts->refresh_budget > 0.0;
+  }
+  if (st->sim_probes < 0 || st->sim_probes > qd || (st->budget > 0.0 && st->sim_probes == 0)) {
+    delete st;
+    return fail(CSC_E_ARG, "need 0 <= sim_probes <= (1 - p) d, and sim_probes > 0 for a refresh budget");
   }
   if (st->tau <= 0.0) st->tau = std::max(0.5, 2.0 * std::sqrt(2.0 * k / qd));
   if (!iter_type_ok(st->iter_dt)) {
@@ -142,6 +162,13 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
             hipMalloc(&st->kwork, st->kwork_bytes) == hipSuccess &&
             hipMalloc(&st->dwork, st->dwork_bytes) == hipSuccess &&
             (d % qd == 0 || hipMalloc(&st->wrap, es * n * qd) == hipSuccess);
+  if (ok && st->track) {
+    st->simwork_bytes = distance_workspace(n);
+    ok = hipMalloc(&st->simd, 4 * sizeof(double)) == hipSuccess &&
+         hipMalloc(&st->simwork, st->simwork_bytes) == hipSuccess &&
+         (st->sim_probes == 0 ||
+          hipMalloc(&st->simbuf, sizeof(float) * n * st->sim_probes) == hipSuccess);
+  }
   if (!ok) {
     free_dyn(st);
     return fail(CSC_E_NOMEM, "device allocation failed in csc_dyn_create");
@@ -282,6 +309,69 @@ csc_status batch_basis(csc_dyn st, const Graph* const* gs, int S, hipStream_t s,
 
 namespace {
 
+// Device copy of this snapshot's operator, for the similarity of the next one.  The copy
+// grows (synchronising) when a snapshot has more entries than it holds.
+csc_status keep_prev(csc_dyn st, const Graph* g, hipStream_t s) {
+  Graph& p = st->pg;
+  const bool comb = g->lap == CSC_LAP_COMBINATORIAL;
+  const size_t es = dtype_size(g->val_dt);
+  if (!p.rowptr || p.cap < g->nnz || p.val_dt != g->val_dt || (comb && !p.diag)) {
+    CSC_HIP(hipStreamSynchronize(s));
+    for (void* q : {static_cast<void*>(p.rowptr), static_cast<void*>(p.colidx), p.vals,
+                    static_cast<void*>(p.diag), static_cast<void*>(p.deg)})
+      if (q) (void)hipFree(q);
+    p = Graph{};
+    p.cap = std::max<int64_t>(g->cap, 1);
+    p.val_dt = g->val_dt;
+    const bool ok = hipMalloc(&p.rowptr, sizeof(int32_t) * (g->n + 1)) == hipSuccess &&
+                    hipMalloc(&p.colidx, sizeof(int32_t) * p.cap) == hipSuccess &&
+                    hipMalloc(&p.vals, es * p.cap) == hipSuccess &&
+                    (!comb || (hipMalloc(&p.diag, sizeof(float) * g->n) == hipSuccess &&
+                               hipMalloc(&p.deg, sizeof(double) * g->n) == hipSuccess));
+    if (!ok) return fail(CSC_E_NOMEM, "cannot allocate the copy of the previous snapshot");
+  }
+  CSC_HIP(hipMemcpyAsync(p.rowptr, g->rowptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToDevice, s));
+  if (g->nnz > 0) {
+    CSC_HIP(hipMemcpyAsync(p.colidx, g->colidx, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToDevice, s));
+    CSC_HIP(hipMemcpyAsync(p.vals, g->vals, es * g->nnz, hipMemcpyDeviceToDevice, s));
+  }
+  if (comb) {
+    CSC_HIP(hipMemcpyAsync(p.diag, g->diag, sizeof(float) * g->n, hipMemcpyDeviceToDevice, s));
+    CSC_HIP(hipMemcpyAsync(p.deg, g->deg, sizeof(double) * g->n, hipMemcpyDeviceToDevice, s));
+  }
+  p.n = g->n;
+  p.nnz = g->nnz;
+  p.lap = g->lap;
+  p.lmax_bound = g->lmax_bound;
+  p.variant_f32 = g->variant_f32;
+  p.variant_bf16 = g->variant_bf16;
+  st->have_prev = true;
+  return CSC_OK;
+}
+
+// Static CSC on snapshot t (Algorithm 1 steps 1-2, and the refresh): d signals from the
+// snapshot's stream, their moments as eigencount probes, a dichotomy on [0, lm], the filter
+// of all d columns at the found cut-off into Theta; the ring restarts.
+csc_status static_pass(csc_dyn st, const Graph* g, double lm, int t, double* cnt, hipStream_t s) {
+  const double sigma = 1.0 / std::sqrt(static_cast<double>(st->d));
+  std::vector<double> a(st->m + 1), mu(st->m + 1);
+  double* mu_d = st->scal + 1;
+  CSC_TRY(launch_randn(st->sig, st->feat_dt, st->n, st->d, st->d, 0, st->seed,
+                       stream_id(t, kSignals), sigma, s));
+  CSC_TRY(run_filter(g, lm, st->m, nullptr, st->sig, st->feat_dt, st->d, nullptr, CSC_F32,
+                     0, st->d, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
+  CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  bisect_moments(mu.data(), st->m, lm, st->damp, sigma * sigma, st->d, st->k, st->n_cand, 0.0,
+                 lm, &st->lam, cnt, nullptr);
+  cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
+  CSC_TRY(run_filter(g, lm, st->m, a.data(), st->sig, st->feat_dt, st->d, st->theta,
+                     st->feat_dt, st->d, st->d, st->iter_dt, nullptr, 0, st->fwork,
+                     st->fwork_bytes, s));
+  st->cursor = 0;
+  return CSC_OK;
+}
+
 // One snapshot of Algorithm 1.  For t >= 2 the fresh signals and (when kept) their iterates
 // live in slot `slot`; with pre_basis the signals are drawn and the iterates computed already
 // (batched recurrence).
@@ -297,21 +387,11 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
   double* mu_d = st->scal + 1;
   const double lm = lmax_for(st, g);
 
+  double rho_e = -1.0, rho_h = -1.0;
+  bool refresh = false;
   if (t == 1) {
     // Algorithm 1, steps 1-2: static CSC on G_1 with the d signals as eigencount probes.
-    CSC_TRY(launch_randn(st->sig, st->feat_dt, st->n, st->d, st->d, 0, st->seed,
-                         stream_id(t, kSignals), sigma, s));
-    CSC_TRY(run_filter(g, lm, st->m, nullptr, st->sig, st->feat_dt, st->d, nullptr, CSC_F32,
-                       0, st->d, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
-    CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
-    CSC_HIP(hipStreamSynchronize(s));
-    bisect_moments(mu.data(), st->m, lm, st->damp, sigma2, st->d, st->k, st->n_cand, 0.0,
-                   lm, &st->lam, &cnt, nullptr);
-    cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
-    CSC_TRY(run_filter(g, lm, st->m, a.data(), st->sig, st->feat_dt, st->d, st->theta,
-                       st->feat_dt, st->d, st->d, st->iter_dt, nullptr, 0, st->fwork,
-                       st->fwork_bytes, s));
-    st->cursor = 0;
+    CSC_TRY(static_pass(st, g, lm, t, &cnt, s));
     ref = 1;
   } else {
     // Steps 4-7: fresh q d columns filtered with h^{t-1}, eigencount, optional refinement.
@@ -343,40 +423,78 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
     CSC_HIP(hipMemcpyAsync(&dot, st->scal, sizeof(double), hipMemcpyDeviceToHost, s));
     CSC_HIP(hipStreamSynchronize(s));
     cnt = dot / (sigma2 * st->qd);
-    if (std::fabs(cnt - st->k) > st->tau) {
-      if (kept)
-        CSC_TRY(run_basis_moments(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, mu_d,
-                                  st->aux, st->aux_bytes, s));
-      else
-        CSC_TRY(run_filter(g, lm, st->m, nullptr, sig, st->feat_dt, st->qd, nullptr,
-                           CSC_F32, 0, st->qd, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
-      CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
+    if (st->track && st->have_prev && st->pg.n == g->n && st->pg.lap == g->lap) {
+      // Sec. 4 metrics against G_{t-1}: ||L_t - L_{t-1}||_F, and the spectral distance
+      // estimated from the first s fresh signals filtered with h^{t-1} on both graphs
+      CSC_TRY(graph_distance2(&st->pg, g, st->simd, st->simwork, st->simwork_bytes, s));
+      const int sp = st->sim_probes;
+      if (sp > 0) {
+        const double lmp = lmax_for(st, &st->pg);
+        std::vector<double> ap(st->m + 1);
+        cheb_coeffs(st->m, lmp, std::min(st->lam, lmp), st->damp, ap.data());
+        CSC_TRY(run_filter(&st->pg, lmp, st->m, ap.data(), sig, st->feat_dt, st->qd, st->simbuf,
+                           CSC_F32, sp, sp, st->iter_dt, nullptr, 0, st->fwork, st->fwork_bytes, s));
+        CSC_TRY(launch_dot(blk, st->feat_dt, ldb, blk, st->feat_dt, ldb, st->n, sp, st->simd + 1,
+                           st->dwork, st->dwork_bytes, s));
+        CSC_TRY(launch_dot(blk, st->feat_dt, ldb, st->simbuf, CSC_F32, sp, st->n, sp, st->simd + 2,
+                           st->dwork, st->dwork_bytes, s));
+        CSC_TRY(launch_dot(st->simbuf, CSC_F32, sp, st->simbuf, CSC_F32, sp, st->n, sp, st->simd + 3,
+                           st->dwork, st->dwork_bytes, s));
+      }
+      double v[4] = {};
+      CSC_HIP(hipMemcpyAsync(v, st->simd, sizeof(v), hipMemcpyDeviceToHost, s));
       CSC_HIP(hipStreamSynchronize(s));
-      const double prev = std::min(st->lam, lm);  // a combinatorial bound may shrink
-      const double lo = cnt < st->k ? prev : 0.0;
-      const double hi = cnt < st->k ? lm : prev;
-      bisect_moments(mu.data(), st->m, lm, st->damp, sigma2, st->qd, st->k, st->n_cand, lo,
-                     hi, &st->lam, &cnt, nullptr);
-      cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
-      if (kept)
-        CSC_TRY(run_combine(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
-                            st->feat_dt, ldb, nullptr, st->feat_dt, 0, nullptr, st->aux,
-                            st->aux_bytes, s));
-      else
-        CSC_TRY(run_filter(g, lm, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
-                           st->feat_dt, ldb, st->qd, st->iter_dt, nullptr, 0, st->fwork,
-                           st->fwork_bytes, s));
+      rho_e = std::sqrt(std::max(0.0, v[0]));
+      if (sp > 0) rho_h = std::sqrt(std::max(0.0, v[1] - 2.0 * v[2] + v[3]) / (sigma2 * sp));
+      // Thm 4.1: reusing a fraction p adds about p * rho to the cost bound
+      refresh = st->budget > 0.0 && rho_h >= 0.0 && st->p * rho_h > st->budget;
+    }
+    if (refresh) {
+      CSC_TRY(static_pass(st, g, lm, t, &cnt, s));
       ref = 1;
+    } else {
+      if (std::fabs(cnt - st->k) > st->tau) {
+        if (kept)
+          CSC_TRY(run_basis_moments(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, mu_d,
+                                    st->aux, st->aux_bytes, s));
+        else
+          CSC_TRY(run_filter(g, lm, st->m, nullptr, sig, st->feat_dt, st->qd, nullptr,
+                             CSC_F32, 0, st->qd, st->iter_dt, mu_d, 1, st->fwork, st->fwork_bytes, s));
+        CSC_HIP(hipMemcpyAsync(mu.data(), mu_d, sizeof(double) * (st->m + 1), hipMemcpyDeviceToHost, s));
+        CSC_HIP(hipStreamSynchronize(s));
+        const double prev = std::min(st->lam, lm);  // a combinatorial bound may shrink
+        const double lo = cnt < st->k ? prev : 0.0;
+        const double hi = cnt < st->k ? lm : prev;
+        bisect_moments(mu.data(), st->m, lm, st->damp, sigma2, st->qd, st->k, st->n_cand, lo,
+                       hi, &st->lam, &cnt, nullptr);
+        cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
+        if (kept)
+          CSC_TRY(run_combine(basis, st->n, st->qd, st->m, st->iter_dt, st->variant, a.data(), blk,
+                              st->feat_dt, ldb, nullptr, st->feat_dt, 0, nullptr, st->aux,
+                              st->aux_bytes, s));
+        else
+          CSC_TRY(run_filter(g, lm, st->m, a.data(), sig, st->feat_dt, st->qd, blk,
+                             st->feat_dt, ldb, st->qd, st->iter_dt, nullptr, 0, st->fwork,
+                             st->fwork_bytes, s));
+        ref = 1;
+      }
+      if (wraps) {
+        const int first = st->d - c0;  // columns c0 .. d-1, then 0 .. qd - first - 1
+        char* th = static_cast<char*>(st->theta);
+        CSC_HIP(hipMemcpy2DAsync(th + es * static_cast<size_t>(c0), es * st->d, blk, es * st->qd,
+                                 es * first, st->n, hipMemcpyDeviceToDevice, s));
+        CSC_HIP(hipMemcpy2DAsync(th, es * st->d, blk + es * static_cast<size_t>(first), es * st->qd,
+                                 es * (st->qd - first), st->n, hipMemcpyDeviceToDevice, s));
+      }
+      st->cursor = (c0 + st->qd) % st->d;
     }
-    if (wraps) {
-      const int first = st->d - c0;  // columns c0 .. d-1, then 0 .. qd - first - 1
-      char* th = static_cast<char*>(st->theta);
-      CSC_HIP(hipMemcpy2DAsync(th + es * static_cast<size_t>(c0), es * st->d, blk, es * st->qd,
-                               es * first, st->n, hipMemcpyDeviceToDevice, s));
-      CSC_HIP(hipMemcpy2DAsync(th, es * st->d, blk + es * static_cast<size_t>(first), es * st->qd,
-                               es * (st->qd - first), st->n, hipMemcpyDeviceToDevice, s));
-    }
-    st->cursor = (c0 + st->qd) % st->d;
+  }
+  if (st->track) {
+    CSC_TRY(keep_prev(st, g, s));
+    st->hist.resize(3 * static_cast<size_t>(t), -1.0);
+    st->hist[3 * (t - 1)] = rho_e;
+    st->hist[3 * (t - 1) + 1] = rho_h;
+    st->hist[3 * (t - 1) + 2] = refresh ? 1.0 : 0.0;
   }
 
   // Step 8: k-means on Theta_t.
@@ -429,8 +547,8 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
     return std::make_tuple(lambdas ? lambdas + j : nullptr, refined ? refined + j : nullptr,
                            counts ? counts + j : nullptr);
   };
-  // the first snapshot, or no kept iterates: one at a time
-  while (i < S && (st->t == 0 || !st->basis)) {
+  // the first snapshot, no kept iterates, or similarity tracking: one at a time
+  while (i < S && (st->t == 0 || !st->basis || st->track)) {
     auto [l, r, c] = out(i);
     CSC_TRY(step_impl(st, &graphs[i]->g, 0, false, labels[i], l, r, c, s));
     ++i;
@@ -484,6 +602,16 @@ csc_status dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* 
   if (dt) *dt = st->feat_dt;
   if (ld) *ld = st->d;
   if (centroids) *centroids = st->C;
+  return CSC_OK;
+}
+
+csc_status dyn_similarity(csc_dyn st, int t, double* rho_edge, double* rho_hat, int* refreshed) {
+  if (!st) return fail(CSC_E_ARG, "null state");
+  if (!st->track) return fail(CSC_E_STATE, "similarity tracking is off for this state");
+  if (t < 1 || t > st->t) return fail(CSC_E_ARG, "snapshot index out of range");
+  if (rho_edge) *rho_edge = st->hist[3 * (t - 1)];
+  if (rho_hat) *rho_hat = st->hist[3 * (t - 1) + 1];
+  if (refreshed) *refreshed = st->hist[3 * (t - 1) + 2] > 0.5 ? 1 : 0;
   return CSC_OK;
 }
 

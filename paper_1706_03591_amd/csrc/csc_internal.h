@@ -91,6 +91,10 @@ struct Graph {
 csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
                        const double* w, int validate, hipStream_t s);
 csc_status graph_ensure_mirror(Graph* g, hipStream_t s);
+// ||L(b) - L(a)||_F^2 into *out (device double); graphs of the same n and Laplacian kind.
+size_t distance_workspace(int64_t n);
+csc_status graph_distance2(const Graph* a, const Graph* b, double* out, void* work,
+                           size_t work_bytes, hipStream_t s);
 
 // ------------------------------------------------------------------------------------
 // fused Chebyshev recurrence

@@ -93,6 +93,12 @@ def test_host_argument_errors(pkg):
     assert lib.csc_dyn_create(100, 8, 2, 1.0, 10, 1, 0, 1, ctypes.byref(opts), ctypes.byref(out)) == 1
     assert lib.csc_dyn_create(100, 8, 2, -0.1, 10, 1, 0, 1, ctypes.byref(opts), ctypes.byref(out)) == 1
     assert lib.csc_dyn_create(100, 8, 2, 0.95, 10, 1, 0, 1, ctypes.byref(opts), ctypes.byref(out)) == 1
+    # similarity options: probes beyond the fresh block, or a refresh budget without probes
+    bad = pkg.binding.DynOpts(keep_iterates=0, lloyd_iters=-1, sim_probes=5)
+    assert lib.csc_dyn_create(100, 8, 2, 0.5, 10, 1, 0, 1, ctypes.byref(bad), ctypes.byref(out)) == 1
+    assert b"sim_probes" in lib.csc_last_error()
+    bad = pkg.binding.DynOpts(keep_iterates=0, lloyd_iters=-1, refresh_budget=0.1)
+    assert lib.csc_dyn_create(100, 8, 2, 0.5, 10, 1, 0, 1, ctypes.byref(bad), ctypes.byref(out)) == 1
     assert lib.csc_dyn_create(100, 8, 2, 0.5, 10, 1, 5, 1, ctypes.byref(opts), ctypes.byref(out)) == 3
     # null handles
     assert lib.csc_cheb_filter(None, 2.0, 3, None, None, 0, 1, None, 0, 1, 1, 0, None, None, 0, None) == 1
