@@ -320,6 +320,28 @@ csc_status csc_dynamic_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t
  * the refresh rule fired.  Host call, no device work. */
 csc_status csc_dyn_similarity(csc_dyn st, int t, double* rho_edge, double* rho_hat,
                               int* refreshed);
+/* Checkpoint and resume of a dynamic state.  The state carried from one snapshot to the
+ * next is Theta, the cut-off lambda_t, the ring cursor, the snapshot counter t, the
+ * centroids and the labels (Algorithm 1 steps 4-8 read nothing else); the random draws are
+ * functions of (seed, t), so a state imported into a fresh handle continues the sequence
+ * bit for bit.  The host buffer holds a csc_dyn_header, then Theta (n x d row-major,
+ * feat_dt), the centroids (float[k * d]) and the labels (int32[n]); its size is
+ * csc_dyn_state_bytes.  A caller may edit the header's lambda (e.g. to force a refinement).
+ * The copy of the previous operator kept for similarity tracking is not part of the state:
+ * the first snapshot after an import reports no similarity.  Both calls synchronise `stream`;
+ * export needs t >= 1 (CSC_E_STATE), import checks that n, d, k, m, q d, feat_dt and seed
+ * match the handle's (CSC_E_ARG). */
+typedef struct {
+  uint64_t magic;   /* 0x31304e5944435343, "CSCDYN01" in little-endian bytes */
+  int64_t n;
+  int32_t d, k, m, qd;
+  int32_t feat_dt, t, cursor, reserved;
+  uint64_t seed;
+  double lambda;
+} csc_dyn_header;
+size_t csc_dyn_state_bytes(csc_dyn st);
+csc_status csc_dyn_export(csc_dyn st, void* host_buf, size_t bytes, void* stream);
+csc_status csc_dyn_import(csc_dyn st, const void* host_buf, size_t bytes, void* stream);
 /* Device view of Theta (n x d, type *dt, leading dimension *ld) and the centroids
  * (float[k * d]).  Valid until destroy. */
 csc_status csc_dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,

@@ -54,6 +54,14 @@ vp, i64, i32, u64, dbl, sz = C.c_void_p, C.c_int64, C.c_int, C.c_uint64, C.c_dou
 pdbl, pi64, pint = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int)
 
 
+class DynHeader(C.Structure):
+    """csc_dyn_header: the fixed-size head of an exported dynamic state."""
+    _fields_ = [("magic", C.c_uint64), ("n", C.c_int64), ("d", C.c_int32), ("k", C.c_int32),
+                ("m", C.c_int32), ("qd", C.c_int32), ("feat_dt", C.c_int32), ("t", C.c_int32),
+                ("cursor", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64),
+                ("lam", C.c_double)]
+
+
 class DynOpts(C.Structure):
     _fields_ = [("lmax", C.c_double), ("tau", C.c_double), ("n_cand", C.c_int),
                 ("lloyd_iters", C.c_int), ("init", C.c_int), ("iter_dt", C.c_int),
@@ -98,6 +106,9 @@ _SIGS = {
     "csc_dynamic_steps": ([vp, C.POINTER(vp), i32, C.POINTER(vp), pdbl, pint, pdbl, vp], i32),
     "csc_dyn_features": ([vp, C.POINTER(vp), pint, pi64, C.POINTER(vp)], i32),
     "csc_dyn_similarity": ([vp, i32, pdbl, pdbl, pint], i32),
+    "csc_dyn_state_bytes": ([vp], sz),
+    "csc_dyn_export": ([vp, vp, sz, vp], i32),
+    "csc_dyn_import": ([vp, vp, sz, vp], i32),
     "csc_dyn_destroy": ([vp], i32),
     "csc_cheb_backward_workspace_bytes": ([i64, i32, i32, i32], sz),
     "csc_cheb_filter_backward": ([vp, dbl, i32, pdbl, vp, i64, vp, i64, i32, vp, i64, vp, vp, i32,
@@ -511,6 +522,25 @@ class DynamicCSC:
         cnt = (C.c_double * S)()
         _check(lib.csc_dynamic_steps(self.h, gh, S, lp, lam, ref, cnt, _stream(stream)))
         return labels, list(lam), [bool(x) for x in ref], list(cnt)
+
+    def export_state(self, stream=None) -> bytearray:
+        """Checkpoint: header, Theta, centroids and labels in one host buffer."""
+        nb = lib.csc_dyn_state_bytes(self.h)
+        buf = bytearray(nb)
+        cbuf = (C.c_char * nb).from_buffer(buf)
+        _check(lib.csc_dyn_export(self.h, C.cast(cbuf, vp), nb, _stream(stream)))
+        return buf
+
+    def import_state(self, buf, stream=None):
+        """Resume from a buffer written by export_state (same parameters and seed)."""
+        buf = bytearray(buf)
+        cbuf = (C.c_char * len(buf)).from_buffer(buf)
+        _check(lib.csc_dyn_import(self.h, C.cast(cbuf, vp), len(buf), _stream(stream)))
+
+    @staticmethod
+    def header(buf) -> DynHeader:
+        """A writable view of the header at the start of an exported state."""
+        return DynHeader.from_buffer(buf)
 
     def similarity(self, t: int):
         """(rho_edge, rho_hat, refreshed) of snapshot t (1-based); -1 where not computed."""

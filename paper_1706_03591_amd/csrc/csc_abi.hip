@@ -121,6 +121,9 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
 csc_status dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,
                         const float** centroids);
 csc_status dyn_similarity(csc_dyn st, int t, double* rho_edge, double* rho_hat, int* refreshed);
+size_t dyn_state_bytes(csc_dyn st);
+csc_status dyn_export(csc_dyn st, void* buf, size_t bytes, hipStream_t s);
+csc_status dyn_import(csc_dyn st, const void* buf, size_t bytes, hipStream_t s);
 csc_status dyn_destroy(csc_dyn st);
 size_t backward_workspace(int64_t n, int w, int m, int ckpt);
 csc_status run_backward(const Graph* g, double lmax, int m, const double* a, const float* X,
@@ -473,6 +476,16 @@ csc_status csc_dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64
 csc_status csc_dyn_similarity(csc_dyn st, int t, double* rho_edge, double* rho_hat,
                               int* refreshed) {
   return dyn_similarity(st, t, rho_edge, rho_hat, refreshed);
+}
+
+size_t csc_dyn_state_bytes(csc_dyn st) { return dyn_state_bytes(st); }
+
+csc_status csc_dyn_export(csc_dyn st, void* host_buf, size_t bytes, void* stream) {
+  return dyn_export(st, host_buf, bytes, as_stream(stream));
+}
+
+csc_status csc_dyn_import(csc_dyn st, const void* host_buf, size_t bytes, void* stream) {
+  return dyn_import(st, host_buf, bytes, as_stream(stream));
 }
 
 csc_status csc_dyn_destroy(csc_dyn st) { return dyn_destroy(st); }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <tuple>
 #include <cmath>
 #include <string>
@@ -602,6 +603,68 @@ csc_status dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* 
   if (dt) *dt = st->feat_dt;
   if (ld) *ld = st->d;
   if (centroids) *centroids = st->C;
+  return CSC_OK;
+}
+
+constexpr uint64_t kStateMagic = 0x31304e5944435343ull;
+
+size_t dyn_state_bytes(csc_dyn st) {
+  if (!st) return 0;
+  return sizeof(csc_dyn_header) + dtype_size(st->feat_dt) * static_cast<size_t>(st->n) * st->d +
+         sizeof(float) * static_cast<size_t>(st->k) * st->d + sizeof(int32_t) * static_cast<size_t>(st->n);
+}
+
+csc_status dyn_export(csc_dyn st, void* buf, size_t bytes, hipStream_t s) {
+  if (!st || !buf) return fail(CSC_E_ARG, "null argument");
+  if (st->t < 1) return fail(CSC_E_STATE, "nothing to export before the first snapshot");
+  if (bytes < dyn_state_bytes(st)) return fail(CSC_E_ARG, "state buffer too small");
+  csc_dyn_header h{};
+  h.magic = kStateMagic;
+  h.n = st->n;
+  h.d = st->d;
+  h.k = st->k;
+  h.m = st->m;
+  h.qd = st->qd;
+  h.feat_dt = static_cast<int32_t>(st->feat_dt);
+  h.t = st->t;
+  h.cursor = st->cursor;
+  h.seed = st->seed;
+  h.lambda = st->lam;
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  const size_t tb = dtype_size(st->feat_dt) * static_cast<size_t>(st->n) * st->d;
+  const size_t cb = sizeof(float) * static_cast<size_t>(st->k) * st->d;
+  CSC_HIP(hipMemcpyAsync(p, st->theta, tb, hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipMemcpyAsync(p + tb, st->C, cb, hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipMemcpyAsync(p + tb + cb, st->prev, sizeof(int32_t) * st->n, hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}
+
+csc_status dyn_import(csc_dyn st, const void* buf, size_t bytes, hipStream_t s) {
+  if (!st || !buf) return fail(CSC_E_ARG, "null argument");
+  if (bytes < dyn_state_bytes(st)) return fail(CSC_E_ARG, "state buffer too small");
+  csc_dyn_header h{};
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kStateMagic) return fail(CSC_E_ARG, "not a dynamic CSC state");
+  if (h.n != st->n || h.d != st->d || h.k != st->k || h.m != st->m || h.qd != st->qd ||
+      h.feat_dt != static_cast<int32_t>(st->feat_dt) || h.seed != st->seed)
+    return fail(CSC_E_ARG, "the state was exported from a handle with other parameters");
+  if (h.t < 1 || h.cursor < 0 || h.cursor >= st->d || !(h.lambda >= 0.0))
+    return fail(CSC_E_ARG, "corrupt state header");
+  const char* p = static_cast<const char*>(buf) + sizeof(h);
+  const size_t tb = dtype_size(st->feat_dt) * static_cast<size_t>(st->n) * st->d;
+  const size_t cb = sizeof(float) * static_cast<size_t>(st->k) * st->d;
+  CSC_HIP(hipMemcpyAsync(st->theta, p, tb, hipMemcpyHostToDevice, s));
+  CSC_HIP(hipMemcpyAsync(st->C, p + tb, cb, hipMemcpyHostToDevice, s));
+  CSC_HIP(hipMemcpyAsync(st->prev, p + tb + cb, sizeof(int32_t) * st->n, hipMemcpyHostToDevice, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  st->t = h.t;
+  st->cursor = h.cursor;
+  st->lam = h.lambda;
+  st->have_prev = false;
+  if (st->track) st->hist.assign(3 * static_cast<size_t>(h.t), -1.0);
   return CSC_OK;
 }
 

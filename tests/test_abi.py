@@ -140,3 +140,15 @@ def test_bf16s_workspace_holds_fp32_state(pkg):
     # two BF16 copies plus two FP32 state arrays on top of the BF16 layout
     assert b16s >= b16 + 2 * n * w * 4
     assert f32 > 0
+
+
+def test_dyn_state_header_layout(pkg):
+    """The exported state starts with a 64-byte csc_dyn_header; null handles are rejected."""
+    H = pkg.binding.DynHeader
+    assert ctypes.sizeof(H) == 64
+    assert H.lam.offset == 56 and H.seed.offset == 48 and H.t.offset == 36
+    lib = pkg.lib
+    assert lib.csc_dyn_state_bytes(None) == 0
+    buf = ctypes.create_string_buffer(64)
+    assert lib.csc_dyn_export(None, buf, 64, None) == 1
+    assert lib.csc_dyn_import(None, buf, 64, None) == 1
