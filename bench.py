@@ -52,7 +52,9 @@ def parse():
                     help="comma list of " + ", ".join(f"{k}: {v[5]}" for k, v in FORMS.items()))
     ap.add_argument("--headline", default="bf16sb")
     ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ckm"], default="c3")
+    ap.add_argument("--n-sample", type=int, default=0,
+                    help="ckm: sampled nodes (0: ceil(4 k ln k))")
     ap.add_argument("--probe", metavar="FORM",
                     help="counter probe: snapshot 1 and one batch of FORM's dynamic steps on the "
                          "C3 sequence, then a plain 1 GiB device copy (run under rocprofv3 --pmc)")
@@ -155,14 +157,14 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the path is single-GPU by design (column sharding "
-              "across GPUs is described in DESIGN.md but not built); run with --gpus 1.",
-              file=sys.stderr)
+              "across GPUs is not built); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.traffic:
         return traffic_summary(args)
     if args.probe:
         return run_probe(args)
-    {"c3": run_dynamic, "c5": run_dynamic, "c2": run_static, "c4": run_adjoint}[args.workload](args)
+    {"c3": run_dynamic, "c5": run_dynamic, "c2": run_static, "c4": run_adjoint,
+     "ckm": run_compressive}[args.workload](args)
 
 
 def run_probe(args):
@@ -568,6 +570,68 @@ def run_adjoint(args):
                         "achieved": round(rate, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                         "frac": round(rate / PEAK_GBPS, 4), "traffic": None,
                         "algorithmic_bytes": round(fwd + bwd)}})
+
+
+def run_compressive(args):
+    """Full k-means against compressive k-means on the C3 features: snapshot 1 of the C3
+    sequence (N=1M, k=50 Zipf blocks) through static CSC gives Theta (d=128, FP32); a step is
+    one clustering of Theta, timed for both with HIP events on the current stream."""
+    import math
+
+    import numpy as np
+    import torch
+    from sklearn.metrics import normalized_mutual_info_score
+
+    import paper_1706_03591_amd as csc
+    from workloads import seed_for
+
+    seq, _ = build_sequence(args, 1)
+    g = seq[0]
+    G = csc.Graph.from_workload(g)
+    dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(3, "signals"),
+                         keep_iterates=0)
+    dyn.step(G)
+    F = dyn.features().contiguous()
+    del dyn
+    ns = args.n_sample or int(math.ceil(4 * args.k * math.log(args.k)))
+    seed = seed_for(3, "kmeans")
+
+    def full():
+        return csc.kmeans(F, args.k, 20, seed=seed, stream_id=2)[0]
+
+    def comp():
+        return csc.compressive_kmeans(G, F, args.k, ns, seed=seed, details=True)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / args.steps
+
+    lab_f, ms_f = timed(full)
+    (lab_c, _, _, _, its), ms_c = timed(comp)
+    lf, lc = lab_f.cpu().numpy(), lab_c.cpu().numpy()
+    conf = np.zeros((args.k, args.k))
+    np.add.at(conf, (lc, lf), 1)
+    log(f"[bench] full k-means {ms_f:.2f} ms, compressive {ms_c:.2f} ms ({its} CG iterations)")
+    _line(args, "k-means on the C3 features: compressive (sampling + Tikhonov) ms per clustering",
+          ms_c, "ms", ms_c,
+          {"higher_is_better": False,
+           "config": {"workload": f"C3 snapshot 1 features: N={args.n}, k={args.k} Zipf(1.2) blocks, "
+                                  f"d={args.d}, m={args.m}; full: k-means++ + 20 Lloyd rounds; "
+                                  f"compressive: {ns} sampled nodes, 20 Lloyd rounds, r=4, "
+                                  f"gamma=1e-3, PCG to 1e-6",
+                      "n_sample": ns},
+           "full_kmeans_ms": round(ms_f, 3), "cg_iterations": its,
+           "agreement_with_full": round(float(conf.max(axis=1).sum() / args.n), 5),
+           "nmi_vs_planted": {"full": round(float(normalized_mutual_info_score(g.labels, lf)), 5),
+                              "compressive": round(float(normalized_mutual_info_score(g.labels, lc)), 5)}})
 
 
 if __name__ == "__main__":

@@ -248,12 +248,35 @@ csc_status csc_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
                       int32_t* labels, double* objective, void* work, size_t work_bytes,
                       void* stream);
 
+/* Compressive k-means (Sec. 2.2, Step 2): k-means on n_sample nodes drawn i.i.d. with
+ * probability proportional to ||theta_i||^2 (a variable density; node i for a uniform u when
+ * C_{i-1} <= u W < C_i over the prefix sums C of the squared row norms), then each cluster
+ * indicator interpolated to every node by Tikhonov regularisation,
+ *     x_j = argmin_x ||P^{-1/2} (M x - y_j)||^2 + gamma x^T L^r x
+ * (M selects the sampled rows, P = diag(n_sample p_omega)), solved by preconditioned
+ * conjugate gradients on the k columns (each product with L is one pass of the fused
+ * recurrence) until every column's residual is below cg_tol times its right-hand side or
+ * cg_iters iterations; node i gets argmax_j x_j[i] (ties to the lowest j).
+ * F: device n x d features (F32 or BF16, ldf), n from the graph; k <= 256,
+ * k <= n_sample <= n, 1 <= r <= 8, gamma > 0.  Random draws: uniforms of (seed,
+ * sample_stream) for the samples and of (seed, kmeans_stream) for k-means++.  Outputs:
+ * labels (device int32[n]); optionally the samples and their labels (device int32[n_sample])
+ * and X (device float n x k); *cg_iters_done (host, nullable).  work:
+ * csc_compressive_workspace_bytes(n, d, k, n_sample).  Synchronising. */
+size_t csc_compressive_workspace_bytes(int64_t n, int d, int k, int n_sample);
+csc_status csc_compressive_kmeans(csc_graph g, const void* F, csc_dtype f_dt, int64_t ldf, int d,
+                                  int k, int n_sample, int r, double gamma, int lloyd_iters,
+                                  int cg_iters, double cg_tol, uint64_t seed,
+                                  uint64_t sample_stream, uint64_t kmeans_stream, int32_t* labels,
+                                  int32_t* samples, int32_t* sample_labels, float* X,
+                                  int* cg_iters_done, void* work, size_t work_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------------
  * Dynamic compressive spectral clustering (Algorithm 1, Sec. 4.1).
  *
- * The state keeps the n x d features Theta as d / (q d) column blocks, q = 1 - p, used as
- * a FIFO ring (for p <= 1/2 the kept columns are exactly those filtered on G_{t-1}), the
- * cut-off of the previous snapshot, and the previous labels.
+ * The state keeps the n x d features Theta as a FIFO of columns, of which each snapshot
+ * replaces the q d = round((1 - p) d) oldest (for p <= 1/2 the kept columns are exactly
+ * those filtered on G_{t-1}), the cut-off of the previous snapshot, and the previous labels.
  *  - The first call runs static CSC on G_1 (Algorithm 1 steps 1-2): d signals, their
  *    moments, an n_cand-step dichotomy on [0, lmax], the filter at the found cut-off,
  *    k-means.

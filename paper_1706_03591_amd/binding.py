@@ -98,6 +98,9 @@ _SIGS = {
     "csc_kmeans_assign": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp], i32),
     "csc_kmeans_update": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp, sz, vp], i32),
     "csc_kmeans_seed": ([vp, i32, i64, i64, i32, i32, vp, vp, vp, vp, sz, vp], i32),
+    "csc_compressive_workspace_bytes": ([i64, i32, i32, i32], sz),
+    "csc_compressive_kmeans": ([vp, vp, i32, i64, i32, i32, i32, i32, dbl, i32, i32, dbl, u64, u64,
+                                u64, vp, vp, vp, vp, pint, vp, sz, vp], i32),
     "csc_kmeans": ([vp, i32, i64, i64, i32, i32, i32, i32, u64, u64, vp, vp, pdbl, vp, sz, vp],
                    i32),
     "csc_dyn_create": ([i64, i32, i32, dbl, i32, i32, i32, u64, C.POINTER(DynOpts), C.POINTER(vp)],
@@ -473,6 +476,29 @@ def kmeans(F: torch.Tensor, k: int, iters: int = 20, seed: int = 0, stream_id: i
     if objective:
         return labels, Cc, np.frombuffer(obj, dtype=np.float64).copy()
     return labels, Cc
+
+
+def compressive_kmeans(g: "Graph", F: torch.Tensor, k: int, n_sample: int, r: int = 4,
+                       gamma: float = 1e-3, lloyd_iters: int = 20, cg_iters: int = 500,
+                       cg_tol: float = 1e-6, seed: int = 0, sample_stream: int = 3,
+                       kmeans_stream: int = 2, details: bool = False, stream=None):
+    """Labels of all nodes from k-means on n_sample drawn nodes and Tikhonov interpolation.
+    With details: (labels, samples, sample labels, X (n x k), CG iterations)."""
+    n, d = F.shape
+    labels = torch.empty(n, dtype=torch.int32, device=F.device)
+    samp = torch.empty(n_sample, dtype=torch.int32, device=F.device) if details else None
+    slab = torch.empty(n_sample, dtype=torch.int32, device=F.device) if details else None
+    X = torch.empty((n, k), dtype=torch.float32, device=F.device) if details else None
+    its = C.c_int()
+    ws = workspace(lib.csc_compressive_workspace_bytes(n, d, k, n_sample), F.device)
+    _check(lib.csc_compressive_kmeans(g.h, _ptr(F), _dt(F), _ld(F), d, int(k), int(n_sample), int(r),
+                                      float(gamma), int(lloyd_iters), int(cg_iters), float(cg_tol),
+                                      int(seed), int(sample_stream), int(kmeans_stream),
+                                      _ptr(labels), _ptr(samp), _ptr(slab), _ptr(X), C.byref(its),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+    if details:
+        return labels, samp, slab, X, its.value
+    return labels
 
 
 # ----------------------------------------------------------------------------------

@@ -258,6 +258,24 @@ csc_status csc_graph_distance(csc_graph g1, csc_graph g2, double* rho, void* str
   return st;
 }
 
+size_t csc_compressive_workspace_bytes(int64_t n, int d, int k, int n_sample) {
+  if (n < 1 || d < 1 || k < 1 || n_sample < 1) return 0;
+  return compressive_workspace(n, d, k, n_sample);
+}
+
+csc_status csc_compressive_kmeans(csc_graph g, const void* F, csc_dtype f_dt, int64_t ldf, int d,
+                                  int k, int n_sample, int r, double gamma, int lloyd_iters,
+                                  int cg_iters, double cg_tol, uint64_t seed,
+                                  uint64_t sample_stream, uint64_t kmeans_stream, int32_t* labels,
+                                  int32_t* samples, int32_t* sample_labels, float* X,
+                                  int* cg_iters_done, void* work, size_t work_bytes, void* stream) {
+  if (!g) return fail(CSC_E_ARG, "null graph");
+  if (lloyd_iters < 0 || lloyd_iters > 1024) return fail(CSC_E_ARG, "lloyd_iters must be in [0, 1024]");
+  return run_compressive(&g->g, F, f_dt, ldf, d, k, n_sample, r, gamma, lloyd_iters, cg_iters,
+                         cg_tol, seed, sample_stream, kmeans_stream, labels, samples,
+                         sample_labels, X, cg_iters_done, work, work_bytes, as_stream(stream));
+}
+
 csc_status csc_lmax(csc_graph h, int iters, double* lmax, void* stream) {
   if (!h || !lmax) return fail(CSC_E_ARG, "null argument");
   if (iters < 0) return fail(CSC_E_ARG, "iters must be >= 0");

@@ -91,6 +91,13 @@ struct Graph {
 csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
                        const double* w, int validate, hipStream_t s);
 csc_status graph_ensure_mirror(Graph* g, hipStream_t s);
+// compressive k-means (k_compress.hip)
+size_t compressive_workspace(int64_t n, int d, int k, int ns);
+csc_status run_compressive(const Graph* g, const void* F, csc_dtype f_dt, int64_t ldf, int d, int k,
+                           int ns, int r, double gamma, int lloyd, int cg_iters, double cg_tol,
+                           uint64_t seed, uint64_t sample_stream, uint64_t kmeans_stream,
+                           int32_t* labels, int32_t* samples, int32_t* sample_labels, float* X,
+                           int* iters_done, void* work, size_t work_bytes, hipStream_t st);
 // ||L(b) - L(a)||_F^2 into *out (device double); graphs of the same n and Laplacian kind.
 size_t distance_workspace(int64_t n);
 csc_status graph_distance2(const Graph* a, const Graph* b, double* out, void* work,
