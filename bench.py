@@ -52,7 +52,8 @@ def parse():
                     help="comma list of " + ", ".join(f"{k}: {v[5]}" for k, v in FORMS.items()))
     ap.add_argument("--headline", default="bf16sb")
     ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ckm"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ckm", "psweep"], default="c3")
+    ap.add_argument("--ps", default="0,0.25,0.5,0.75", help="psweep: reused fractions p")
     ap.add_argument("--n-sample", type=int, default=0,
                     help="ckm: sampled nodes (0: ceil(4 k ln k))")
     ap.add_argument("--probe", metavar="FORM",
@@ -164,7 +165,7 @@ def main():
     if args.probe:
         return run_probe(args)
     {"c3": run_dynamic, "c5": run_dynamic, "c2": run_static, "c4": run_adjoint,
-     "ckm": run_compressive}[args.workload](args)
+     "ckm": run_compressive, "psweep": run_psweep}[args.workload](args)
 
 
 def run_probe(args):
@@ -253,6 +254,83 @@ def traffic_summary(args):
     print(json.dumps({"form": form, "bytes_per_launch": per_launch, **rec["detail"][form]}))
 
 
+def _time_form(args, form, p, resident, cap, cid):
+    """Snapshot 1, the warm-up snapshots, then the timed snapshots of one storage form at
+    reuse fraction p; returns the form's record and the timed snapshots' labels."""
+    import torch
+
+    import paper_1706_03591_amd as csc
+    from workloads import seed_for
+
+    dev = torch.device("cuda")
+    T = 1 + args.warmup + args.steps
+    fdt, idt, vdt, batched, graph, _ = FORMS[form]
+    feat, iters, vals = torch_types(form)
+    rp, ci, ww = resident[0]
+    G = csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=True, nnz_capacity=cap)
+    # kernel shape of the fresh block's recurrence, timed on snapshot 1
+    qd = int(round((1 - p) * args.d))
+    variant = G.autotune(qd, iter_dtype=iters)
+    dyn = csc.DynamicCSC(args.n, args.d, args.k, p, args.m, seed=seed_for(cid, "signals"),
+                         feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
+                         use_graph=graph, keep_iterates=1 if batched else -1, variant=variant)
+    labels = torch.empty(args.n, dtype=torch.int32, device=dev)
+    _, lam, ref, cnt = dyn.step(G, labels)
+    log(f"[bench] {form}: snapshot 1 lambda {lam:.5f} count {cnt:.2f}")
+    for t in range(2, 2 + args.warmup):
+        G.update_device(*resident[t - 1], validate=False)
+        dyn.step(G, labels)
+    timed = list(range(2 + args.warmup, T + 1))
+    labs = [torch.empty(args.n, dtype=torch.int32, device=dev) for _ in timed]
+    if batched:
+        Gs = [G] + [csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=False, nnz_capacity=cap)
+                    for _ in range(len(timed) - 1)]
+    torch.cuda.synchronize()
+    csc.timing_reset()
+    csc.timing_enable(True)
+    refines = 0
+    lams = []
+    t0 = time.perf_counter()
+    if batched:
+        for q, t in enumerate(timed):
+            Gs[q].update_device(*resident[t - 1], validate=False)
+        labs, lams, refs, _ = dyn.steps(Gs, labs)
+        refines = sum(refs)
+        labels = labs[-1]
+    else:
+        for q, t in enumerate(timed):
+            G.update_device(*resident[t - 1], validate=False)
+            _, lam, ref, cnt = dyn.step(G, labs[q])
+            refines += int(ref)
+            lams.append(lam)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches, kbytes = csc.timing_read()
+    csc.timing_enable(False)
+    log(f"[bench] {form}: {wall / args.steps * 1e3:.2f} ms/snapshot, step kernels "
+        f"{kms / launches * 1e3:.1f} us/launch, {kbytes / (kms * 1e-3) / 1e9:.0f} GB/s, "
+        f"refines {refines}")
+    entry = dict(
+        ms_per_snapshot=wall / args.steps * 1e3,
+        gbps_whole=kbytes / wall / 1e9,
+        step_kernel_gbps=kbytes / (kms * 1e-3) / 1e9,
+        step_kernel_us=kms / launches * 1e3,
+        step_launches=launches,
+        bytes_per_launch=kbytes / launches,
+        refines=refines,
+        lambda_last=lams[-1] if lams else None,
+        storage=dict(signals=fdt, features=fdt, values=vdt, iterates=idt, accumulate="float32"),
+        batch=args.batch if batched else 1,
+        hip_graph=graph,
+        autotuned_variant=variant,
+        G=G,
+    )
+    del dyn
+    if batched:
+        del Gs
+    return entry, labs
+
+
 def run_dynamic(args):
     import numpy as np
     import torch
@@ -278,72 +356,9 @@ def run_dynamic(args):
     final_labels = {}
     all_labels = {}
     for form in args.forms.split(","):
-        fdt, idt, vdt, batched, graph, _ = FORMS[form]
-        feat, iters, vals = torch_types(form)
-        rp, ci, ww = resident[0]
-        G = csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=True, nnz_capacity=cap)
-        # kernel shape of the fresh block's recurrence, timed on snapshot 1
-        qd = int(round((1 - args.p) * args.d))
-        variant = G.autotune(qd, iter_dtype=iters)
-        dyn = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed_for(cid, "signals"),
-                             feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
-                             use_graph=graph, keep_iterates=1 if batched else -1, variant=variant)
-        labels = torch.empty(args.n, dtype=torch.int32, device=dev)
-        _, lam, ref, cnt = dyn.step(G, labels)
-        log(f"[bench] {form}: snapshot 1 lambda {lam:.5f} count {cnt:.2f}")
-        for t in range(2, 2 + args.warmup):
-            G.update_device(*resident[t - 1], validate=False)
-            dyn.step(G, labels)
-        timed = list(range(2 + args.warmup, T + 1))
-        labs = [torch.empty(args.n, dtype=torch.int32, device=dev) for _ in timed]
-        if batched:
-            Gs = [G] + [csc.Graph(args.n, rp, ci, ww, val_dtype=vals, validate=False, nnz_capacity=cap)
-                        for _ in range(len(timed) - 1)]
-        torch.cuda.synchronize()
-        csc.timing_reset()
-        csc.timing_enable(True)
-        refines = 0
-        lams = []
-        t0 = time.perf_counter()
-        if batched:
-            for q, t in enumerate(timed):
-                Gs[q].update_device(*resident[t - 1], validate=False)
-            labs, lams, refs, _ = dyn.steps(Gs, labs)
-            refines = sum(refs)
-            labels = labs[-1]
-        else:
-            for q, t in enumerate(timed):
-                G.update_device(*resident[t - 1], validate=False)
-                _, lam, ref, cnt = dyn.step(G, labs[q])
-                refines += int(ref)
-                lams.append(lam)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        forms[form], labs = _time_form(args, form, args.p, resident, cap, cid)
         final_labels[form] = labs[-1].cpu().numpy()
         all_labels[form] = [x.cpu().numpy() for x in labs]
-        kms, launches, kbytes = csc.timing_read()
-        csc.timing_enable(False)
-        log(f"[bench] {form}: {wall / args.steps * 1e3:.2f} ms/snapshot, step kernels "
-            f"{kms / launches * 1e3:.1f} us/launch, {kbytes / (kms * 1e-3) / 1e9:.0f} GB/s, "
-            f"refines {refines}")
-        forms[form] = dict(
-            ms_per_snapshot=wall / args.steps * 1e3,
-            gbps_whole=kbytes / wall / 1e9,
-            step_kernel_gbps=kbytes / (kms * 1e-3) / 1e9,
-            step_kernel_us=kms / launches * 1e3,
-            step_launches=launches,
-            bytes_per_launch=kbytes / launches,
-            refines=refines,
-            lambda_last=lams[-1] if lams else None,
-            storage=dict(signals=fdt, features=fdt, values=vdt, iterates=idt, accumulate="float32"),
-            batch=args.batch if batched else 1,
-            hip_graph=graph,
-            autotuned_variant=variant,
-            G=G,
-        )
-        del dyn
-        if batched:
-            del Gs
 
     # error of each form's filter against the FP64 oracle on 10k sampled rows (4 columns),
     # at a fixed cut-off on the last snapshot; the oracle run doubles as the CPU baseline
@@ -570,6 +585,41 @@ def run_adjoint(args):
                         "achieved": round(rate, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                         "frac": round(rate / PEAK_GBPS, 4), "traffic": None,
                         "algorithmic_bytes": round(fwd + bwd)}})
+
+
+def run_psweep(args):
+    """Time side of the reuse study (Sec. 5.2, Fig. 2(b)) at C3 scale: ms per dynamic snapshot
+    of the headline form as the reused fraction p grows, on the C3 sequence.  The value is the
+    time saved at the largest p relative to p = 0 (the paper reports up to 25%)."""
+    import torch
+
+    T = 1 + args.warmup + args.steps
+    seq, _ = build_sequence(args, T)
+    dev = torch.device("cuda")
+    resident = [(torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev),
+                 torch.from_numpy(g.w).to(dev)) for g in seq]
+    cap = max(g.nnz for g in seq)
+    ps = [float(x) for x in args.ps.split(",")]
+    rows = []
+    for p in ps:
+        entry, _ = _time_form(args, args.headline, p, resident, cap, 3)
+        rows.append(dict(p=p, qd=int(round((1 - p) * args.d)),
+                         ms_per_snapshot=round(entry["ms_per_snapshot"], 3),
+                         step_kernel_us=round(entry["step_kernel_us"], 1),
+                         refines=entry["refines"], batch=entry["batch"]))
+        del entry
+        torch.cuda.empty_cache()
+    base = rows[0]["ms_per_snapshot"]
+    for r in rows:
+        r["saved_vs_first"] = round(1.0 - r["ms_per_snapshot"] / base, 4)
+    last = rows[-1]
+    _line(args, f"time saved per dynamic snapshot by reusing a fraction p of the features "
+                f"(C3, {args.headline}), p={ps[-1]} vs p={ps[0]}",
+          100.0 * last["saved_vs_first"], "%", last["ms_per_snapshot"],
+          {"config": {"workload": f"dynamic SBM N={args.n}, k={args.k} Zipf(1.2) blocks, degree 16, "
+                                  f"ratio 0.1; d={args.d}, m={args.m}; p in {ps}",
+                      "form": args.headline},
+           "sweep": rows})
 
 
 def run_compressive(args):
