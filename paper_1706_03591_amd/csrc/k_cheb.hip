@@ -221,6 +221,20 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
     if (row < p.n) {
       const int32_t rs = p.rowptr[row], re = p.rowptr[row + 1];
       int32_t e = rs;
+      for (; e + 8 <= re; e += 8) {
+        const int32_t l = e - e0;
+        uint4 g[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) g[q] = ld16(zc + static_cast<int64_t>(s_col[l + q]) * WT);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float f[VEC];
+          P::unpack(g[q], f);
+          const float v = s_val[l + q];
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v, f[i], acc[i]);
+        }
+      }
       for (; e + 4 <= re; e += 4) {
         const int32_t l = e - e0;
         const int32_t c0 = s_col[l], c1 = s_col[l + 1], c2 = s_col[l + 2], c3 = s_col[l + 3];
