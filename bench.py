@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--forms", default="fp32,bf16io,bf16,bf16s,bf16sb",
                     help="comma list of " + ", ".join(f"{k}: {v[5]}" for k, v in FORMS.items()))
     ap.add_argument("--headline", default="bf16sb")
+    ap.add_argument("--init", choices=["pp", "warm"], default="pp",
+                    help="k-means start per snapshot: k-means++ (pp) or the previous labels' means")
     ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
     ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ckm", "psweep"], default="c3")
     ap.add_argument("--ps", default="0,0.25,0.5,0.75", help="psweep: reused fractions p")
@@ -273,7 +275,8 @@ def _time_form(args, form, p, resident, cap, cid):
     variant = G.autotune(qd, iter_dtype=iters)
     dyn = csc.DynamicCSC(args.n, args.d, args.k, p, args.m, seed=seed_for(cid, "signals"),
                          feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
-                         use_graph=graph, keep_iterates=1 if batched else -1, variant=variant)
+                         use_graph=graph, keep_iterates=1 if batched else -1, variant=variant,
+                         init=1 if args.init == "warm" else 0)
     labels = torch.empty(args.n, dtype=torch.int32, device=dev)
     _, lam, ref, cnt = dyn.step(G, labels)
     log(f"[bench] {form}: snapshot 1 lambda {lam:.5f} count {cnt:.2f}")
@@ -438,6 +441,7 @@ def run_dynamic(args):
                          f"m={args.m}, p={args.p}; step = one dynamic snapshot"),
             "n": args.n, "nnz_max": cap, "d": args.d, "m": args.m, "p": args.p, "k": args.k,
             "storage": FORMS[args.headline][5], "parallelism": "single GPU",
+            "kmeans_init": "k-means++" if args.init == "pp" else "previous labels' means",
         },
         "roofline": {
             "bound": "hbm",
