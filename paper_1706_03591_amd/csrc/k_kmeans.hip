@@ -168,8 +168,9 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
 // centroid value is the sum of three BF16 parts (hi, mid, lo; residual below 2^-26 of the
 // value), and each FP32 feature likewise, so every partial product is exact in FP32.  Each
 // 32-column step of the dominant hi x hi product goes into a fresh FP32 accumulator and is
-// added to an FP64 sum, and the small cross products (weights 2^-8 and below) are chained
-// into a second accumulator; the rounding of a dot product is then at most
+// added to an FP64 sum, and the small cross products (weights 2^-8 and below) of each step
+// are summed in FP32 and added to a second, running FP32 accumulator; the rounding of a dot
+// product is then at most
 // E ||f|| ||c|| with E = 40 2^-24, so the exact score s*_c = ||c||^2 - 2 f.c lies in
 // [s_c - e_c, s_c + e_c] with e_c = 2 E ||f|| ||c|| (+ FP64 rounding).  The argmin is then
 // among the centroids whose lower end is below the smallest upper end.  Each lane keeps its
@@ -430,19 +431,24 @@ __global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int
         for (int t = 0; t < T; ++t) {
           double dot[4] = {0.0, 0.0, 0.0, 0.0};
           f32x4 small = zero4;
+          // every step starts its own accumulators, so the matrix-core chains are at most
+          // three long and the steps overlap in the pipeline; the small parts of a step are
+          // then added to the running FP32 sum
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
             const bf16x8 ch = lds_bf8(cb + s * 32);
             const bf16x8 cm = lds_bf8(cb + kc_max * SB + s * 32);
             const bf16x8 cl = lds_bf8(cb + 2 * kc_max * SB + s * 32);
             const f32x4 main = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][0][s], zero4, 0, 0, 0);
-            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][0][s], small, 0, 0, 0);
-            small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[t][0][s], small, 0, 0, 0);
+            f32x4 sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][0][s], zero4, 0, 0, 0);
+            sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[t][0][s], sm, 0, 0, 0);
             if constexpr (NP == 3) {
-              small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][1][s], small, 0, 0, 0);
-              small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][1][s], small, 0, 0, 0);
-              small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][2][s], small, 0, 0, 0);
+              f32x4 sm2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][1][s], zero4, 0, 0, 0);
+              sm2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][1][s], sm2, 0, 0, 0);
+              sm2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][2][s], sm2, 0, 0, 0);
+              sm += sm2;
             }
+            small += sm;
 #pragma unroll
             for (int r = 0; r < 4; ++r) dot[r] += static_cast<double>(main[r]);
           }
