@@ -35,7 +35,7 @@ template <>
 __device__ inline float to_f<uint16_t>(uint16_t v) { return bf16_to_f32(v); }
 
 __device__ inline double block_sum(double v) {
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[16];  // blocks of up to 1024 threads
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -318,10 +318,12 @@ inline size_t mf_lds_bytes(int DP, int kc_max) {
   return static_cast<size_t>(3) * kc_max * (DP + 8) * 2 + static_cast<size_t>(kc_max) * 16;
 }
 
-// T row tiles per wave (T > 1 when the centroids need several LDS chunks: each staged chunk
-// then serves 64 T rows, dividing the re-staging traffic by T).
-template <typename TF, int DP, int T>
-__global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int64_t n, int d,
+// T row tiles per wave and WV waves per block (T > 1 and WV = 8 when the centroids need
+// several LDS chunks: each staged chunk then serves 16 WV T rows, dividing the re-staging
+// traffic; the registers of T = 2 allow one such block per CU, the same eight waves as two
+// blocks of four).
+template <typename TF, int DP, int T, int WV>
+__global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf, int64_t n, int d,
                                                    const uint16_t* parts, const double* cn_g,
                                                    const float* C, int k, int kp, int kc_max,
                                                    int32_t* labels, float* best_d2,
@@ -338,7 +340,7 @@ __global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int
   const int wave = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int nchunks = (kp + kc_max - 1) / kc_max;
-  const int64_t panels = (n + 64 * T - 1) / (64 * T);
+  const int64_t panels = (n + 16 * WV * T - 1) / (16 * WV * T);
   const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
   double objsum = 0.0;
   bool staged = false;
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(256) void k_assign_mf(const TF* F, int64_t ldf, int
   // (FP32 rows already hold three split parts in registers; a prefetch costs occupancy there)
   constexpr bool PF = sizeof(TF) == 2 && T == 1;
   auto row_of = [&](int64_t panel, int t) -> int64_t {
-    return ((panel * 4 + wave) * T + t) * 16 + li;
+    return ((panel * WV + wave) * T + t) * 16 + li;
   };
   u32x4 raw[T][NS][RW];
   if constexpr (PF) {
@@ -1057,7 +1059,7 @@ size_t kmeans_workspace(int64_t n, int d, int k) { return km_layout(n, d, k).tot
 // centroids fit one chunk (staged once per block); two when they do not (BF16 rows), so that
 // each re-staged chunk serves 128 rows.
 struct MfPlan {
-  int DP = 0, kp = 0, kc = 0, T = 1;
+  int DP = 0, kp = 0, kc = 0, T = 1, wv = 4;
   size_t lds = 0;
   int64_t blocks = 1;
 };
@@ -1074,9 +1076,11 @@ MfPlan mf_plan(int64_t n, int d, int k, bool bf16_rows = false) {
   P.kp = kp;
   P.kc = kc;
   P.T = (bf16_rows && kc < kp) ? 2 : 1;
+  P.wv = P.T == 2 ? 8 : 4;
   P.lds = mf_lds_bytes(DP, kc);
-  const int64_t panels = (n + 64 * P.T - 1) / (64 * P.T);
-  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / static_cast<int64_t>(P.lds)));
+  const int64_t panels = (n + 16 * P.wv * P.T - 1) / (16 * P.wv * P.T);
+  const int64_t per_cu = P.wv == 8 ? 1 :
+      std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / static_cast<int64_t>(P.lds)));
   P.blocks = std::max<int64_t>(1, std::min<int64_t>(panels, 256 * per_cu));
   return P;
 }
@@ -1110,7 +1114,8 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
     hipLaunchKernelGGL(k_centroid_norms, dim3(P.kp), dim3(64), 0, s, C, k, d, P.kp, cn);
     const unsigned blocks = static_cast<unsigned>(P.blocks);
 #define CSC_MF(TF, DPV, TV)                                                                        \
-  hipLaunchKernelGGL((k_assign_mf<TF, DPV, TV>), dim3(blocks), dim3(256), P.lds, s,               \
+  hipLaunchKernelGGL((k_assign_mf<TF, DPV, TV, (TV == 2 ? 8 : 4)>), dim3(blocks), dim3(64 * P.wv), \
+                     P.lds, s,                                                                    \
                      static_cast<const TF*>(F), ldf, n, d, parts, cn, C, k, P.kp, P.kc, labels,   \
                      best_d2, obj_part)
 #define CSC_MF_DP(TF, TV)                    \
