@@ -602,38 +602,22 @@ constexpr int kUpdRows = 1024;
 template <typename TF>
 __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, int64_t n, int d,
                                                       const int32_t* labels, int k, int64_t rpb,
-                                                      int cw, const uint32_t* maxabs,
+                                                      int nsub, int cw, const uint32_t* maxabs,
                                                       unsigned long long* gsums, int32_t* gcnt) {
-  // LDS: k * cw sums, then k counts, k offsets, rpb labels, rpb row order
+  // LDS: k * cw sums, then k counts, k offsets, k block totals, rpb labels, rpb row order.
+  // The block takes nsub consecutive stretches of rpb rows; each is sorted by label on its
+  // own, and the sums of all of them meet in the same LDS accumulators before the single
+  // flush to global memory.
   extern __shared__ unsigned long long s_acc[];
   int32_t* s_cnt = reinterpret_cast<int32_t*>(s_acc + static_cast<size_t>(k) * cw);
   int32_t* s_off = s_cnt + k;
-  int32_t* s_lab = s_off + k;
+  int32_t* s_tot = s_off + k;
+  int32_t* s_lab = s_tot + k;
   int32_t* s_perm = s_lab + rpb;
   for (int t = threadIdx.x; t < k * cw; t += kThreads) s_acc[t] = 0ull;
-  for (int t = threadIdx.x; t < k; t += kThreads) s_cnt[t] = 0;
-  __syncthreads();
+  for (int t = threadIdx.x; t < k; t += kThreads) s_tot[t] = 0;
   const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rpb;
-  const int nr = static_cast<int>(max<int64_t>(0, min(r0 + rpb, n) - r0));
   __shared__ int s_nv;
-  for (int i = threadIdx.x; i < nr; i += kThreads) {
-    int lb = labels[r0 + i];
-    if (lb < 0 || lb >= k) lb = -1;  // out-of-range labels are ignored
-    s_lab[i] = lb;
-    if (lb >= 0) atomicAdd(&s_cnt[lb], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int c = 0; c < k; ++c) { s_off[c] = run; run += s_cnt[c]; }
-    s_nv = run;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nr; i += kThreads)
-    if (s_lab[i] >= 0) s_perm[atomicAdd(&s_off[s_lab[i]], 1)] = i;
-  __syncthreads();
-  const int nv = s_nv;
   // a lane owns 8 consecutive columns; LR lanes cover the block's cw columns of one row, and
   // the kThreads / LR row slots split the label-ordered rows into contiguous stretches
   const int LR = cw / 8;
@@ -643,81 +627,109 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
   const int col0 = blockIdx.y * cw + c8;
   const bool vec = sizeof(TF) * 8 % 16 == 0 && col0 + 8 <= d &&
                    reinterpret_cast<uintptr_t>(F) % 16 == 0 && (ldf * sizeof(TF)) % 16 == 0;
-  const int per = (nv + slots - 1) / slots;
-  const int q0 = slot * per, q1 = min(nv, q0 + per);
-  int cur = -1;
-  long long run[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) run[i] = 0;
-  auto flush = [&]() {
-    if (cur < 0) return;
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (run[i] != 0 && c8 + i < cw)
-        atomicAdd(&s_acc[cur * cw + c8 + i], static_cast<unsigned long long>(run[i]));
-  };
-  auto load8v = [&](int ii, float* v) {
-    const TF* rp = F + (r0 + ii) * ldf + col0;
-    if (vec) {
-      if constexpr (sizeof(TF) == 4) {
-        const uint4 u0 = reinterpret_cast<const uint4*>(rp)[0];
-        const uint4 u1 = reinterpret_cast<const uint4*>(rp)[1];
-        v[0] = __uint_as_float(u0.x); v[1] = __uint_as_float(u0.y);
-        v[2] = __uint_as_float(u0.z); v[3] = __uint_as_float(u0.w);
-        v[4] = __uint_as_float(u1.x); v[5] = __uint_as_float(u1.y);
-        v[6] = __uint_as_float(u1.z); v[7] = __uint_as_float(u1.w);
-      } else {
-        const uint4 u = reinterpret_cast<const uint4*>(rp)[0];
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          v[2 * i] = __uint_as_float(w[i] << 16);
-          v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-        }
+  for (int sub = 0; sub < nsub; ++sub) {
+    const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * nsub + sub) * rpb;
+    const int nr = static_cast<int>(max<int64_t>(0, min(r0 + rpb, n) - r0));
+    if (nr == 0) break;  // uniform across the block
+    for (int t = threadIdx.x; t < k; t += kThreads) s_cnt[t] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr; i += kThreads) {
+      int lb = labels[r0 + i];
+      if (lb < 0 || lb >= k) lb = -1;  // out-of-range labels are ignored
+      s_lab[i] = lb;
+      if (lb >= 0) atomicAdd(&s_cnt[lb], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = 0;
+      for (int c = 0; c < k; ++c) {
+        s_off[c] = run;
+        run += s_cnt[c];
+        s_tot[c] += s_cnt[c];
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = col0 + i < d ? to_f<TF>(rp[i]) : 0.f;
+      s_nv = run;
     }
-  };
-  int q = q0;
-  for (; q + 4 <= q1; q += 4) {
-    int lb[4];
-    float v[4][8];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr; i += kThreads)
+      if (s_lab[i] >= 0) s_perm[atomicAdd(&s_off[s_lab[i]], 1)] = i;
+    __syncthreads();
+    const int nv = s_nv;
+    const int per = (nv + slots - 1) / slots;
+    const int q0 = slot * per, q1 = min(nv, q0 + per);
+    int cur = -1;
+    long long run[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ii = s_perm[q + u];
-      lb[u] = s_lab[ii];
-      load8v(ii, v[u]);
+    for (int i = 0; i < 8; ++i) run[i] = 0;
+    auto flush = [&]() {
+      if (cur < 0) return;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (run[i] != 0 && c8 + i < cw)
+          atomicAdd(&s_acc[cur * cw + c8 + i], static_cast<unsigned long long>(run[i]));
+    };
+    auto load8v = [&](int ii, float* v) {
+      const TF* rp = F + (r0 + ii) * ldf + col0;
+      if (vec) {
+        if constexpr (sizeof(TF) == 4) {
+          const uint4 u0 = reinterpret_cast<const uint4*>(rp)[0];
+          const uint4 u1 = reinterpret_cast<const uint4*>(rp)[1];
+          v[0] = __uint_as_float(u0.x); v[1] = __uint_as_float(u0.y);
+          v[2] = __uint_as_float(u0.z); v[3] = __uint_as_float(u0.w);
+          v[4] = __uint_as_float(u1.x); v[5] = __uint_as_float(u1.y);
+          v[6] = __uint_as_float(u1.z); v[7] = __uint_as_float(u1.w);
+        } else {
+          const uint4 u = reinterpret_cast<const uint4*>(rp)[0];
+          const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            v[2 * i] = __uint_as_float(w[i] << 16);
+            v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = col0 + i < d ? to_f<TF>(rp[i]) : 0.f;
+      }
+    };
+    int q = q0;
+    for (; q + 4 <= q1; q += 4) {
+      int lb[4];
+      float v[4][8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ii = s_perm[q + u];
+        lb[u] = s_lab[ii];
+        load8v(ii, v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (lb[u] != cur) {
+          flush();
+          cur = lb[u];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) run[i] = 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[u][i]), S));
+      }
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (lb[u] != cur) {
+    for (; q < q1; ++q) {
+      const int ii = s_perm[q];
+      const int lb = s_lab[ii];
+      float v[8];
+      load8v(ii, v);
+      if (lb != cur) {
         flush();
-        cur = lb[u];
+        cur = lb;
 #pragma unroll
         for (int i = 0; i < 8; ++i) run[i] = 0;
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[u][i]), S));
+      for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[i]), S));
     }
+    flush();
+    __syncthreads();  // s_lab and s_perm are rewritten by the next stretch
   }
-  for (; q < q1; ++q) {
-    const int ii = s_perm[q];
-    const int lb = s_lab[ii];
-    float v[8];
-    load8v(ii, v);
-    if (lb != cur) {
-      flush();
-      cur = lb;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) run[i] = 0;
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[i]), S));
-  }
-  flush();
-  __syncthreads();
   for (int t = threadIdx.x; t < k * cw; t += kThreads) {
     const int c = t / cw, cc = t % cw;
     const int gc = blockIdx.y * cw + cc;
@@ -725,7 +737,7 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
   }
   if (blockIdx.y == 0)
     for (int t = threadIdx.x; t < k; t += kThreads)
-      if (s_cnt[t]) atomicAdd(&gcnt[t], s_cnt[t]);
+      if (s_tot[t]) atomicAdd(&gcnt[t], s_tot[t]);
 }
 
 __global__ void k_upd_final(const unsigned long long* gsums, const int32_t* gcnt,
@@ -1031,19 +1043,24 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
                          static_cast<const uint16_t*>(F), ldf, n, d, mx);
   }
   const int cw = k <= 112 ? 64 : 32;
-  // rows per block: up to kUpdRows, within 64 KiB of LDS next to the k x cw sums
-  const size_t fixed_lds = static_cast<size_t>(k) * cw * 8 + static_cast<size_t>(k) * 8;
+  // rows per stretch: up to kUpdRows, within 64 KiB of LDS next to the k x cw sums; each block
+  // takes up to 16 stretches (about 512 blocks across x), so the k x cw flush to global
+  // memory is amortised over more rows
+  const size_t fixed_lds = static_cast<size_t>(k) * cw * 8 + static_cast<size_t>(k) * 12;
   const int64_t cap = std::min<int64_t>(kUpdRows, static_cast<int64_t>((64 * 1024 - fixed_lds) / 8));
-  const int64_t nblk = std::max<int64_t>(1, (n + cap - 1) / cap);
-  const int64_t rpb = (n + nblk - 1) / nblk;  // <= cap
+  const int64_t nstretch = std::max<int64_t>(1, (n + cap - 1) / cap);
+  const int64_t rpb = (n + nstretch - 1) / nstretch;  // <= cap
+  const int nsub = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(16, nstretch / 512)));
+  const int64_t nblk = (nstretch + nsub - 1) / nsub;
   const size_t lds = fixed_lds + static_cast<size_t>(rpb) * 8;
   const dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>((d + cw - 1) / cw));
   if (f_dt == CSC_F32)
     hipLaunchKernelGGL(k_upd_acc<float>, grid, dim3(kThreads), lds, s, static_cast<const float*>(F),
-                       ldf, n, d, labels, k, rpb, cw, mx, sums, cnt);
+                       ldf, n, d, labels, k, rpb, nsub, cw, mx, sums, cnt);
   else
     hipLaunchKernelGGL(k_upd_acc<uint16_t>, grid, dim3(kThreads), lds, s,
-                       static_cast<const uint16_t*>(F), ldf, n, d, labels, k, rpb, cw, mx, sums, cnt);
+                       static_cast<const uint16_t*>(F), ldf, n, d, labels, k, rpb, nsub, cw, mx,
+                       sums, cnt);
   hipLaunchKernelGGL(k_upd_final, dim3(static_cast<unsigned>((kd + 255) / 256)), dim3(256), 0, s,
                      sums, cnt, mx, n, k, d, C, counts);
   CSC_HIP(hipGetLastError());
