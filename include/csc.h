@@ -302,8 +302,9 @@ typedef struct {
   int init;           /* 0: k-means++ every snapshot; 1: warm start from previous labels */
   csc_dtype iter_dt;  /* storage of the recurrence iterates (F32, BF16 or BF16S) */
   int keep_iterates;  /* -1: keep all m + 1 iterates of the fresh block when they fit in free
-                         device memory (a refinement then recombines them instead of running
-                         the recurrence again); 0: never; 1: always (CSC_E_NOMEM otherwise) */
+                         device memory and m < 256 (a refinement then recombines them, in FP64,
+                         instead of running the recurrence again); 0: never; 1: always
+                         (CSC_E_NOMEM when they do not fit, CSC_E_ARG when m >= 256) */
   int batch;          /* csc_dynamic_steps: fresh blocks of up to `batch` (<= 8) snapshots are
                          filtered together, one launch per recurrence step; needs the
                          iterates kept (0 or 1 -> one snapshot at a time) */

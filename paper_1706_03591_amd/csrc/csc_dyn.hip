@@ -177,7 +177,11 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   // Keep all m + 1 iterates of the fresh block when they fit: a refinement of the cut-off is
   // then a new linear combination of stored iterates instead of a second recurrence.
   const int keep = opts ? opts->keep_iterates : -1;
-  if (keep != 0 && m + 1 <= 512) {
+  if (keep == 1 && m + 1 > 256) {
+    free_dyn(st);
+    return fail(CSC_E_ARG, "keeping the iterates needs m < 256");
+  }
+  if (keep != 0 && m + 1 <= 256) {
     Graph probe{};
     probe.variant_f32 = probe.variant_bf16 = -1;
     st->variant = (opts && opts->variant >= 0) ? opts->variant : default_variant(&probe, qd, st->iter_dt);

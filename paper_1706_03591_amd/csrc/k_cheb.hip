@@ -1057,7 +1057,7 @@ namespace csc {
 
 namespace {
 
-constexpr int kMaxCombine = 512;
+constexpr int kMaxCombine = 256;  // FP64 coefficients in the 4 KiB kernel arguments
 
 struct CombineParams {
   const void* basis;   // (m + 1) slots of n x wpad (tiled)
@@ -1071,7 +1071,7 @@ struct CombineParams {
   int p_dt;
   int64_t ldp;
   double* part;        // per block
-  float coef[kMaxCombine];
+  double coef[kMaxCombine];
 };
 
 __device__ inline float load_any(const void* p, int dt, int64_t i) {
@@ -1080,8 +1080,10 @@ __device__ inline float load_any(const void* p, int dt, int64_t i) {
   return static_cast<float>(static_cast<const double*>(p)[i]);
 }
 
-// One thread per (row, VEC columns of a tile): Y = sum_j a_j Z_j accumulated in FP32 in the
-// order j = 0..m, the same arithmetic as the fused recurrence's accumulator.
+// One thread per (row, VEC columns of a tile): Y = sum_j a_j Z_j with FP64 coefficients,
+// accumulated in FP64 in the order j = 0..m and rounded once.  The filtered block can be a
+// small fraction of the input's norm (about 0.2% at the C3 cut-off), so FP32 coefficients
+// and an FP32 sum would cost more accuracy than the iterates themselves carry.
 template <typename TZ>
 __global__ __launch_bounds__(kThreads) void k_combine(CombineParams p) {
   constexpr int VEC = Pack<TZ>::VEC;
@@ -1095,23 +1097,24 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineParams p) {
     const int tile = col0 / p.wt, c = col0 - tile * p.wt;
     const TZ* z = static_cast<const TZ*>(p.basis) + static_cast<int64_t>(tile) * p.n * p.wt +
                   row * p.wt + c;
-    float y[VEC];
+    double y[VEC];
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) y[i] = 0.f;
+    for (int i = 0; i < VEC; ++i) y[i] = 0.0;
     for (int j = 0; j <= p.m; ++j) {
       float f[VEC];
       Pack<TZ>::unpack(ld16(z + static_cast<int64_t>(j) * p.slot), f);
-      const float a = p.coef[j];
+      const double a = p.coef[j];
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) y[i] = fmaf(a, f[i], y[i]);
+      for (int i = 0; i < VEC; ++i) y[i] = fma(a, static_cast<double>(f[i]), y[i]);
     }
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
       const int col = col0 + i;
       if (col < p.w) {
-        float yv = y[i];
+        const float y32 = static_cast<float>(y[i]);
+        float yv = y32;
         if (p.y_dt == CSC_BF16) yv = bf16_to_f32(f32_to_bf16(yv));
-        store_out(p.Y, p.y_dt, row * p.ldy + col, y[i]);
+        store_out(p.Y, p.y_dt, row * p.ldy + col, y32);
         if (p.P) dot += static_cast<double>(load_any(p.P, p.p_dt, row * p.ldp + col)) * static_cast<double>(yv);
       }
     }
@@ -1240,7 +1243,7 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
                        const double* a, void* Y, csc_dtype y_dt, int64_t ldy, const void* P,
                        csc_dtype p_dt, int64_t ldp, double* dot, void* aux, size_t aux_bytes,
                        hipStream_t s) {
-  if (m + 1 > kMaxCombine) return fail(CSC_E_ARG, "combine supports m < 512");
+  if (m + 1 > kMaxCombine) return fail(CSC_E_ARG, "combine supports m < 256");
   if (!Y || ldy < w) return fail(CSC_E_ARG, "bad Y");
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
   const int VEC = iter_dt == CSC_F32 ? 4 : 8;  // BF16 and BF16S keep BF16 copies
@@ -1262,7 +1265,7 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
   p.p_dt = int(p_dt);
   p.ldp = ldp;
   p.part = dot ? static_cast<double*>(aux) : nullptr;
-  for (int j = 0; j <= m; ++j) p.coef[j] = static_cast<float>(a[j]);
+  for (int j = 0; j <= m; ++j) p.coef[j] = a[j];
   if (iter_dt == CSC_F32)
     hipLaunchKernelGGL(k_combine<float>, dim3(blocks), dim3(kThreads), 0, s, p);
   else

@@ -1,0 +1,106 @@
+"""Full-size checks in the launch configurations the benchmark times.
+
+C3 (N = 1M, k = 50 Zipf blocks, degree 16, d = 128, m = 120, p = 0.5): the dynamic state in
+the benchmark's forms (kept basis, four snapshots per batched launch replayed from a HIP graph)
+filters the fresh blocks of snapshots 2-5 at a cut-off the test fixes through an imported
+state; the oracle filters four sampled columns of snapshot 5's block on every row.
+
+C5 (N = 8M Chung-Lu, 160M entries, w = 64, m = 150): no oracle run fits here, so properties
+that hold at any size are checked instead: h(L) is symmetric, so X^T h(L) X must be a
+symmetric matrix, and the BF16 form must stay within the BF16 bound of the FP32 form.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import chebyshev, operator, philox
+from workloads import DynamicSBM, block_sizes_zipf, chung_lu, gaussian_block, sbm, seed_for
+from helpers import say
+
+pytestmark = pytest.mark.gpu
+
+SIGNALS = 1
+
+
+@pytest.fixture(scope="module")
+def c3_seq():
+    n, k = 1_000_000, 50
+    g = sbm(n, k, 16.0, 0.1, seed=seed_for(3, "graph"), sizes=block_sizes_zipf(n, k, 1.2))
+    dyn = DynamicSBM(g, seed=seed_for(3, "perturb"))
+    seq = [g] + [dyn.step(0.01, 0.005) for _ in range(4)]
+    say(f"C3 sequence nnz {[s.nnz for s in seq]}")
+    return seq
+
+
+@pytest.mark.parametrize("form,lam", [("fp32", 0.5), ("bf16sb", 0.5), ("fp32", 0.4), ("bf16sb", 0.4)])
+def test_c3_batched_fresh_blocks_match_oracle(csc, c3_seq, form, lam):
+    n, d, k, m, p, seed = 1_000_000, 128, 50, 120, 0.5, seed_for(3, "signals")
+    feat = torch.float32 if form == "fp32" else torch.bfloat16
+    iters = torch.float32 if form == "fp32" else "bf16s"
+    say(f"C3 full size, form {form}, cut-off {lam}")
+    # the benchmark's launch configuration of each form: FP32 one snapshot at a time with the
+    # kept basis, bf16sb four snapshots per batched launch replayed from a HIP graph
+    batched = form == "bf16sb"
+    st = csc.DynamicCSC(n, d, k, p, m, seed=seed, feat_dtype=feat, iter_dtype=iters, tau=1e9,
+                        keep_iterates=1, batch=4 if batched else 1, use_graph=batched,
+                        lloyd_iters=2)
+    # a state after snapshot 1 with the cut-off fixed by the test
+    buf = bytearray(csc.lib.csc_dyn_state_bytes(st.h))
+    h = csc.DynamicCSC.header(buf)
+    h.magic, h.n, h.d, h.k, h.m, h.qd = 0x31304E5944435343, n, d, k, m, 64
+    h.feat_dt, h.t, h.cursor, h.seed, h.lam = (0 if form == "fp32" else 1), 1, 0, seed, lam
+    st.import_state(buf)
+    Gs = [csc.Graph.from_workload(g) for g in c3_seq[1:]]
+    _, lams, refs, _ = st.steps(Gs)
+    assert lams == [lam] * 4 and not any(refs)
+    theta = st.features().float().cpu().numpy()
+    # snapshot 5 wrote columns 64..127 (the ring: 0..63, 64..127, 0..63, 64..127)
+    cols = [0, 21, 42, 63]
+    R = philox.gaussian_block(n, 64, 1 / np.sqrt(d), seed, 16 * 5 + SIGNALS,
+                              dtype="bf16" if form == "bf16sb" else np.float32)
+    A, _ = operator.normalized_adjacency(n, c3_seq[4].rowptr, c3_seq[4].colidx, c3_seq[4].w)
+    a = chebyshev.step_coefficients(m, 2.0, lam, "jackson")
+    rows = np.sort(np.random.default_rng(7).choice(n, 10_000, replace=False))
+    ref = chebyshev.filter_recurrence(A, 2.0, a, np.asarray(R[:, cols], dtype=np.float64))[rows]
+    got = theta[rows][:, [64 + c for c in cols]].astype(np.float64)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    r_norm = float(np.linalg.norm(np.asarray(R[rows][:, cols], dtype=np.float64)))
+    gain = float(np.linalg.norm(ref)) / r_norm
+    abs_err = float(np.linalg.norm(got - ref))
+    say(f"  |h(L) R| / |R| = {gain:.4f}; rel Frobenius error on 10k rows x 4 columns: {err:.3e} "
+        f"({abs_err / r_norm:.3e} of |R|)")
+    if form == "fp32":
+        # the stated 1e-5 relative to the output where the filter keeps a sizeable part of the
+        # input; near lambda_k it keeps 0.2%, and the FP32 rounding of the iterates alone (u/2 of
+        # iterates whose norm stays near |R|, m times) is then about 1e-5 of the output, so there
+        # the bound is stated relative to the input
+        if gain >= 0.01:
+            assert err <= 1e-5
+        else:
+            assert abs_err <= 1e-7 * r_norm
+    else:
+        # BF16 rounds every gathered copy (2^-9 relative) of iterates whose norm stays near |R|;
+        # the stable recurrence and |h| <= 1 keep the resulting error below 2^-9 |R| whatever the
+        # cut-off, so the bound is stated relative to the input (relative to the output it grows
+        # as the filter's gain falls: 0.09 at cut-off 0.5, 0.002 at 0.4)
+        assert abs_err <= 2.0 ** -9 * r_norm
+
+
+def test_c5_full_size_properties(csc):
+    g = chung_lu(8_000_000, 200, 20.0, 2.5, 0.1, seed=seed_for(5, "graph"))
+    say(f"C5 graph nnz {g.nnz}")
+    G = csc.Graph.from_workload(g, validate=False)
+    Gb = csc.Graph.from_workload(g, val_dtype=torch.bfloat16, validate=False)
+    X = torch.from_numpy(gaussian_block(g.n, 64, 1 / 16.0, seed=seed_for(5, "signals"))).cuda()
+    a = csc.cheb_coeffs(150, 2.0, 0.45)
+    Y = csc.cheb_filter(G, a, X)
+    Yb = csc.cheb_filter(Gb, a, X.to(torch.bfloat16), iter_dtype="bf16s").float()
+    M = (X.double().T @ Y.double()).cpu().numpy()
+    asym = np.linalg.norm(M - M.T) / np.linalg.norm(M)
+    rel = float(torch.linalg.norm(Yb.double() - Y.double()) / torch.linalg.norm(Y.double()))
+    say(f"  X^T h(L) X asymmetry {asym:.3e}; BF16S vs FP32 {rel:.3e}")
+    assert asym <= 1e-5
+    # the BF16 form starts from BF16-rounded signals (2^-9) and rounds its gathered copies; with
+    # |h| <= 1 both stay within 2^-9 |X| each
+    assert float(torch.linalg.norm(Yb.double() - Y.double())) <= 2.0 ** -8 * float(torch.linalg.norm(X.double()))
