@@ -18,12 +18,17 @@
  *    host results; all others are asynchronous.
  *  - Dense blocks are row-major: element (i, j) of an n x w block X with leading
  *    dimension ldx (in elements, ldx >= w) is X[i * ldx + j].
- *  - Handles (csc_graph, csc_dyn) own their internal device memory; it is allocated only
- *    in *_create.  Scratch memory of the other calls comes from a caller buffer `work`
+ *  - Handles (csc_graph, csc_dyn) own their internal device memory, allocated in
+ *    *_create.  The exceptions say so where they are declared: csc_lmax and
+ *    csc_graph_distance take temporary memory, and a dynamic state that tracks similarity
+ *    allocates its copy of the previous operator on the first snapshot (and grows it for a
+ *    larger one).  Scratch memory of the other calls comes from a caller buffer `work`
  *    whose size is given by the matching *_workspace_bytes query; a too-small buffer is
  *    CSC_E_ARG.
  *  - Results are deterministic given the inputs and seeds: every floating-point
- *    reduction runs in a fixed order (no floating-point atomics).
+ *    reduction runs in a fixed order.  The one floating-point atomic sum (duplicate draws
+ *    in compressive k-means) adds identical values, so its result does not depend on the
+ *    order either.
  */
 #ifndef CSC_H
 #define CSC_H
@@ -40,7 +45,7 @@ typedef enum {
   CSC_E_ARG = 1,    /* invalid argument (size, range, alignment, aliasing, workspace) */
   CSC_E_GRAPH = 2,  /* the CSR input is not a simple symmetric graph with w > 0 */
   CSC_E_DTYPE = 3,  /* unsupported element type for this argument */
-  CSC_E_NOMEM = 4,  /* device allocation failed (only in *_create) */
+  CSC_E_NOMEM = 4,  /* device allocation failed (in *_create, or where a call says it allocates) */
   CSC_E_HIP = 5,    /* a HIP runtime call failed */
   CSC_E_STATE = 6   /* handle used out of order */
 } csc_status;
