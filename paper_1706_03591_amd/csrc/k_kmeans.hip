@@ -790,45 +790,89 @@ __global__ void k_pp_cdist(const float* C, int d, int cj, double* cd) {
 // ||C_cj - C_owner||^2 >= 4 d2 (1 + 1e-9): by the triangle inequality the new centre is then
 // no closer, so the result equals the unpruned pass (the margin covers the FP64 rounding of
 // both sides).  Sixteen lanes share a row so that each load instruction reads whole rows; the
-// lanes' partial sums meet in a fixed shuffle tree.
+// lanes' partial sums meet in a fixed shuffle tree.  The block first reads the current
+// distances and owners of all its rows (coalesced) and decides which rows to read, so the
+// feature loads that follow wait on no other global load.
 template <typename TF, bool VEC, int NPC>
 __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, int64_t n, int d,
                                                       int dp, const float* C, int cj, int first,
                                                       const double* cd, int32_t* owner,
                                                       double* d2, double* bsum) {
   constexpr int V = 16 / sizeof(TF);  // values per 16-byte piece; a lane reads NPC pieces
-  constexpr int U = VEC ? 8 : 2;      // rows per group in flight
+  constexpr int U = VEC ? 8 / NPC : 2;  // rows per group in flight
+  constexpr int RB = kThreads * kRIT;  // rows per block
   __shared__ float s_cj[256];
   __shared__ double s_cd[256];
+  __shared__ double s_old[RB];
+  __shared__ unsigned char s_need[RB];
   const float* Cj = C + static_cast<int64_t>(cj) * d;
   for (int t = threadIdx.x; t < dp; t += kThreads) s_cj[t] = t < d ? Cj[t] : 0.f;
   if (!first)
     for (int t = threadIdx.x; t < cj; t += kThreads) s_cd[t] = cd[t];
   __syncthreads();
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kRIT;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RB;
+  if (first) {
+#pragma unroll
+    for (int i = 0; i < kRIT; ++i) {
+      const int r = threadIdx.x + i * kThreads;
+      s_old[r] = 0.0;
+      s_need[r] = base + r < n ? 1 : 0;
+    }
+  } else {
+    double dv[kRIT];
+    int32_t ow[kRIT];
+#pragma unroll
+    for (int i = 0; i < kRIT; ++i) {
+      const int64_t row = base + threadIdx.x + i * kThreads;
+      const int64_t rr = row < n ? row : n - 1;  // rows past n read the last row, unused
+      dv[i] = d2[rr];
+      ow[i] = owner[rr];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < kRIT; ++i) {
+      const int r = threadIdx.x + i * kThreads;
+      const bool in = base + r < n;
+      s_old[r] = in ? dv[i] : 0.0;
+      s_need[r] = (in && !(s_cd[ow[i]] >= 4.0 * dv[i] * (1.0 + 1e-9))) ? 1 : 0;
+    }
+  }
+  __syncthreads();
   const int l16 = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;  // 16 row groups per block
+  double cjd[NPC][V];  // the lane's columns of the new centre
+#pragma unroll
+  for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int c = (pc * 16 + l16) * V + i;
+      cjd[pc][i] = c < d ? static_cast<double>(s_cj[c]) : 0.0;
+    }
   double local = 0.0;
-  for (int q0 = 0; q0 < kThreads * kRIT / 16; q0 += U) {
+  for (int q0 = 0; q0 < RB / 16; q0 += U) {
     uint4 raw[U][NPC];
     bool need[U];
     double dold[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t row = base + (q0 + u) * 16 + grp;
-      need[u] = row < n;
-      dold[u] = 0.0;
-      if (!first && row < n) {
-        dold[u] = d2[row];
-        need[u] = !(s_cd[owner[row]] >= 4.0 * dold[u] * (1.0 + 1e-9));
-      }
-      const TF* rowp = F + (row < n ? row : 0) * ldf;
+      const int r = (q0 + u) * 16 + grp;
+      const int64_t row = base + r;
+      need[u] = s_need[r] != 0;
+      dold[u] = s_old[r];
+      if constexpr (VEC) {
+        // branch-free, so that all U x NPC loads are in flight together: skipped rows read
+        // row 0 and pieces past d read column 0 (in bounds, cached, and never summed)
+        const TF* rowp = F + (need[u] ? row : 0) * ldf;
 #pragma unroll
-      for (int pc = 0; pc < NPC; ++pc) {
-        const int c0 = (pc * 16 + l16) * V;
-        if (need[u] && VEC && c0 + V <= d) {
-          raw[u][pc] = *reinterpret_cast<const uint4*>(rowp + c0);
-        } else {
+        for (int pc = 0; pc < NPC; ++pc) {
+          const int c0 = (pc * 16 + l16) * V;
+          raw[u][pc] = *reinterpret_cast<const uint4*>(rowp + (c0 < d ? c0 : 0));
+        }
+      } else {
+        const TF* rowp = F + (row < n ? row : 0) * ldf;
+#pragma unroll
+        for (int pc = 0; pc < NPC; ++pc) {
+          const int c0 = (pc * 16 + l16) * V;
           TF tmp[V];
 #pragma unroll
           for (int i = 0; i < V; ++i) tmp[i] = (need[u] && c0 + i < d) ? rowp[c0 + i] : TF(0);
@@ -836,35 +880,37 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
         }
       }
     }
+    // keep the loads of all U rows ahead of the first use
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t row = base + (q0 + u) * 16 + grp;
+      // every row is summed (no divergent branch around the loads' uses); a skipped row's
+      // sum is then discarded
       double s = 0.0;
-      if (need[u]) {
 #pragma unroll
-        for (int pc = 0; pc < NPC; ++pc) {
-          const int c0 = (pc * 16 + l16) * V;
-          const uint32_t w[4] = {raw[u][pc].x, raw[u][pc].y, raw[u][pc].z, raw[u][pc].w};
-          float f[V];
-          if constexpr (sizeof(TF) == 4) {
+      for (int pc = 0; pc < NPC; ++pc) {
+        const int c0 = (pc * 16 + l16) * V;
+        const uint32_t w[4] = {raw[u][pc].x, raw[u][pc].y, raw[u][pc].z, raw[u][pc].w};
+        float f[V];
+        if constexpr (sizeof(TF) == 4) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(w[i]);
-          } else {
+          for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(w[i]);
+        } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              f[2 * i] = __uint_as_float(w[i] << 16);
-              f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-            }
-          }
-#pragma unroll
-          for (int i = 0; i < V; ++i) {
-            if (c0 + i < d) {
-              const double t = static_cast<double>(f[i]) - static_cast<double>(s_cj[c0 + i]);
-              s += t * t;
-            }
+          for (int i = 0; i < 4; ++i) {
+            f[2 * i] = __uint_as_float(w[i] << 16);
+            f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
           }
         }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          // columns past d add an exact zero
+          const double t = c0 + i < d ? static_cast<double>(f[i]) - cjd[pc][i] : 0.0;
+          s += t * t;
+        }
       }
+      if (!need[u]) s = 0.0;
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 16);
       if (row < n && l16 == 0) {
@@ -1207,7 +1253,8 @@ csc_status launch_kmeans_seed(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   double* d2 = reinterpret_cast<double*>(base + L.off_d2);
   double* bsum = reinterpret_cast<double*>(base + L.off_bsum);
   int32_t* sel = reinterpret_cast<int32_t*>(base + L.off_sel);
-  const bool vec = rows_aligned(F, f_dt, ldf);
+  // the 16-byte path needs aligned rows and whole 16-byte pieces (its loads are unmasked)
+  const bool vec = rows_aligned(F, f_dt, ldf) && d % static_cast<int>(16 / dtype_size(f_dt)) == 0;
   const int64_t rows_per_blk = static_cast<int64_t>(kThreads) * kRIT;
   const int64_t nblk = assign_blocks(n);
   const int dp = padded_d(d);

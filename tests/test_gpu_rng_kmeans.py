@@ -98,15 +98,21 @@ def test_update_matches_oracle(csc, n, d, k):
     assert torch.equal(Cg, Cg2)
 
 
-@pytest.mark.parametrize("n,d,k", [(3000, 16, 6), (50000, 64, 20)])
-def test_kmeanspp_matches_oracle(csc, n, d, k):
-    say(f"kmeans++ n={n} d={d} k={k}")
-    F = _mixture(n, d, k, seed=7)
+@pytest.mark.parametrize("n,d,k,dtype", [(3000, 16, 6, torch.float32), (50000, 64, 20, torch.float32),
+                                         (3000, 200, 8, torch.float32),
+                                         (20011, 128, 40, torch.bfloat16),
+                                         (6001, 256, 60, torch.bfloat16)])
+def test_kmeanspp_matches_oracle(csc, n, d, k, dtype):
+    # the BF16 cases read one (d = 128) or two (d = 256) 16-byte pieces per lane; well
+    # separated mixtures make the triangle-inequality skip fire on most rows of later passes
+    say(f"kmeans++ n={n} d={d} k={k} {dtype}")
+    F = torch.from_numpy(_mixture(n, d, k, seed=7)).to(dtype)
+    Fn = F.double().numpy()
     u = csc.uniforms(k, seed=99, stream_id=2)
-    C, idx = csc.kmeans_seed(torch.from_numpy(F).cuda(), u, k)
-    ref = okm.kmeanspp(F.astype(np.float64), k, philox.uniforms(k, 99, 2))
+    C, idx = csc.kmeans_seed(F.cuda(), u, k)
+    ref = okm.kmeanspp(Fn, k, philox.uniforms(k, 99, 2))
     assert idx.cpu().numpy().tolist() == ref.tolist()
-    assert np.array_equal(C.cpu().numpy(), F[ref])
+    assert np.array_equal(C.double().cpu().numpy(), Fn[ref])
 
 
 def test_lloyd_matches_oracle(csc):
