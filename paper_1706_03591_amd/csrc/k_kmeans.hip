@@ -577,15 +577,34 @@ __global__ void k_upd_clear(unsigned long long* sums, int64_t kd, int32_t* cnt, 
   if (t == 0 && maxabs) maxabs[0] = 0u;
 }
 
+// max |F| as float bits (the fixed-point scale of the update).  A contiguous, 16-byte aligned
+// block is read as one flat array of 16-byte pieces; otherwise row by row.
 template <typename TF>
-__global__ void k_maxabs(const TF* F, int64_t ldf, int64_t n, int d, uint32_t* out) {
-  const int64_t total = n * d;
+__global__ void k_maxabs(const TF* F, int64_t ldf, int64_t n, int d, int flat, uint32_t* out) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   float m = 0.f;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int64_t r = i / d;
-    const int c = static_cast<int>(i - r * d);
-    m = fmaxf(m, fabsf(to_f<TF>(F[r * ldf + c])));
+  if (flat) {
+    constexpr int V = 16 / sizeof(TF);
+    const int64_t total = n * d, nv = total / V;
+    const uint4* P = reinterpret_cast<const uint4*>(F);
+    for (int64_t i = gid; i < nv; i += stride) {
+      const uint4 u = P[i];
+      const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if constexpr (sizeof(TF) == 4) {
+          m = fmaxf(m, fabsf(__uint_as_float(w[q])));
+        } else {
+          m = fmaxf(m, fabsf(__uint_as_float(w[q] << 16)));
+          m = fmaxf(m, fabsf(__uint_as_float(w[q] & 0xffff0000u)));
+        }
+      }
+    }
+    for (int64_t i = nv * V + gid; i < total; i += stride) m = fmaxf(m, fabsf(to_f<TF>(F[i])));
+  } else {
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x)
+      for (int c = threadIdx.x; c < d; c += blockDim.x) m = fmaxf(m, fabsf(to_f<TF>(F[r * ldf + c])));
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
@@ -599,15 +618,23 @@ __global__ void k_maxabs(const TF* F, int64_t ldf, int64_t n, int d, uint32_t* o
 // fixed point, so neither the order inside a label nor the order of the atomics changes them.
 constexpr int kUpdRows = 1024;
 
-template <typename TF>
+template <typename TF, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, int64_t n, int d,
                                                       const int32_t* labels, int k, int64_t rpb,
-                                                      int nsub, int cw, const uint32_t* maxabs,
+                                                      int nsub, int cw, int64_t nblk, int ny,
+                                                      const uint32_t* maxabs,
                                                       unsigned long long* gsums, int32_t* gcnt) {
   // LDS: k * cw sums, then k counts, k offsets, k block totals, rpb labels, rpb row order.
   // The block takes nsub consecutive stretches of rpb rows; each is sorted by label on its
   // own, and the sums of all of them meet in the same LDS accumulators before the single
   // flush to global memory.
+  // Blocks are numbered so that the ny column groups of one row block follow each other on
+  // the same XCD (workgroups go to the eight XCDs in turn): they then share that XCD's L2
+  // copy of the rows' cache lines.  Ids past the last row block exit at once.
+  const int64_t L = blockIdx.x;
+  const int64_t bx = (L / (8 * ny)) * 8 + (L & 7);
+  const int by = static_cast<int>((L >> 3) % ny);
+  if (bx >= nblk) return;
   extern __shared__ unsigned long long s_acc[];
   int32_t* s_cnt = reinterpret_cast<int32_t*>(s_acc + static_cast<size_t>(k) * cw);
   int32_t* s_off = s_cnt + k;
@@ -618,17 +645,19 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
   for (int t = threadIdx.x; t < k; t += kThreads) s_tot[t] = 0;
   const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
   __shared__ int s_nv;
+  __shared__ int s_wsum[kThreads / 64];
   // a lane owns 8 consecutive columns; LR lanes cover the block's cw columns of one row, and
   // the kThreads / LR row slots split the label-ordered rows into contiguous stretches
   const int LR = cw / 8;
   const int slots = kThreads / LR;
   const int slot = threadIdx.x / LR;
   const int c8 = (threadIdx.x % LR) * 8;
-  const int col0 = blockIdx.y * cw + c8;
-  const bool vec = sizeof(TF) * 8 % 16 == 0 && col0 + 8 <= d &&
-                   reinterpret_cast<uintptr_t>(F) % 16 == 0 && (ldf * sizeof(TF)) % 16 == 0;
+  const int col0 = by * cw + c8;
+  // VEC (aligned rows, d a multiple of 8): unmasked 16-byte loads; a lane past d reads
+  // column 0 and its sums are never flushed
+  const int lcol = VEC && col0 >= d ? 0 : col0;
   for (int sub = 0; sub < nsub; ++sub) {
-    const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * nsub + sub) * rpb;
+    const int64_t r0 = (bx * nsub + sub) * rpb;
     const int nr = static_cast<int>(max<int64_t>(0, min(r0 + rpb, n) - r0));
     if (nr == 0) break;  // uniform across the block
     for (int t = threadIdx.x; t < k; t += kThreads) s_cnt[t] = 0;
@@ -640,14 +669,26 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
       if (lb >= 0) atomicAdd(&s_cnt[lb], 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int run = 0;
-      for (int c = 0; c < k; ++c) {
-        s_off[c] = run;
-        run += s_cnt[c];
-        s_tot[c] += s_cnt[c];
+    {
+      // exclusive prefix of the k <= kThreads label counts: a scan in each wave, then the
+      // totals of the waves before
+      const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+      const int c = t < k ? s_cnt[t] : 0;
+      int x = c;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
       }
-      s_nv = run;
+      if (lane == 63) s_wsum[wave] = x;
+      __syncthreads();
+      int add = 0;
+      for (int w = 0; w < wave; ++w) add += s_wsum[w];
+      if (t < k) {
+        s_off[t] = add + x - c;
+        s_tot[t] += c;
+      }
+      if (t == kThreads - 1) s_nv = add + x;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nr; i += kThreads)
@@ -667,42 +708,57 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
         if (run[i] != 0 && c8 + i < cw)
           atomicAdd(&s_acc[cur * cw + c8 + i], static_cast<unsigned long long>(run[i]));
     };
-    auto load8v = [&](int ii, float* v) {
-      const TF* rp = F + (r0 + ii) * ldf + col0;
-      if (vec) {
-        if constexpr (sizeof(TF) == 4) {
-          const uint4 u0 = reinterpret_cast<const uint4*>(rp)[0];
-          const uint4 u1 = reinterpret_cast<const uint4*>(rp)[1];
-          v[0] = __uint_as_float(u0.x); v[1] = __uint_as_float(u0.y);
-          v[2] = __uint_as_float(u0.z); v[3] = __uint_as_float(u0.w);
-          v[4] = __uint_as_float(u1.x); v[5] = __uint_as_float(u1.y);
-          v[6] = __uint_as_float(u1.z); v[7] = __uint_as_float(u1.w);
-        } else {
-          const uint4 u = reinterpret_cast<const uint4*>(rp)[0];
-          const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+    constexpr int RW = sizeof(TF) / 2;  // 16-byte pieces per eight values
+    auto load_raw = [&](int ii, uint4* raw) {
+      const TF* rp = F + (r0 + ii) * ldf + lcol;
+      if constexpr (VEC) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            v[2 * i] = __uint_as_float(w[i] << 16);
-            v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-          }
-        }
+        for (int w = 0; w < RW; ++w) raw[w] = reinterpret_cast<const uint4*>(rp)[w];
       } else {
+        TF tmp[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = col0 + i < d ? to_f<TF>(rp[i]) : 0.f;
+        for (int i = 0; i < 8; ++i) tmp[i] = col0 + i < d ? rp[i] : TF(0);
+        __builtin_memcpy(raw, tmp, sizeof(tmp));
       }
     };
-    int q = q0;
-    for (; q + 4 <= q1; q += 4) {
-      int lb[4];
-      float v[4][8];
+    auto unpack = [&](const uint4* raw, float* v) {
+      if constexpr (sizeof(TF) == 4) {
+        v[0] = __uint_as_float(raw[0].x); v[1] = __uint_as_float(raw[0].y);
+        v[2] = __uint_as_float(raw[0].z); v[3] = __uint_as_float(raw[0].w);
+        v[4] = __uint_as_float(raw[1].x); v[5] = __uint_as_float(raw[1].y);
+        v[6] = __uint_as_float(raw[1].z); v[7] = __uint_as_float(raw[1].w);
+      } else {
+        const uint32_t w[4] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w};
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+        for (int i = 0; i < 4; ++i) {
+          v[2 * i] = __uint_as_float(w[i] << 16);
+          v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+      }
+    };
+    auto load8v = [&](int ii, float* v) {
+      uint4 raw[RW];
+      load_raw(ii, raw);
+      unpack(raw, v);
+    };
+    // UR rows in flight per lane (eight 16-byte loads)
+    constexpr int UR = 8 / RW;
+    int q = q0;
+    for (; q + UR <= q1; q += UR) {
+      int lb[UR];
+      uint4 raw[UR][RW];
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
         const int ii = s_perm[q + u];
         lb[u] = s_lab[ii];
-        load8v(ii, v[u]);
+        load_raw(ii, raw[u]);
       }
+      // all the rows' loads ahead of the first use
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < UR; ++u) {
+        float v[8];
+        unpack(raw[u], v);
         if (lb[u] != cur) {
           flush();
           cur = lb[u];
@@ -710,7 +766,7 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
           for (int i = 0; i < 8; ++i) run[i] = 0;
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[u][i]), S));
+        for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[i]), S));
       }
     }
     for (; q < q1; ++q) {
@@ -732,10 +788,10 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
   }
   for (int t = threadIdx.x; t < k * cw; t += kThreads) {
     const int c = t / cw, cc = t % cw;
-    const int gc = blockIdx.y * cw + cc;
+    const int gc = by * cw + cc;
     if (gc < d && s_acc[t] != 0ull) atomicAdd(&gsums[static_cast<int64_t>(c) * d + gc], s_acc[t]);
   }
-  if (blockIdx.y == 0)
+  if (by == 0)
     for (int t = threadIdx.x; t < k; t += kThreads)
       if (s_tot[t]) atomicAdd(&gcnt[t], s_tot[t]);
 }
@@ -1025,6 +1081,21 @@ bool rows_aligned(const void* F, csc_dtype f_dt, int64_t ldf) {
 
 int padded_d(int d) { return (d + kCH - 1) / kCH * kCH; }
 
+csc_status launch_maxabs(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
+                         uint32_t* mx, hipStream_t s) {
+  const int flat = (ldf == d && reinterpret_cast<uintptr_t>(F) % 16 == 0) ? 1 : 0;
+  const unsigned mblocks = static_cast<unsigned>(
+      std::max<int64_t>(1, std::min<int64_t>(2048, flat ? (n * d / 8 + 255) / 256 : n)));
+  if (f_dt == CSC_F32)
+    hipLaunchKernelGGL(k_maxabs<float>, dim3(mblocks), dim3(256), 0, s, static_cast<const float*>(F),
+                       ldf, n, d, flat, mx);
+  else
+    hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(F), ldf, n, d, flat, mx);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
 int64_t assign_blocks(int64_t n) {
   const int64_t per = static_cast<int64_t>(kThreads) * kRIT;
   return std::max<int64_t>(1, (n + per - 1) / per);
@@ -1079,15 +1150,7 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
   const int64_t kd = static_cast<int64_t>(k) * d;
   hipLaunchKernelGGL(k_upd_clear, dim3(static_cast<unsigned>((std::max<int64_t>(kd, k) + 255) / 256)),
                      dim3(256), 0, s, sums, kd, cnt, k, max_ready ? nullptr : mx);
-  if (!max_ready) {
-    const unsigned mblocks = static_cast<unsigned>(std::min<int64_t>(2048, (n * d + 255) / 256));
-    if (f_dt == CSC_F32)
-      hipLaunchKernelGGL(k_maxabs<float>, dim3(mblocks), dim3(256), 0, s, static_cast<const float*>(F),
-                         ldf, n, d, mx);
-    else
-      hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(F), ldf, n, d, mx);
-  }
+  if (!max_ready) CSC_TRY(launch_maxabs(F, f_dt, ldf, n, d, mx, s));
   const int cw = k <= 112 ? 64 : 32;
   // rows per stretch: up to kUpdRows, within 64 KiB of LDS next to the k x cw sums; each block
   // takes up to 16 stretches (about 512 blocks across x), so the k x cw flush to global
@@ -1099,14 +1162,20 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
   const int nsub = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(16, nstretch / 512)));
   const int64_t nblk = (nstretch + nsub - 1) / nsub;
   const size_t lds = fixed_lds + static_cast<size_t>(rpb) * 8;
-  const dim3 grid(static_cast<unsigned>(nblk), static_cast<unsigned>((d + cw - 1) / cw));
-  if (f_dt == CSC_F32)
-    hipLaunchKernelGGL(k_upd_acc<float>, grid, dim3(kThreads), lds, s, static_cast<const float*>(F),
-                       ldf, n, d, labels, k, rpb, nsub, cw, mx, sums, cnt);
-  else
-    hipLaunchKernelGGL(k_upd_acc<uint16_t>, grid, dim3(kThreads), lds, s,
-                       static_cast<const uint16_t*>(F), ldf, n, d, labels, k, rpb, nsub, cw, mx,
-                       sums, cnt);
+  const int ny = (d + cw - 1) / cw;
+  // row blocks in groups of eight, each group's ny column groups in turn per XCD
+  const int64_t grid = (nblk + 7) / 8 * 8 * ny;
+  const bool vec = rows_aligned(F, f_dt, ldf) && d % 8 == 0;
+#define CSC_UPD(TF, V)                                                                         \
+  hipLaunchKernelGGL((k_upd_acc<TF, V>), dim3(static_cast<unsigned>(grid)), dim3(kThreads), lds, s, \
+                     static_cast<const TF*>(F), ldf, n, d, labels, k, rpb, nsub, cw, nblk, ny, mx,  \
+                     sums, cnt)
+  if (f_dt == CSC_F32) {
+    if (vec) CSC_UPD(float, true); else CSC_UPD(float, false);
+  } else {
+    if (vec) CSC_UPD(uint16_t, true); else CSC_UPD(uint16_t, false);
+  }
+#undef CSC_UPD
   hipLaunchKernelGGL(k_upd_final, dim3(static_cast<unsigned>((kd + 255) / 256)), dim3(256), 0, s,
                      sums, cnt, mx, n, k, d, C, counts);
   CSC_HIP(hipGetLastError());
@@ -1321,15 +1390,7 @@ csc_status run_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
   // max |F| once: the features do not change during the Lloyd rounds
   hipLaunchKernelGGL(k_upd_clear, dim3(1), dim3(256), 0, s, static_cast<unsigned long long*>(nullptr),
                      int64_t(0), static_cast<int32_t*>(nullptr), 0, mx);
-  {
-    const unsigned mblocks = static_cast<unsigned>(std::min<int64_t>(2048, (n * d + 255) / 256));
-    if (f_dt == CSC_F32)
-      hipLaunchKernelGGL(k_maxabs<float>, dim3(mblocks), dim3(256), 0, s, static_cast<const float*>(F),
-                         ldf, n, d, mx);
-    else
-      hipLaunchKernelGGL(k_maxabs<uint16_t>, dim3(mblocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(F), ldf, n, d, mx);
-  }
+  CSC_TRY(launch_maxabs(F, f_dt, ldf, n, d, mx, s));
   const int64_t nparts = assign_parts(n, d, k, F, f_dt, ldf);
   for (int it = 0; it <= iters; ++it) {
     CSC_TRY(assign_impl(F, f_dt, ldf, n, d, C, k, labels, nullptr, objective ? obj : nullptr,

@@ -78,24 +78,39 @@ def test_assign_bf16_features(csc, n, d, k):
     assert np.sum((lab.cpu().numpy() != ref) & ~(exempt & ok_tie)) == 0
 
 
-@pytest.mark.parametrize("n,d,k", [(5000, 32, 5), (100003, 128, 50), (3000, 256, 200)])
-def test_update_matches_oracle(csc, n, d, k):
-    say(f"kmeans update n={n} d={d} k={k}")
-    F = _mixture(n, d, k, seed=n + 1)
+@pytest.mark.parametrize("n,d,k,dtype", [(5000, 32, 5, torch.float32), (100003, 128, 50, torch.float32),
+                                         (3000, 256, 200, torch.float32), (9001, 50, 20, torch.float32),
+                                         (20011, 200, 130, torch.float32),
+                                         (100003, 128, 50, torch.bfloat16),
+                                         (600000, 256, 200, torch.bfloat16)])
+def test_update_matches_oracle(csc, n, d, k, dtype):
+    # d = 50: rows not in whole 16-byte pieces (masked loads); d = 200, k = 130: 32-column
+    # groups, the last one partly past d; N = 600000: 586 row blocks (not a multiple of the
+    # eight XCDs) times eight column groups
+    say(f"kmeans update n={n} d={d} k={k} {dtype}")
+    F = torch.from_numpy(_mixture(n, d, k, seed=n + 1)).to(dtype)
     rng = np.random.default_rng(2)
     lab = rng.integers(0, k, size=n).astype(np.int32)
     lab[lab == k - 1] = 0  # cluster k-1 empty: keeps its previous centroid
     C0 = rng.standard_normal((k, d)).astype(np.float32)
     Cg = torch.from_numpy(C0.copy()).cuda()
-    counts = csc.kmeans_update(torch.from_numpy(F).cuda(), torch.from_numpy(lab).cuda(), Cg)
-    ref, rc = okm.update(F.astype(np.float64), lab, C0.astype(np.float64))
+    Fg = F.cuda()
+    counts = csc.kmeans_update(Fg, torch.from_numpy(lab).cuda(), Cg)
+    ref, rc = okm.update(F.double().numpy(), lab, C0.astype(np.float64))
     assert np.array_equal(counts.cpu().numpy(), rc)
     got = Cg.cpu().numpy()
     assert np.array_equal(got[k - 1], C0[k - 1])
     assert np.max(np.abs(got - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
     Cg2 = torch.from_numpy(C0.copy()).cuda()
-    csc.kmeans_update(torch.from_numpy(F).cuda(), torch.from_numpy(lab).cuda(), Cg2)
+    csc.kmeans_update(Fg, torch.from_numpy(lab).cuda(), Cg2)
     assert torch.equal(Cg, Cg2)
+    # the same rows with a leading dimension of d + 8 (row-wise max scan, and unaligned rows
+    # where (d + 8) x element size is not a multiple of 16 bytes): fixed-point sums, same bits
+    Fp = torch.zeros((n, d + 8), dtype=dtype, device="cuda")
+    Fp[:, :d] = Fg
+    Cg3 = torch.from_numpy(C0.copy()).cuda()
+    csc.kmeans_update(Fp[:, :d], torch.from_numpy(lab).cuda(), Cg3)
+    assert torch.equal(Cg, Cg3)
 
 
 @pytest.mark.parametrize("n,d,k,dtype", [(3000, 16, 6, torch.float32), (50000, 64, 20, torch.float32),
