@@ -255,11 +255,24 @@ __device__ inline void load8(const TF* F, int64_t ldf, int64_t n, int d, int64_t
 }
 
 // Raw 16-byte loads of eight consecutive values of row `row` from column col (zeros past d
-// or n); RW = 1 (BF16) or 2 (FP32) vectors.
-template <typename TF>
+// or n); RW = 1 (BF16) or 2 (FP32) vectors.  FULL (aligned rows, d a multiple of 8): one
+// unmasked load from an in-bounds address, so the loads of a panel stay in flight together;
+// rows past n then hold row 0's values (their results are never written) and pieces past d
+// are zeroed.
+template <typename TF, bool FULL>
 __device__ inline void load_raw8(const TF* F, int64_t ldf, int64_t n, int d, int64_t row, int col,
                                  u32x4* raw) {
   constexpr int RW = sizeof(TF) / 2;
+  if constexpr (FULL) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(F + (row < n ? row : 0) * ldf + (col < d ? col : 0));
+    const u32x4 z = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const u32x4 v = p[q];
+      raw[q] = col < d ? v : z;
+    }
+    return;
+  }
   if (row < n && col + 8 <= d) {
     const u32x4* p = reinterpret_cast<const u32x4*>(F + row * ldf + col);
 #pragma unroll
@@ -322,7 +335,7 @@ inline size_t mf_lds_bytes(int DP, int kc_max) {
 // several LDS chunks: each staged chunk then serves 16 WV T rows, dividing the re-staging
 // traffic; the registers of T = 2 allow one such block per CU, the same eight waves as two
 // blocks of four).
-template <typename TF, int DP, int T, int WV>
+template <typename TF, int DP, int T, int WV, bool FULL>
 __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf, int64_t n, int d,
                                                    const uint16_t* parts, const double* cn_g,
                                                    const float* C, int k, int kp, int kc_max,
@@ -355,7 +368,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
   if constexpr (PF) {
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      load_raw8<TF>(F, ldf, n, d, row_of(blockIdx.x, 0), s * 32 + lq * 8, raw[0][s]);
+      load_raw8<TF, FULL>(F, ldf, n, d, row_of(blockIdx.x, 0), s * 32 + lq * 8, raw[0][s]);
   }
   for (int64_t panel = blockIdx.x; panel < panels; panel += gridDim.x) {
     if constexpr (!PF) {
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-          load_raw8<TF>(F, ldf, n, d, row_of(panel, t), s * 32 + lq * 8, raw[t][s]);
+          load_raw8<TF, FULL>(F, ldf, n, d, row_of(panel, t), s * 32 + lq * 8, raw[t][s]);
     }
     double bl3[T][3], um[T], fnl[T];  // three smallest lower ends, smallest upper end, ||f||
     int bi3[T][3];
@@ -400,22 +413,40 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
     if (PF && panel + gridDim.x < panels) {
 #pragma unroll
       for (int s = 0; s < NS; ++s)
-        load_raw8<TF>(F, ldf, n, d, row_of(panel + gridDim.x, 0), s * 32 + lq * 8, raw[0][s]);
+        load_raw8<TF, FULL>(F, ldf, n, d, row_of(panel + gridDim.x, 0), s * 32 + lq * 8, raw[0][s]);
     }
     for (int chunk = 0; chunk < nchunks; ++chunk) {
       const int c0 = chunk * kc_max;
       const int kc = min(kc_max, kp - c0);
       if (nchunks > 1 || !staged) {
         __syncthreads();
-        // 16-byte copies of the chunk's three parts, then its norms
+        // 16-byte copies of the chunk's three parts, SU loads in flight per thread (the last
+        // group re-reads the final piece instead of branching), then its norms
+        constexpr int SU = 4;
         const int vpr = DP / 8;
-        for (int q = threadIdx.x; q < 3 * kc * vpr; q += blockDim.x) {
-          const int p = q / (kc * vpr);
-          const int rem = q - p * kc * vpr;
-          const int c = rem / vpr, v = rem - c * vpr;
-          const u32x4 val = *reinterpret_cast<const u32x4*>(
-              parts + (static_cast<int64_t>(p) * kp + c0 + c) * DP + 8 * v);
-          *reinterpret_cast<u32x4*>(s_cb + (p * kc_max + c) * SB + 8 * v) = val;
+        const int tot = 3 * kc * vpr;
+        for (int q0 = threadIdx.x; q0 < tot; q0 += SU * blockDim.x) {
+          u32x4 val[SU];
+#pragma unroll
+          for (int j = 0; j < SU; ++j) {
+            const int q = min(q0 + j * static_cast<int>(blockDim.x), tot - 1);
+            const int p = q / (kc * vpr);
+            const int rem = q - p * kc * vpr;
+            const int c = rem / vpr, v = rem - c * vpr;
+            val[j] = *reinterpret_cast<const u32x4*>(
+                parts + (static_cast<int64_t>(p) * kp + c0 + c) * DP + 8 * v);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int j = 0; j < SU; ++j) {
+            const int q = q0 + j * static_cast<int>(blockDim.x);
+            if (q < tot) {
+              const int p = q / (kc * vpr);
+              const int rem = q - p * kc * vpr;
+              const int c = rem / vpr, v = rem - c * vpr;
+              *reinterpret_cast<u32x4*>(s_cb + (p * kc_max + c) * SB + 8 * v) = val[j];
+            }
+          }
         }
         for (int c = threadIdx.x; c < kc; c += blockDim.x) {
           const double q = cn_g[c0 + c];
@@ -1245,11 +1276,19 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
                        P.kp, P.DP, parts);
     hipLaunchKernelGGL(k_centroid_norms, dim3(P.kp), dim3(64), 0, s, C, k, d, P.kp, cn);
     const unsigned blocks = static_cast<unsigned>(P.blocks);
-#define CSC_MF(TF, DPV, TV)                                                                        \
-  hipLaunchKernelGGL((k_assign_mf<TF, DPV, TV, (TV == 2 ? 8 : 4)>), dim3(blocks), dim3(64 * P.wv), \
+#define CSC_MF_F(TF, DPV, TV, FV)                                                                   \
+  hipLaunchKernelGGL((k_assign_mf<TF, DPV, TV, (TV == 2 ? 8 : 4), FV>), dim3(blocks), dim3(64 * P.wv), \
                      P.lds, s,                                                                    \
                      static_cast<const TF*>(F), ldf, n, d, parts, cn, C, k, P.kp, P.kc, labels,   \
                      best_d2, obj_part)
+    // whole 16-byte pieces: the unmasked row loads
+    const bool full = d % 8 == 0;
+#define CSC_MF(TF, DPV, TV)                  \
+  if (full) {                                \
+    CSC_MF_F(TF, DPV, TV, true);             \
+  } else {                                   \
+    CSC_MF_F(TF, DPV, TV, false);            \
+  }
 #define CSC_MF_DP(TF, TV)                    \
   switch (P.DP) {                            \
     case 32: CSC_MF(TF, 32, TV); break;      \
@@ -1262,6 +1301,7 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
     else { CSC_MF_DP(uint16_t, 2) }
 #undef CSC_MF_DP
 #undef CSC_MF
+#undef CSC_MF_F
     CSC_HIP(hipGetLastError());
     return CSC_OK;
   }
