@@ -392,12 +392,12 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       for (int s = 0; s < NS; ++s) {
         float v[8];
         raw8_to_f<TF>(raw[t][s], v);
+        // BF16 rows are their own operand: the loaded bits, in memory order
+        if constexpr (NP == 1) a[t][0][s] = __builtin_bit_cast(bf16x8, raw[t][s][0]);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           fs = fmaf(v[e], v[e], fs);
-          if constexpr (NP == 1) {
-            a[t][0][s][e] = __builtin_bit_cast(__bf16, f32_to_bf16(v[e]));
-          } else {
+          if constexpr (NP == 3) {
             uint16_t h, m, l;
             split3(v[e], h, m, l);
             a[t][0][s][e] = __builtin_bit_cast(__bf16, h);
@@ -489,17 +489,36 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
           for (int r = 0; r < 4; ++r) {
             const int lc = ct * 16 + mf_drow(r, lq);
             const int cent = c0 + lc;
-            if (cent < k) {
+            double* b = bl3[t];
+            int* ix = bi3[t];
+            if constexpr (T == 1 && NP == 1) {
+              // sorted insertion of (lo, cent) into the three smallest lower ends, as selects
+              // (no branches, so no register shuffling at joins); centroids arrive in
+              // increasing index order within a lane, and strict < keeps ties on the lower
+              // index
+              const double cnv = s_cn[lc];
+              const double crv = s_cr[lc];
+              const double sc = cnv - 2.0 * (dot[r] + static_cast<double>(small[r]));
+              const double e = E2 * fnl[t] * crv + 1e-13 * (cnv + fnl[t] * crv);
+              const bool real = cent < k;
+              um[t] = real ? fmin(um[t], sc + e) : um[t];
+              const double lo = real ? sc - e : INFINITY;
+              const bool l0 = lo < b[0], l1 = lo < b[1], l2 = lo < b[2];
+              b[2] = l1 ? b[1] : (l2 ? lo : b[2]);
+              ix[2] = l1 ? ix[1] : (l2 ? cent : ix[2]);
+              b[1] = l0 ? b[0] : (l1 ? lo : b[1]);
+              ix[1] = l0 ? ix[0] : (l1 ? cent : ix[1]);
+              b[0] = l0 ? lo : b[0];
+              ix[0] = l0 ? cent : ix[0];
+            } else if (cent < k) {
+              // the same insertion with branches (two row tiles or FP32 rows: the selects'
+              // extra live registers would cost occupancy or spill)
               const double cnv = s_cn[lc];
               const double crv = s_cr[lc];
               const double sc = cnv - 2.0 * (dot[r] + static_cast<double>(small[r]));
               const double e = E2 * fnl[t] * crv + 1e-13 * (cnv + fnl[t] * crv);
               um[t] = fmin(um[t], sc + e);
-              // centroids arrive in increasing index order within a lane: strict < keeps
-              // ties on the lower index
               const double lo = sc - e;
-              double* b = bl3[t];
-              int* ix = bi3[t];
               if (lo < b[2]) {
                 if (lo < b[1]) {
                   b[2] = b[1]; ix[2] = ix[1];
