@@ -452,6 +452,65 @@ __global__ void k_init(const void* X, int x_dt, int64_t ldx, int64_t n, int w, i
   if (acc) acc[row * wpad + col] = a0 * stored;
 }
 
+// k_init for eight columns per thread (16-byte loads and stores): X is F32 or BF16 with
+// 16-byte aligned rows and w a multiple of 8, so a group of eight columns lies wholly inside
+// or wholly past w, and inside one tile (wt is a multiple of 8).  Same values as k_init.
+template <typename TZ>
+__global__ void k_init8(const void* X, int x_dt, int64_t ldx, int64_t n, int w, int wpad, int wt,
+                        TZ* z0, float* acc, float a0, float* s0) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int gpr = wpad / 8;
+  if (g >= n * gpr) return;
+  const int64_t row = g / gpr;
+  const int col = static_cast<int>(g - row * gpr) * 8;
+  float x[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) x[i] = 0.f;
+  if (col < w) {
+    if (x_dt == CSC_BF16) {
+      const uint4 u = ld16(static_cast<const uint16_t*>(X) + row * ldx + col);
+      const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) {
+        x[2 * k2] = __uint_as_float(wd[k2] << 16);
+        x[2 * k2 + 1] = __uint_as_float(wd[k2] & 0xffff0000u);
+      }
+    } else {
+      const float* xp = static_cast<const float*>(X) + row * ldx + col;
+      const uint4 u0 = ld16(xp), u1 = ld16(xp + 4);
+      x[0] = __uint_as_float(u0.x); x[1] = __uint_as_float(u0.y);
+      x[2] = __uint_as_float(u0.z); x[3] = __uint_as_float(u0.w);
+      x[4] = __uint_as_float(u1.x); x[5] = __uint_as_float(u1.y);
+      x[6] = __uint_as_float(u1.z); x[7] = __uint_as_float(u1.w);
+    }
+  }
+  const int tile = col / wt, c = col - tile * wt;
+  const int64_t e = static_cast<int64_t>(tile) * n * wt + row * wt + c;
+  float stored[8];
+  if constexpr (sizeof(TZ) == 4) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) stored[i] = x[i];
+    st8f(reinterpret_cast<float*>(z0) + e, x);
+  } else {
+    uint32_t wd[4];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      const uint16_t lo = f32_to_bf16(x[2 * k2]), hi = f32_to_bf16(x[2 * k2 + 1]);
+      wd[k2] = static_cast<uint32_t>(lo) | (static_cast<uint32_t>(hi) << 16);
+      stored[2 * k2] = s0 ? x[2 * k2] : bf16_to_f32(lo);  // BF16S: the state keeps FP32
+      stored[2 * k2 + 1] = s0 ? x[2 * k2 + 1] : bf16_to_f32(hi);
+    }
+    st16(z0 + e, make_uint4(wd[0], wd[1], wd[2], wd[3]));
+    if (s0) st8f(s0 + e, x);
+  }
+  if (acc) {
+    float av[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) av[i] = a0 * stored[i];
+    st8f(acc + row * wpad + col, av);
+  }
+}
+
 __global__ void k_acc_out(const float* acc, int64_t n, int w, int wpad, void* y, int y_dt,
                           int64_t ldy) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -527,6 +586,20 @@ BatchFn batch_fn(csc_dtype iter_dt, int lpr, csc_dtype val_dt) {
 // acc is given.
 void launch_init(csc_dtype iter_dt, const void* X, csc_dtype x_dt, int64_t ldx, int64_t n, int w,
                  int wpad, int wt, void* z0, float* acc, float a0, float* s0, hipStream_t s) {
+  const size_t xs = dtype_size(x_dt);
+  if ((x_dt == CSC_F32 || x_dt == CSC_BF16) && w % 8 == 0 && wpad % 8 == 0 && wt % 8 == 0 &&
+      reinterpret_cast<uintptr_t>(X) % 16 == 0 && (static_cast<size_t>(ldx) * xs) % 16 == 0) {
+    const int64_t groups = n * (wpad / 8);
+    const unsigned gb = static_cast<unsigned>((groups + 255) / 256);
+    if (iter_dt == CSC_F32)
+      hipLaunchKernelGGL(k_init8<float>, dim3(gb), dim3(256), 0, s, X, int(x_dt), ldx, n, w, wpad,
+                         wt, static_cast<float*>(z0), acc, a0, static_cast<float*>(nullptr));
+    else
+      hipLaunchKernelGGL(k_init8<uint16_t>, dim3(gb), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
+                         wpad, wt, static_cast<uint16_t*>(z0), acc, a0,
+                         iter_dt == CSC_BF16S ? s0 : static_cast<float*>(nullptr));
+    return;
+  }
   const int64_t total = n * wpad;
   const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
   if (iter_dt == CSC_F32)
@@ -1070,6 +1143,7 @@ struct CombineParams {
   const void* P;       // optional: <P, Y> partials
   int p_dt;
   int64_t ldp;
+  int vec;             // Y (and P) in whole 16-byte pieces per lane: vector stores and loads
   double* part;        // per block
   double coef[kMaxCombine];
 };
@@ -1097,25 +1171,105 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineParams p) {
     const int tile = col0 / p.wt, c = col0 - tile * p.wt;
     const TZ* z = static_cast<const TZ*>(p.basis) + static_cast<int64_t>(tile) * p.n * p.wt +
                   row * p.wt + c;
+    // the lane's probe values, read ahead of the slot loop on the vector path (F32 or BF16
+    // pieces, 4 or 8 values each)
+    constexpr int PW = VEC / 4;
+    uint4 praw[PW];
+    const bool vp = p.vec && p.P && col0 < p.w;
+    if (vp) {
+      const char* pb = static_cast<const char*>(p.P) +
+                       (row * p.ldp + col0) * static_cast<int64_t>(p.p_dt == CSC_BF16 ? 2 : 4);
+#pragma unroll
+      for (int w = 0; w < PW; ++w)
+        praw[w] = (p.p_dt == CSC_BF16 && w > 0) ? praw[0] : ld16(pb + 16 * w);
+    }
     double y[VEC];
 #pragma unroll
     for (int i = 0; i < VEC; ++i) y[i] = 0.0;
-    for (int j = 0; j <= p.m; ++j) {
+    // eight slots' loads in flight, then their terms in slot order
+    constexpr int JU = 8;
+    int j = 0;
+    for (; j + JU <= p.m + 1; j += JU) {
+      uint4 g[JU];
+#pragma unroll
+      for (int u = 0; u < JU; ++u) g[u] = ld16(z + static_cast<int64_t>(j + u) * p.slot);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < JU; ++u) {
+        float f[VEC];
+        Pack<TZ>::unpack(g[u], f);
+        const double a = p.coef[j + u];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) y[i] = fma(a, static_cast<double>(f[i]), y[i]);
+      }
+    }
+    for (; j <= p.m; ++j) {
       float f[VEC];
       Pack<TZ>::unpack(ld16(z + static_cast<int64_t>(j) * p.slot), f);
       const double a = p.coef[j];
 #pragma unroll
       for (int i = 0; i < VEC; ++i) y[i] = fma(a, static_cast<double>(f[i]), y[i]);
     }
+    if (p.vec) {
+      if (col0 < p.w) {
+        float y32[VEC], yv[VEC];
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-      const int col = col0 + i;
-      if (col < p.w) {
-        const float y32 = static_cast<float>(y[i]);
-        float yv = y32;
-        if (p.y_dt == CSC_BF16) yv = bf16_to_f32(f32_to_bf16(yv));
-        store_out(p.Y, p.y_dt, row * p.ldy + col, y32);
-        if (p.P) dot += static_cast<double>(load_any(p.P, p.p_dt, row * p.ldp + col)) * static_cast<double>(yv);
+        for (int i = 0; i < VEC; ++i) y32[i] = static_cast<float>(y[i]);
+        char* yb = static_cast<char*>(p.Y) + (row * p.ldy + col0) *
+                                               static_cast<int64_t>(p.y_dt == CSC_BF16 ? 2 : 4);
+        if (p.y_dt == CSC_BF16) {
+#pragma unroll
+          for (int i0 = 0; i0 < VEC; i0 += 8) {
+            uint32_t wd[4];
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+              const uint16_t lo = f32_to_bf16(y32[i0 + 2 * k2]), hi = f32_to_bf16(y32[i0 + 2 * k2 + 1]);
+              yv[i0 + 2 * k2] = bf16_to_f32(lo);
+              yv[i0 + 2 * k2 + 1] = bf16_to_f32(hi);
+              wd[k2] = static_cast<uint32_t>(lo) | (static_cast<uint32_t>(hi) << 16);
+            }
+            st16(yb + 2 * i0, make_uint4(wd[0], wd[1], wd[2], wd[3]));
+          }
+        } else {
+#pragma unroll
+          for (int i0 = 0; i0 < VEC; i0 += 4) {
+            st16(yb + 4 * i0, make_uint4(__float_as_uint(y32[i0]), __float_as_uint(y32[i0 + 1]),
+                                         __float_as_uint(y32[i0 + 2]), __float_as_uint(y32[i0 + 3])));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) yv[i0 + i] = y32[i0 + i];
+          }
+        }
+        if (vp) {
+          float pv[VEC];
+          if (p.p_dt == CSC_BF16) {
+            // eight BF16 values per piece (VEC = 8 here: BF16 probes go with BF16 copies)
+            const uint32_t wd[4] = {praw[0].x, praw[0].y, praw[0].z, praw[0].w};
+#pragma unroll
+            for (int i = 0; i < VEC; ++i)
+              pv[i] = i < 8 ? __uint_as_float(i & 1 ? wd[(i >> 1) & 3] & 0xffff0000u : wd[(i >> 1) & 3] << 16)
+                            : 0.f;
+          } else {
+#pragma unroll
+            for (int w = 0; w < PW; ++w) {
+              pv[4 * w] = __uint_as_float(praw[w].x); pv[4 * w + 1] = __uint_as_float(praw[w].y);
+              pv[4 * w + 2] = __uint_as_float(praw[w].z); pv[4 * w + 3] = __uint_as_float(praw[w].w);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) dot += static_cast<double>(pv[i]) * static_cast<double>(yv[i]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        const int col = col0 + i;
+        if (col < p.w) {
+          const float y32 = static_cast<float>(y[i]);
+          float yv = y32;
+          if (p.y_dt == CSC_BF16) yv = bf16_to_f32(f32_to_bf16(yv));
+          store_out(p.Y, p.y_dt, row * p.ldy + col, y32);
+          if (p.P) dot += static_cast<double>(load_any(p.P, p.p_dt, row * p.ldp + col)) * static_cast<double>(yv);
+        }
       }
     }
   }
@@ -1265,6 +1419,14 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
   p.p_dt = int(p_dt);
   p.ldp = ldp;
   p.part = dot ? static_cast<double*>(aux) : nullptr;
+  // vector epilogue: whole pieces per lane (w a multiple of VEC), 16-byte aligned rows, and
+  // element types whose pieces match the lane's VEC values (BF16 only with eight per lane)
+  auto rows16 = [](const void* b, int64_t ld, csc_dtype dt) {
+    return reinterpret_cast<uintptr_t>(b) % 16 == 0 && (ld * static_cast<int64_t>(dtype_size(dt))) % 16 == 0;
+  };
+  auto type_ok = [&](csc_dtype dt) { return dt == CSC_F32 || (dt == CSC_BF16 && VEC == 8); };
+  p.vec = (w % VEC == 0 && type_ok(y_dt) && rows16(Y, ldy, y_dt) &&
+           (!p.P || (type_ok(p_dt) && rows16(P, ldp, p_dt)))) ? 1 : 0;
   for (int j = 0; j <= m; ++j) p.coef[j] = a[j];
   if (iter_dt == CSC_F32)
     hipLaunchKernelGGL(k_combine<float>, dim3(blocks), dim3(kThreads), 0, s, p);
