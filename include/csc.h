@@ -213,14 +213,18 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  * csc_kmeans_assign: labels[i] = argmin_c sum_t (F[i, t] - C[c, t])^2 for the n rows of
  * F (device, type f_dt, leading dimension ldf, d columns) and the k centroids C (device
  * float[k * d], row-major).  For d <= 256 and 16-byte aligned rows the scores
- * ||C_c||^2 - 2 F_i.C_c are formed on the matrix cores from exact BF16 splits of F and C
- * (FP32 accumulation, error bounded by (6d + 2) 2^-24 ||F_i|| ||C_c||); a row whose best two
- * scores are not separated by twice that bound is re-scored against every centroid in the
- * FP64 direct form.  Otherwise candidates are ranked in FP32 and the two best re-scored in
- * FP64.  Exact ties go to the lowest index.  labels: device int32[n]; best_d2: device
- * float[n] (the FP64 squared distance to the chosen centroid, rounded) or NULL.  Uses a
- * library-owned device buffer for the split centroids, grown on demand, so concurrent calls
- * race.  Asynchronous.
+ * ||C_c||^2 - 2 F_i.C_c are formed on the matrix cores from exact BF16 splits of C (three
+ * parts) and of FP32 rows (three parts; BF16 rows are exact): each 32-column step's leading
+ * product goes to a fresh FP32 accumulator that is added in FP64, and the small cross
+ * products to an FP32 sum, so each score is within 2 * 40 * 2^-24 ||F_i|| ||C_c|| (plus FP64
+ * rounding) of its exact value.  A row with one centroid whose interval can hold the
+ * minimum is decided; with two, both are re-scored in the FP64 direct form; with more, every
+ * centroid is.  Otherwise (d > 256 or unaligned rows) candidates are ranked in FP32 and the
+ * two best re-scored in FP64.  Exact ties go to the lowest index.  labels: device
+ * int32[n]; best_d2: device float[n] (the FP64 squared distance to the chosen centroid,
+ * rounded) or NULL.  The split centroids live in a library-owned buffer of the current
+ * device, grown on demand (the growth allocates, and waits for the device), so concurrent
+ * calls on one device race.  Asynchronous.
  *
  * csc_kmeans_update: C[c] = mean of the rows labelled c; an empty cluster keeps its
  * previous centroid (C is read and overwritten); rows whose label is outside [0, k) are
@@ -397,10 +401,12 @@ csc_status csc_cheb_filter_backward(csc_graph g, double lmax, int m, const doubl
                                     void* stream);
 
 /* ---------------------------------------------------------------------------------
- * Measurement.  When enabled, csc_cheb_filter / csc_cheb_moments record a pair of HIP
- * events on their stream around their sequence of recurrence-step kernels, and
- * csc_timing_read sums, over the calls since the last reset, the elapsed time, the number
- * of step kernels and their algorithmic bytes (synchronising on the recorded events).
+ * Measurement.  When enabled, csc_cheb_filter / csc_cheb_moments and the recurrences of the
+ * dynamic calls record a pair of HIP events on their stream around their sequence of
+ * recurrence-step kernels, and csc_timing_read sums, over the calls since the last reset,
+ * the elapsed time, the number of step kernels and their algorithmic bytes (synchronising
+ * on the recorded events).  The measurement state is one per process, not per thread or
+ * device: enable, read and reset it from one thread while no other thread issues calls.
  */
 csc_status csc_timing_enable(int on);
 csc_status csc_timing_reset(void);

@@ -2,9 +2,10 @@
 // Lloyd update and k-means++ seeding.
 //
 // Assignment (d <= 256, aligned rows): the cross term on the BF16 matrix cores in exact
-// split precision with a certified error bound; rows the bound cannot separate are
-// re-scored in FP64 against every centroid.  Fallback (wider rows): one lane per row,
-// scalar-broadcast centroids, FP32 direct-form ranking and FP64 re-score of the best two.
+// split precision with a certified error bound; a row whose certified candidates are two
+// is re-scored in FP64 against both, a row with more against every centroid.  Fallback
+// (wider or unaligned rows): one lane per row, scalar-broadcast centroids, FP32 direct-form
+// ranking and FP64 re-score of the best two.
 //
 // Update: sums of the rows of each cluster in 64-bit fixed point (scale 2^S chosen from
 // max |F| and n so that no sum can overflow), accumulated with integer atomics in LDS and
@@ -12,10 +13,11 @@
 // the order of the atomics and the update is bit-reproducible; the quantisation step
 // 2^-S is far below FP32 resolution.
 //
-// k-means++: FP64 squared distances to the newest centre (one lane per row), block sums over
-// contiguous row ranges, and a one-block pick of the first row whose running sum exceeds
-// u_j * total.
+// k-means++: FP64 squared distances to the newest centre (sixteen lanes per row, rows the
+// triangle inequality rules out are not read), block sums over contiguous row ranges, and a
+// one-block pick of the first row whose running sum exceeds u_j * total.
 #include <cmath>
+#include <mutex>
 
 #include "csc_internal.h"
 
@@ -1342,24 +1344,42 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   return CSC_OK;
 }
 
+namespace {
+// scratch of the workspace-free assignment call, one per device
+constexpr int kMaxDevices = 64;
+struct CpBuf {
+  float* p = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_cp_mutex;
+CpBuf g_cp[kMaxDevices];
+}  // namespace
+
 csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                                 const float* C, int k, int32_t* labels, float* best_d2,
                                 double* obj_part, hipStream_t s) {
   CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
   if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
-  // the ABI call has no workspace: the padded centroids live in a small per-device buffer
-  // owned by the library (grown on demand, kept until exit)
-  static float* cp_buf = nullptr;
-  static size_t cp_bytes = 0;
+  // the ABI call has no workspace: the padded centroids live in a small buffer per device
+  // (the current one), owned by the library, grown on demand and kept until exit
+  int dev = 0;
+  CSC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CSC_E_ARG, "device index out of range");
   const size_t need = assign_scratch_bytes(k, d);
-  if (need > cp_bytes) {
-    if (cp_buf) (void)hipFree(cp_buf);
-    cp_buf = nullptr;
-    cp_bytes = 0;
-    CSC_HIP(hipMalloc(&cp_buf, need));
-    cp_bytes = need;
+  float* buf = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_cp_mutex);
+    CpBuf& b = g_cp[dev];
+    if (need > b.bytes) {
+      if (b.p) (void)hipFree(b.p);  // waits for the device's work that may still use it
+      b.p = nullptr;
+      b.bytes = 0;
+      CSC_HIP(hipMalloc(&b.p, need));
+      b.bytes = need;
+    }
+    buf = b.p;
   }
-  return assign_impl(F, f_dt, ldf, n, d, C, k, labels, best_d2, obj_part, cp_buf, s);
+  return assign_impl(F, f_dt, ldf, n, d, C, k, labels, best_d2, obj_part, buf, s);
 }
 
 csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
