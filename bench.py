@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--p", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16io,bf16,bf16s,bf16sb",
+    ap.add_argument("--forms", default="fp32,bf16io,bf16,bf16s,bf16b,bf16sb",
                     help="comma list of " + ", ".join(f"{k}: {v[5]}" for k, v in FORMS.items()))
     ap.add_argument("--headline", default="bf16sb")
     ap.add_argument("--init", choices=["pp", "warm"], default="pp",
