@@ -33,15 +33,17 @@ def c3_seq():
     return seq
 
 
-@pytest.mark.parametrize("form,lam", [("fp32", 0.5), ("bf16sb", 0.5), ("fp32", 0.4), ("bf16sb", 0.4)])
+@pytest.mark.parametrize("form,lam", [("fp32", 0.5), ("bf16sb", 0.5), ("bf16b", 0.5),
+                                      ("fp32", 0.4), ("bf16sb", 0.4), ("bf16b", 0.4)])
 def test_c3_batched_fresh_blocks_match_oracle(csc, c3_seq, form, lam):
     n, d, k, m, p, seed = 1_000_000, 128, 50, 120, 0.5, seed_for(3, "signals")
     feat = torch.float32 if form == "fp32" else torch.bfloat16
-    iters = torch.float32 if form == "fp32" else "bf16s"
+    iters = {"fp32": torch.float32, "bf16sb": "bf16s", "bf16b": torch.bfloat16}[form]
     say(f"C3 full size, form {form}, cut-off {lam}")
     # the benchmark's launch configuration of each form: FP32 one snapshot at a time with the
-    # kept basis, bf16sb four snapshots per batched launch replayed from a HIP graph
-    batched = form == "bf16sb"
+    # kept basis; bf16sb (BF16 copies, FP32 state) and bf16b (BF16 iterates) four snapshots
+    # per batched launch replayed from a HIP graph
+    batched = form != "fp32"
     st = csc.DynamicCSC(n, d, k, p, m, seed=seed, feat_dtype=feat, iter_dtype=iters, tau=1e9,
                         keep_iterates=1, batch=4 if batched else 1, use_graph=batched,
                         lloyd_iters=2)
@@ -58,7 +60,7 @@ def test_c3_batched_fresh_blocks_match_oracle(csc, c3_seq, form, lam):
     # snapshot 5 wrote columns 64..127 (the ring: 0..63, 64..127, 0..63, 64..127)
     cols = [0, 21, 42, 63]
     R = philox.gaussian_block(n, 64, 1 / np.sqrt(d), seed, 16 * 5 + SIGNALS,
-                              dtype="bf16" if form == "bf16sb" else np.float32)
+                              dtype="bf16" if form != "fp32" else np.float32)
     A, _ = operator.normalized_adjacency(n, c3_seq[4].rowptr, c3_seq[4].colidx, c3_seq[4].w)
     a = chebyshev.step_coefficients(m, 2.0, lam, "jackson")
     rows = np.sort(np.random.default_rng(7).choice(n, 10_000, replace=False))
@@ -80,10 +82,11 @@ def test_c3_batched_fresh_blocks_match_oracle(csc, c3_seq, form, lam):
         else:
             assert abs_err <= 1e-7 * r_norm
     else:
-        # BF16 rounds every gathered copy (2^-9 relative) of iterates whose norm stays near |R|;
-        # the stable recurrence and |h| <= 1 keep the resulting error below 2^-9 |R| whatever the
-        # cut-off, so the bound is stated relative to the input (relative to the output it grows
-        # as the filter's gain falls: 0.09 at cut-off 0.5, 0.002 at 0.4)
+        # BF16 rounds every gathered copy (2^-9 relative) of iterates whose norm stays near |R|
+        # (bf16b also rounds the stored iterates themselves); the stable recurrence and |h| <= 1
+        # keep the resulting error below 2^-9 |R| whatever the cut-off, so the bound is stated
+        # relative to the input (relative to the output it grows as the filter's gain falls:
+        # 0.09 at cut-off 0.5, 0.002 at 0.4)
         assert abs_err <= 2.0 ** -9 * r_norm
 
 
