@@ -1260,6 +1260,11 @@ MfPlan mf_plan(int64_t n, int d, int k, bool bf16_rows = false) {
   P.kp = kp;
   P.kc = kc;
   P.T = (bf16_rows && kc < kp) ? 2 : 1;
+  // the two-tile kernel runs one 8-wave block per CU, so its chunks may fill the CU's whole
+  // LDS (160 KiB on gfx950): fewer chunks, fewer restaging rounds per panel
+  if (P.T == 2)
+    while (kc + 16 <= kp && mf_lds_bytes(DP, kc + 16) <= 160 * 1024) kc += 16;
+  P.kc = kc;
   P.wv = P.T == 2 ? 8 : 4;
   P.lds = mf_lds_bytes(DP, kc);
   const int64_t panels = (n + 16 * P.wv * P.T - 1) / (16 * P.wv * P.T);
