@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <tuple>
 #include <cmath>
 #include <string>
@@ -220,7 +221,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     free_dyn(st);
     return fail(CSC_E_HIP, "cannot create the capture stream");
   }
-  if (st->nbuf == 2) {
+  if (st->nbuf == 2 || (st->basis && st->batch == 1)) {
     // non-blocking: callers often work on the null stream, which would otherwise serialise
     // with it; the order between the two streams comes only from the events below
     bool ev_ok = hipStreamCreateWithFlags(&st->fs, hipStreamNonBlocking) == hipSuccess &&
@@ -381,7 +382,8 @@ csc_status static_pass(csc_dyn st, const Graph* g, double lm, int t, double* cnt
 // live in slot `slot`; with pre_basis the signals are drawn and the iterates computed already
 // (batched recurrence).
 csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32_t* labels,
-                     double* lambda_t, int* refined, double* count, hipStream_t s) {
+                     double* lambda_t, int* refined, double* count, hipStream_t s,
+                     const std::function<csc_status()>& before_kmeans = {}) {
   const int t = ++st->t;
   const double sigma = 1.0 / std::sqrt(static_cast<double>(st->d));
   const double sigma2 = sigma * sigma;
@@ -502,6 +504,10 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
     st->hist[3 * (t - 1) + 2] = refresh ? 1.0 : 0.0;
   }
 
+  // the kept iterates and signals of this snapshot are no longer needed: a caller may start
+  // the next snapshot's recurrence here, beside the k-means
+  if (before_kmeans) CSC_TRY(before_kmeans());
+
   // Step 8: k-means on Theta_t.
   int init = 0;
   if (st->init == 1 && t > 1) {
@@ -563,8 +569,12 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
   const int t0 = st->t;  // snapshot i has index t0 + 1 + (i - i0)
   const int nbatch = (S - i0 + st->batch - 1) / st->batch;
   const bool pipe = st->nbuf == 2;
-  hipStream_t fs = pipe ? st->fs : s;
-  if (pipe) {
+  // one buffer of kept iterates, one snapshot per batch: the next snapshot's recurrence starts
+  // on the state's stream as soon as this snapshot's recombination and refinement are done,
+  // and runs beside its k-means
+  const bool early = !pipe && st->batch == 1 && st->fs != nullptr;
+  hipStream_t fs = (pipe || early) ? st->fs : s;
+  if (pipe || early) {
     // the recurrence stream sees everything the caller enqueued before (graph updates)
     CSC_HIP(hipEventRecord(st->ev_start, s));
     CSC_HIP(hipStreamWaitEvent(fs, st->ev_start, 0));
@@ -580,7 +590,7 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
       CSC_TRY(draw_signals(st, t0 + 1 + (j - i0) + q, buf * st->batch + q, fs));
     }
     CSC_TRY(batch_basis(st, gs, nb, fs, buf));
-    if (pipe) CSC_HIP(hipEventRecord(st->ev_basis[buf], fs));
+    if (pipe || early) CSC_HIP(hipEventRecord(st->ev_basis[buf], fs));
     return CSC_OK;
   };
   CSC_TRY(issue(0));
@@ -589,13 +599,22 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
     const int j = i0 + b * st->batch;
     const int nb = std::min(st->batch, S - j);
     const int buf = pipe ? (b & 1) : 0;
-    if (pipe) CSC_HIP(hipStreamWaitEvent(s, st->ev_basis[buf], 0));
+    if (pipe || early) CSC_HIP(hipStreamWaitEvent(s, st->ev_basis[buf], 0));
+    // early: before this snapshot's k-means, the next recurrence waits for the work enqueued
+    // so far on the caller's stream (recombination, refinement) and is then issued
+    const std::function<csc_status()> next = [&]() -> csc_status {
+      CSC_HIP(hipEventRecord(st->ev_free[0], s));
+      CSC_HIP(hipStreamWaitEvent(fs, st->ev_free[0], 0));
+      return issue(b + 1);
+    };
+    const bool hand_over = early && b + 1 < nbatch;
     for (int q = 0; q < nb; ++q) {
       auto [l, r, c] = out(j + q);
-      CSC_TRY(step_impl(st, &graphs[j + q]->g, buf * st->batch + q, true, labels[j + q], l, r, c, s));
+      CSC_TRY(step_impl(st, &graphs[j + q]->g, buf * st->batch + q, true, labels[j + q], l, r, c, s,
+                        hand_over ? next : std::function<csc_status()>()));
     }
     if (pipe) CSC_HIP(hipEventRecord(st->ev_free[buf], s));
-    if (!pipe && b + 1 < nbatch) CSC_TRY(issue(b + 1));
+    if (!pipe && !early && b + 1 < nbatch) CSC_TRY(issue(b + 1));
   }
   return CSC_OK;
 }
