@@ -139,7 +139,11 @@ def test_lmax_estimate_is_upper_bound(csc):
     assert lam[-1] * 0.999 <= est <= 2.0
 
 
+# batch 1 with kept iterates: the sequence call starts each next recurrence beside the
+# current k-means (one buffer), which must not change any result
 @pytest.mark.parametrize("batch,use_graph,iters,p,d", [(1, True, torch.float32, 0.5, 32),
+                                                       (1, False, "bf16s", 0.5, 32),
+                                                       (1, False, torch.float32, 0.3, 40),
                                                        (3, False, torch.float32, 0.5, 32),
                                                        (4, True, torch.float32, 0.5, 32),
                                                        (4, True, "bf16s", 0.5, 32),
