@@ -593,30 +593,36 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
     if (pipe || early) CSC_HIP(hipEventRecord(st->ev_basis[buf], fs));
     return CSC_OK;
   };
-  CSC_TRY(issue(0));
-  for (int b = 0; b < nbatch; ++b) {
-    if (pipe && b + 1 < nbatch) CSC_TRY(issue(b + 1));
-    const int j = i0 + b * st->batch;
-    const int nb = std::min(st->batch, S - j);
-    const int buf = pipe ? (b & 1) : 0;
-    if (pipe || early) CSC_HIP(hipStreamWaitEvent(s, st->ev_basis[buf], 0));
-    // early: before this snapshot's k-means, the next recurrence waits for the work enqueued
-    // so far on the caller's stream (recombination, refinement) and is then issued
-    const std::function<csc_status()> next = [&]() -> csc_status {
-      CSC_HIP(hipEventRecord(st->ev_free[0], s));
-      CSC_HIP(hipStreamWaitEvent(fs, st->ev_free[0], 0));
-      return issue(b + 1);
-    };
-    const bool hand_over = early && b + 1 < nbatch;
-    for (int q = 0; q < nb; ++q) {
-      auto [l, r, c] = out(j + q);
-      CSC_TRY(step_impl(st, &graphs[j + q]->g, buf * st->batch + q, true, labels[j + q], l, r, c, s,
-                        hand_over ? next : std::function<csc_status()>()));
+  // on a failure, work already issued on the recurrence stream is drained before returning,
+  // so that no later call races with it
+  const csc_status rc = [&]() -> csc_status {
+    CSC_TRY(issue(0));
+    for (int b = 0; b < nbatch; ++b) {
+      if (pipe && b + 1 < nbatch) CSC_TRY(issue(b + 1));
+      const int j = i0 + b * st->batch;
+      const int nb = std::min(st->batch, S - j);
+      const int buf = pipe ? (b & 1) : 0;
+      if (pipe || early) CSC_HIP(hipStreamWaitEvent(s, st->ev_basis[buf], 0));
+      // early: before this snapshot's k-means, the next recurrence waits for the work enqueued
+      // so far on the caller's stream (recombination, refinement) and is then issued
+      const std::function<csc_status()> next = [&]() -> csc_status {
+        CSC_HIP(hipEventRecord(st->ev_free[0], s));
+        CSC_HIP(hipStreamWaitEvent(fs, st->ev_free[0], 0));
+        return issue(b + 1);
+      };
+      const bool hand_over = early && b + 1 < nbatch;
+      for (int q = 0; q < nb; ++q) {
+        auto [l, r, c] = out(j + q);
+        CSC_TRY(step_impl(st, &graphs[j + q]->g, buf * st->batch + q, true, labels[j + q], l, r,
+                          c, s, hand_over ? next : std::function<csc_status()>()));
+      }
+      if (pipe) CSC_HIP(hipEventRecord(st->ev_free[buf], s));
+      if (!pipe && !early && b + 1 < nbatch) CSC_TRY(issue(b + 1));
     }
-    if (pipe) CSC_HIP(hipEventRecord(st->ev_free[buf], s));
-    if (!pipe && !early && b + 1 < nbatch) CSC_TRY(issue(b + 1));
-  }
-  return CSC_OK;
+    return CSC_OK;
+  }();
+  if (rc != CSC_OK && fs != s) (void)hipStreamSynchronize(fs);
+  return rc;
 }
 
 csc_status dyn_features(csc_dyn st, const void** theta, csc_dtype* dt, int64_t* ld,
