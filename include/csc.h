@@ -343,9 +343,13 @@ csc_status csc_dynamic_step(csc_dyn st, csc_graph g_t, int32_t* labels, double* 
 /* S snapshots in order (Algorithm 1 steps 4-8 for each): the fresh signals of up to
  * opts->batch snapshots are filtered in one batched recurrence (their graphs must share n
  * and the value type), then each snapshot's eigencount check, refinement, ring update and
- * k-means run in order, so the results equal S calls to csc_dynamic_step.  labels[i]:
- * device int32[n] per snapshot; lambdas, refined, counts: host arrays of S or NULL.
- * Synchronising. */
+ * k-means run in order, so the results equal S calls to csc_dynamic_step.  The state's own
+ * non-blocking stream runs the recurrences and events order it against `stream`: with two
+ * buffers of kept iterates the next batch's recurrence runs beside the current batch's
+ * k-means, and with one buffer and batch 1 the next snapshot's recurrence starts once the
+ * current snapshot's recombination and refinement are enqueued.  labels[i]: device int32[n]
+ * per snapshot; lambdas, refined, counts: host arrays of S or NULL.  Synchronising: on return
+ * (also on an error) no work of the call is left on either stream. */
 csc_status csc_dynamic_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
                              double* lambdas, int* refined, double* counts, void* stream);
 /* Similarity record of snapshot t (1-based, already processed): the edge distance and the
