@@ -348,8 +348,8 @@ csc_status csc_dynamic_step(csc_dyn st, csc_graph g_t, int32_t* labels, double* 
  * buffers of kept iterates the next batch's recurrence runs beside the current batch's
  * k-means, and with one buffer and batch 1 the next snapshot's recurrence starts once the
  * current snapshot's recombination and refinement are enqueued.  labels[i]: device int32[n]
- * per snapshot; lambdas, refined, counts: host arrays of S or NULL.  Synchronising: on return
- * (also on an error) no work of the call is left on either stream. */
+ * per snapshot; lambdas, refined, counts: host arrays of S or NULL.  Synchronising; after
+ * an error the state's stream is drained before the call returns. */
 csc_status csc_dynamic_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const* labels,
                              double* lambdas, int* refined, double* counts, void* stream);
 /* Similarity record of snapshot t (1-based, already processed): the edge distance and the
