@@ -1,0 +1,77 @@
+"""Static CSC through the C ABI against SC (Thm 3.1, Lemma 3.1, Thm 3.2 of Sec. 3.1) on C1.
+
+C1: SBM N = 1000, k = 5 equal blocks, degree 16, ratio 0.1; m = 50; the cut-off midway
+between lambda_5 and lambda_6 of a dense eigendecomposition (or found by the eigencount
+dichotomy on the signals themselves); k-means++ and 20 Lloyd rounds on the GPU features.
+d = 32 is C1's own width, where Thm 3.1's bound exceeds sqrt(k) and says nothing (reported
+as vacuous); d = 256 is where it is informative.  The checks and the wrong assignments that
+must fail them are described in tests/quality.py.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import quality as Q
+from oracle import eigcount, kmeans
+from helpers import say
+
+pytestmark = pytest.mark.gpu
+
+FORMS = {  # features, iterates, operator values
+    "fp32": (torch.float32, torch.float32, torch.float32),
+    "bf16io": (torch.bfloat16, torch.float32, torch.bfloat16),
+    "bf16s": (torch.bfloat16, "bf16s", torch.bfloat16),
+    "bf16": (torch.bfloat16, torch.bfloat16, torch.bfloat16),
+}
+
+
+@pytest.fixture(scope="module")
+def c1():
+    g = Q.c1_graph()
+    A, lam, U, c_phi = Q.sc_reference(g)
+    return g, A, lam, U, c_phi
+
+
+@pytest.mark.parametrize("d", [32, 256])
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("cut", ["eigh", "eigcount"])
+def test_static_csc_quality(csc, c1, form, d, cut):
+    if cut == "eigcount" and form not in ("fp32", "bf16s"):
+        pytest.skip("the dichotomy is covered by the FP32 and BF16S forms")
+    g, A, lam, U, c_phi = c1
+    feat, iters, vals = FORMS[form]
+    store = "f32" if feat == torch.float32 else "bf16"
+    say(f"static CSC quality: form {form}, d={d}, cut-off from {cut}")
+    G = csc.Graph.from_workload(g, val_dtype=vals)
+    R = csc.randn(g.n, d, Q.seed_for(1, "signals"), 1, sigma=1 / np.sqrt(d), dtype=feat)
+    Rn = Q.signals(g.n, d, store)
+    assert np.array_equal(R.double().cpu().numpy(), Rn)
+    if cut == "eigh":
+        lam_c = 0.5 * (lam[Q.K - 1] + lam[Q.K])
+    else:
+        lam_c, cnt, _, _ = csc.eigcount(G, Q.M, R, sigma2=1.0 / d, k=Q.K, n_cand=16, iter_dtype=iters)
+        mu = eigcount.moments_direct(A, 2.0, Q.M, Rn)
+        lam_o, cnt_o, _ = eigcount.eigcount_bisect(mu, Q.M, 2.0, "jackson", 1.0 / d, d, Q.K, 16, 0.0, 2.0)
+        say(f"  dichotomy: GPU {lam_c:.6f} (count {cnt:.3f}), oracle {lam_o:.6f} (count {cnt_o:.3f})")
+        assert abs(lam_c - lam_o) <= 2.0 ** -15
+    a = csc.cheb_coeffs(Q.M, 2.0, lam_c)
+    Y = csc.cheb_filter(G, a, R, out_dtype=feat, iter_dtype=iters)
+    labels, _ = csc.kmeans(Y, Q.K, iters=20, seed=Q.seed_for(1, "kmeans"), stream_id=2)
+    lab = labels.cpu().numpy()
+    F = Y.double().cpu().numpy()
+    _, lab_o = Q.oracle_csc(A, lam_c, Rn)
+    Phi = U[:, :Q.K]
+    c_o = kmeans.cost(Phi, lab_o)
+    thm, chain = Q.bounds(U, c_phi, Rn, F)
+    ok, c = Q.quality_ok(Phi, lab, thm, chain, c_o)
+    vac = " (vacuous: >= sqrt(k))" if thm >= np.sqrt(Q.K) else ""
+    say(f"  C_Psi {c:.4f}; C_Phi {c_phi:.4f}; oracle CSC {c_o:.4f}; Thm 3.1 bound {thm:.4f}{vac}; "
+        f"Lemma 3.1 chain {chain:.4f}")
+    assert ok
+    if d == 256:
+        assert thm < np.sqrt(Q.K)  # the informative case
+    for name, bad in Q.corruptions(lab).items():
+        bad_ok, cb = Q.quality_ok(Phi, bad, thm, chain, c_o)
+        say(f"  wrong assignment {name}: cost {cb:.4f} -> rejected {not bad_ok}")
+        assert not bad_ok

@@ -95,3 +95,22 @@ def test_cor41_projector_perturbation_bound():
     assert alpha > 0
     dL = (operator.laplacian(A1) - operator.laplacian(A0)).toarray()
     assert np.linalg.norm(H1 - H0) <= np.sqrt(2) / alpha * np.linalg.norm(dL)
+
+
+@pytest.mark.parametrize("d", [32, 256])
+def test_quality_checks_accept_csc_and_reject_wrong_assignments(d):
+    # the checks of tests/quality.py on the oracle's own static CSC: its assignment passes,
+    # random labels, two merged clusters and half a cluster moved do not
+    import quality as Q
+    g = Q.c1_graph()
+    A, lam, U, c_phi = Q.sc_reference(g)
+    R = Q.signals(g.n, d, "f32")
+    lam_c = 0.5 * (lam[Q.K - 1] + lam[Q.K])
+    Y, lab = Q.oracle_csc(A, lam_c, R)
+    Phi = U[:, :Q.K]
+    thm, chain = Q.bounds(U, c_phi, R, Y)
+    ok, c = Q.quality_ok(Phi, lab, thm, chain, kmeans.cost(Phi, lab))
+    assert ok
+    assert (thm < np.sqrt(Q.K)) == (d == 256)
+    for bad in Q.corruptions(lab).values():
+        assert not Q.quality_ok(Phi, bad, thm, chain, c)[0]
