@@ -92,15 +92,28 @@ FORMS = {
     "bf16sb": ("bfloat16", "bf16s", "bfloat16", True, True,
                "the bf16s form with the fresh blocks of --batch snapshots filtered in one "
                "batched recurrence replayed from a HIP graph"),
+    "f16": ("bfloat16", "float16", "bfloat16", False, False,
+            "BF16 signals, features and operator values; IEEE binary16 recurrence iterates; "
+            "FP32 arithmetic and accumulation"),
+    "f16b": ("bfloat16", "float16", "bfloat16", True, True,
+             "the f16 form with the fresh blocks of --batch snapshots filtered in one batched "
+             "recurrence replayed from a HIP graph"),
+    "f16s": ("bfloat16", "f16s", "bfloat16", False, False,
+             "BF16 signals, features and operator values; binary16 gathered iterate copies; the "
+             "recurrence state, arithmetic and accumulation FP32"),
+    "f16sb": ("bfloat16", "f16s", "bfloat16", True, True,
+              "the f16s form with the fresh blocks of --batch snapshots filtered in one batched "
+              "recurrence replayed from a HIP graph"),
 }
+SPLIT_MODES = ("bf16s", "f16s")
 
 
 def torch_types(form):
-    """(features, iterates, values) of a form; iterates may be the mode string "bf16s"."""
+    """(features, iterates, values) of a form; iterates may be a split-mode string."""
     import torch
 
     fdt, idt, vdt = FORMS[form][:3]
-    return getattr(torch, fdt), (idt if idt == "bf16s" else getattr(torch, idt)), getattr(torch, vdt)
+    return getattr(torch, fdt), (idt if idt in SPLIT_MODES else getattr(torch, idt)), getattr(torch, vdt)
 
 
 def kernel_digest() -> str:
@@ -303,6 +316,13 @@ def _time_form(args, form, p, resident, cap, cid):
     labels = labs[-1]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the last timed snapshot's fresh columns as the timed path wrote them into Theta: the
+    # ring's cursor starts at column 0 on snapshot 2 and advances by q d per snapshot
+    rows, cols = error_sample(args, qd)
+    c0 = ((T - 2) * qd) % args.d
+    idx = torch.tensor([(c0 + c) % args.d for c in cols], device=dev)
+    theta_sample = (dyn.features().index_select(0, torch.from_numpy(rows).to(dev))
+                    .index_select(1, idx).double().cpu().numpy())
     kms, launches, kbytes = csc.timing_read()
     csc.timing_enable(False)
     log(f"[bench] {form}: {wall / args.steps * 1e3:.2f} ms/snapshot, step kernels "
@@ -322,11 +342,91 @@ def _time_form(args, form, p, resident, cap, cid):
         hip_graph=graph,
         autotuned_variant=variant,
         G=G,
+        theta_sample=theta_sample,
     )
     del dyn
     if batched:
         del Gs
     return entry, labs
+
+
+def error_sample(args, qd):
+    """(rows, cols) of the error sample: 10k rows drawn with the probe seed, 4 fresh columns."""
+    import numpy as np
+
+    from workloads import seed_for
+
+    cid = 5 if args.workload == "c5" else 3
+    cols = [0, 21, 42, 63] if qd >= 64 else list(range(min(4, qd)))
+    rows = np.sort(np.random.default_rng(seed_for(cid, "probes")).choice(args.n, 10_000, replace=False))
+    return rows, cols
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def timed_path_errors(args, gl, T, cid, forms):
+    """Per form: the relative Frobenius error of the timed path's last fresh columns against
+    the FP64 oracle (the multi-core C filter of oracle/), and the CPU baseline: that oracle
+    filter timed on all host cores and on one."""
+    import numpy as np
+
+    from oracle import cfilter, chebyshev, operator, philox
+    from workloads import seed_for
+
+    qd = int(round((1 - args.p) * args.d))
+    rows, cols = error_sample(args, qd)
+    A, _ = operator.normalized_adjacency(gl.n, gl.rowptr, gl.colidx, gl.w)
+    sig = {}
+    for store in ("f32", "bf16"):
+        R = philox.gaussian_block(args.n, qd, 1.0 / np.sqrt(args.d), seed_for(cid, "signals"),
+                                  16 * T + 1, dtype="bf16" if store == "bf16" else np.float32)
+        sig[store] = np.asarray(R[:, cols], dtype=np.float64)
+    cache, errors, cpu = {}, {}, None
+    for form, rec in forms.items():
+        store = "bf16" if FORMS[form][0] == "bfloat16" else "f32"
+        lam = rec["lambda_last"]
+        key = (lam, store)
+        if key not in cache:
+            a = chebyshev.step_coefficients(args.m, 2.0, lam, "jackson")
+            log(f"[bench] oracle: FP64 filter of {len(cols)} columns of snapshot {T} at cut-off "
+                f"{lam:.6f} ({store} signals)")
+            t0 = time.perf_counter()
+            Y, used = cfilter.filter_recurrence_c(A, 2.0, a, sig[store])
+            t_all = time.perf_counter() - t0
+            cache[key] = Y[rows]
+            if cpu is None:
+                t0 = time.perf_counter()
+                cfilter.filter_recurrence_c(A, 2.0, a, sig[store], threads=1)
+                t_one = time.perf_counter() - t0
+                nnz = gl.nnz + gl.n  # L~ stores the diagonal too
+                alg = args.m * (nnz * 12.0 + 8.0 * (gl.n + 1) + gl.n * len(cols) * (3 * 8 + 2 * 8))
+                cpu = dict(value=round(alg / t_all / 1e9, 3), unit="GB/s", cores=used, kind="oracle",
+                           one_core_value=round(alg / t_one / 1e9, 3), cpu_model=cpu_model(),
+                           nproc=os.cpu_count(),
+                           sample=f"FP64 C/OpenMP three-term filter of the oracle, {len(cols)} of the "
+                                  f"{qd} fresh columns of snapshot {T} (N={gl.n}, nnz={gl.nnz}, "
+                                  f"m={args.m}): {t_all:.2f} s on {used} threads, {t_one:.2f} s on "
+                                  f"one; the {qd}-column filter of one snapshot extrapolates to "
+                                  f"{t_all * qd / len(cols):.1f} s on {used} threads",
+                           seconds=round(t_all, 3), seconds_one_core=round(t_one, 3))
+        ref = cache[key]
+        got = rec["theta_sample"]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        gain = float(np.linalg.norm(ref) / np.linalg.norm(sig[store][rows]))
+        errors[form] = dict(rel_fro_vs_fp64=err, cut_off=lam, snapshot=T,
+                            output_over_input=gain, signals=store)
+        log(f"[bench] {form}: timed-path error {err:.3e} of the output at cut-off {lam:.5f} "
+            f"(the filter keeps {gain:.4f} of the input)")
+    return errors, cpu
 
 
 def run_dynamic(args):
@@ -358,84 +458,13 @@ def run_dynamic(args):
         final_labels[form] = labs[-1].cpu().numpy()
         all_labels[form] = [x.cpu().numpy() for x in labs]
 
-    # error of each form's filter against the FP64 oracle on 10k sampled rows (4 columns),
-    # at a fixed cut-off on the last snapshot; the oracle run doubles as the CPU baseline
-    from oracle import chebyshev, operator
-    from workloads import gaussian_block
-
-    gl = seq[-1]
-    lam_c = 0.5
-    a = chebyshev.step_coefficients(args.m, 2.0, lam_c, "jackson")
-    qd = int(round((1 - args.p) * args.d))
-    X = gaussian_block(args.n, qd, 1.0 / np.sqrt(args.d), seed=seed_for(cid, "probes"))
-    cols = [0, 21, 42, 63] if qd >= 64 else list(range(min(4, qd)))
-    rows = np.sort(np.random.default_rng(seed_for(cid, "probes")).choice(args.n, 10_000, replace=False))
-    cpu = None
-    errors = {}
-    if not args.no_error or not args.no_cpu_baseline:
-        A, _ = operator.normalized_adjacency(gl.n, gl.rowptr, gl.colidx, gl.w)
-        log("[bench] oracle: FP64 filter of 4 columns on the last snapshot (CPU baseline)")
-        t0 = time.perf_counter()
-        ref = chebyshev.filter_recurrence(A, 2.0, a, X[:, cols].astype(np.float64))
-        t_cpu = time.perf_counter() - t0
-        nnz = gl.nnz
-        alg_bytes_cpu = args.m * (nnz * 12.0 + 8.0 * (gl.n + 1) + gl.n * len(cols) * (3 * 8 + 2 * 8))
-        cpu = dict(value=alg_bytes_cpu / t_cpu / 1e9, unit="GB/s", cores=1, kind="oracle",
-                   sample=f"FP64 NumPy/SciPy three-term filter, {len(cols)} of the {qd} fresh columns "
-                          f"of one snapshot (N={gl.n}, nnz={nnz}, m={args.m}), single thread, "
-                          f"{t_cpu:.1f} s; per-snapshot filter time extrapolated to {qd} columns: "
-                          f"{t_cpu * qd / len(cols) * 1e3:.0f} ms",
-                   seconds=t_cpu)
-        ref_rows = ref[rows]
-        ref_b = None
-        for form, rec in forms.items():
-            fdt, idt, vdt = FORMS[form][:3]
-            bf = vdt == "bfloat16"
-            Xt = torch.from_numpy(X).to(dev)
-            if bf:
-                Xt = Xt.to(torch.bfloat16)
-            iters = torch_types(form)[1]
-            G = rec["G"]
-            G.update_device(*resident[-1], validate=False)
-            Y = csc.cheb_filter(G, a, Xt, out_dtype=Xt.dtype, iter_dtype=iters).float().cpu().numpy()
-            got = Y[rows][:, cols].astype(np.float64)
-            e_total = float(np.linalg.norm(got - ref_rows) / np.linalg.norm(ref_rows))
-            rec_err = dict(rel_fro_vs_fp64=e_total)
-            if bf:
-                if ref_b is None:
-                    Xr = Xt.float().cpu().numpy()[:, cols].astype(np.float64)
-                    log("[bench] oracle: same 4 columns from BF16-rounded signals")
-                    ref_b = chebyshev.filter_recurrence(A, 2.0, a, Xr)[rows]
-                rec_err["rel_fro_vs_fp64_same_bf16_inputs"] = float(
-                    np.linalg.norm(got - ref_b) / np.linalg.norm(ref_b))
-            errors[form] = rec_err
-            log(f"[bench] {form}: error {rec_err}")
-        # the same at a cut-off near lambda_k of C3 (0.4), where the filtered block is ~0.2% of
-        # the input's norm and a fixed absolute rounding error is a far larger fraction of it
-        if args.workload == "c3" and not args.no_error:
-            lam_k = 0.4
-            a_k = chebyshev.step_coefficients(args.m, 2.0, lam_k, "jackson")
-            log(f"[bench] oracle: the 4 columns at cut-off {lam_k}")
-            ref_k = chebyshev.filter_recurrence(A, 2.0, a_k, X[:, cols].astype(np.float64))[rows]
-            ref_kb = None
-            for form, rec in forms.items():
-                bf = FORMS[form][2] == "bfloat16"
-                Xt = torch.from_numpy(X).to(dev)
-                if bf:
-                    Xt = Xt.to(torch.bfloat16)
-                    if ref_kb is None:
-                        Xr = Xt.float().cpu().numpy()[:, cols].astype(np.float64)
-                        ref_kb = chebyshev.filter_recurrence(A, 2.0, a_k, Xr)[rows]
-                Y = csc.cheb_filter(rec["G"], a_k, Xt, out_dtype=Xt.dtype,
-                                    iter_dtype=torch_types(form)[1]).float().cpu().numpy()
-                got = Y[rows][:, cols].astype(np.float64)
-                r = ref_kb if bf else ref_k
-                errors[form]["rel_fro_vs_fp64_at_0.4"] = float(np.linalg.norm(got - r) / np.linalg.norm(r))
-                errors[form]["abs_err_over_input_at_0.4"] = float(
-                    np.linalg.norm(got - r) / np.linalg.norm(X[rows][:, cols].astype(np.float64)))
-                log(f"[bench] {form}: at cut-off {lam_k}: {errors[form]['rel_fro_vs_fp64_at_0.4']:.3e} of the "
-                    f"output, {errors[form]['abs_err_over_input_at_0.4']:.3e} of the input")
-
+    # error of the timed path: the last timed snapshot's fresh columns (4 of them, 10k sampled
+    # rows) as each form wrote them into Theta, against the FP64 oracle's filter of the same
+    # Philox signals on the same snapshot at the cut-off that form's snapshot used; the
+    # oracle runs double as the CPU baseline
+    errors, cpu = {}, None
+    if not args.no_error:
+        errors, cpu = timed_path_errors(args, seq[-1], T, cid, forms)
     head = forms[args.headline]
     traffic = load_traffic(digest, args.headline, args.workload)
     achieved = head["step_kernel_gbps"]
@@ -474,7 +503,8 @@ def run_dynamic(args):
             "algorithmic_bytes_per_launch": round(head["bytes_per_launch"]),
             "avg_launch_us": round(head["step_kernel_us"], 2),
         },
-        "forms": {f: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items() if k != "G"}
+        "forms": {f: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
+                      if k not in ("G", "theta_sample")}
                   for f, r in forms.items()},
         "errors_vs_fp64_oracle": errors,
         "cpu_baseline": None if args.no_cpu_baseline else cpu,

@@ -50,10 +50,24 @@ typedef enum {
   CSC_E_STATE = 6   /* handle used out of order */
 } csc_status;
 
-/* CSC_BF16S is an iterate storage mode only (the iter_dt arguments): the Chebyshev iterates
- * are stored in BF16 for the neighbour gathers and the kept basis, while the three-term
- * recurrence itself is carried in FP32 (its state is never rounded to BF16). */
-typedef enum { CSC_F32 = 0, CSC_BF16 = 1, CSC_F64 = 2, CSC_BF16S = 3 } csc_dtype;
+/* Iterate storage modes (the iter_dt arguments only):
+ *  - CSC_F16: the Chebyshev iterates are stored in IEEE binary16 (11 significant bits
+ *    against BF16's 8, at the same two bytes).  The iterates of the filter satisfy
+ *    |Z_j[:, c]|_2 <= |X[:, c]|_2 (|T_j| <= 1 on the mapped spectrum), so every entry stays
+ *    inside binary16's range when every column of X has 2-norm below 2^15; the caller
+ *    guarantees that (signals of variance 1/d on n nodes have column norms sqrt(n / d)).
+ *    Entries below 2^-14 are stored as binary16 subnormals (absolute spacing 2^-24).
+ *  - CSC_BF16S / CSC_F16S: BF16 / binary16 copies of the iterates serve the neighbour
+ *    gathers and the kept basis, while the three-term recurrence itself is carried in FP32
+ *    (its state is never rounded). */
+typedef enum {
+  CSC_F32 = 0,
+  CSC_BF16 = 1,
+  CSC_F64 = 2,
+  CSC_BF16S = 3,
+  CSC_F16 = 4,
+  CSC_F16S = 5
+} csc_dtype;
 
 typedef enum { CSC_DAMP_NONE = 0, CSC_DAMP_JACKSON = 1 } csc_damping;
 
@@ -143,8 +157,10 @@ csc_status csc_cheb_coeffs(int m, double lmax, double lambda_c, csc_damping damp
  * X: device n x w block, type x_dt (F32/BF16/F64), leading dimension ldx.
  * Y: device n x w block, type y_dt (F32/BF16/F64), leading dimension ldy; must not
  *    overlap X.  a: host double[m + 1].  iter_dt: storage of the iterates Z_j: CSC_F32;
- *    CSC_BF16 (rounded to BF16 at every step, half the traffic); or CSC_BF16S (BF16 copies
- *    for the gathers, FP32 recurrence state).  Arithmetic is always FP32.
+ *    CSC_BF16 or CSC_F16 (rounded to BF16 / binary16 at every step, half the traffic;
+ *    binary16 keeps 3 more bits, within the range condition stated with csc_dtype); or
+ *    CSC_BF16S / CSC_F16S (BF16 / binary16 copies for the gathers, FP32 recurrence state).
+ *    Arithmetic is always FP32.
  * moments: NULL, or device double[m + 1] receiving mu_j = <X, T_j(L~) X> (summed over the
  *    w columns) for j = 0..m, obtained during the same pass from the doubling identities
  *    T_j^2 = (T_2j + T_0) / 2 and T_{j+1} T_j = (T_2j+1 + T_1) / 2.
@@ -309,7 +325,7 @@ typedef struct {
   int n_cand;         /* dichotomy steps, 0 -> 16 */
   int lloyd_iters;    /* Lloyd rounds after seeding, < 0 -> 20 */
   int init;           /* 0: k-means++ every snapshot; 1: warm start from previous labels */
-  csc_dtype iter_dt;  /* storage of the recurrence iterates (F32, BF16 or BF16S) */
+  csc_dtype iter_dt;  /* storage of the recurrence iterates (F32, BF16, F16, BF16S, F16S) */
   int keep_iterates;  /* -1: keep all m + 1 iterates of the fresh block when they fit in free
                          device memory and m < 256 (a refinement then recombines them, in FP64,
                          instead of running the recurrence again); 0: never; 1: always

@@ -10,10 +10,10 @@ oracle's FP64 three-term recurrence with exactly those roundings and nothing els
 arithmetic operation stays FP64).
 
 Rounding is to nearest, ties to even, to a given number of significant bits: 53 (FP64,
-no rounding), 24 (FP32), 11 (FP16), 8 (BF16).  Exponent range is not modelled: the iterates
-of signals of variance 1/d stay far inside the normal range of all four (FP16 ends at 65504
-and turns subnormal below 2^-14, where its spacing 2^-24 is still far below the rounding of
-entries of typical size).
+no rounding), 24 (FP32), 11 (FP16), 8 (BF16).  For FP16 the exponent range is modelled as
+IEEE binary16 has it: below 2^-14 values are rounded to the subnormal grid of spacing 2^-24,
+and results of magnitude 2^16 or more (after rounding) overflow to infinity.  For FP32 and
+BF16 it is not: their range (down to about 1e-38) holds every iterate of these signals.
 
 Formats of one form (each a key of FORMAT_BITS, or an int number of bits):
   val     the stored values of A (normalized adjacency, L = I - A);
@@ -60,13 +60,19 @@ def _bits(fmt) -> int:
 
 
 def round_sig(x, fmt) -> np.ndarray:
-    """x rounded to nearest (ties to even) with the significant bits of `fmt`."""
+    """x rounded to nearest (ties to even) with the significant bits of `fmt` (and, for
+    "f16", binary16's subnormal grid and overflow)."""
     x = np.asarray(x, dtype=np.float64)
     bits = _bits(fmt)
     if bits >= 53:
         return x.copy()
     m, e = np.frexp(x)                      # x = m 2^e, 0.5 <= |m| < 1 (m = 0 for x = 0)
-    return np.ldexp(np.rint(np.ldexp(m, bits)), e - bits)  # np.rint rounds half to even
+    r = np.ldexp(np.rint(np.ldexp(m, bits)), e - bits)  # np.rint rounds half to even
+    if isinstance(fmt, str) and fmt == "f16":
+        sub = np.abs(x) < 2.0 ** -14
+        r = np.where(sub, np.ldexp(np.rint(np.ldexp(x, 24)), -24), r)
+        r = np.where(np.abs(r) >= 2.0 ** 16, np.copysign(np.inf, x), r)
+    return r
 
 
 def round_values(A: sp.csr_matrix, fmt) -> sp.csr_matrix:
@@ -130,6 +136,8 @@ FORMS = {
                          out="bf16"),
     "f16s_basis": dict(val="bf16", state="f32", gather="f16", combine="basis", basis="f32",
                        out="bf16"),
+    "f16s_basis_f16copies": dict(val="bf16", state="f32", gather="f16", combine="basis",
+                                 basis="f16", out="bf16"),
 }
 
 

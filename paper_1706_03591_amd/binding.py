@@ -16,10 +16,11 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsc.so")
 
-F32, BF16, F64, BF16S = 0, 1, 2, 3
-# iterate storage modes: a torch dtype, or "bf16s" (BF16 copies for the gathers and the kept
-# basis, FP32 recurrence state)
+F32, BF16, F64, BF16S, F16, F16S = 0, 1, 2, 3, 4, 5
+# iterate storage modes: a torch dtype (float32, bfloat16, float16), or "bf16s" / "f16s"
+# (BF16 / binary16 copies for the gathers and the kept basis, FP32 recurrence state)
 BF16S_ITER = "bf16s"
+F16S_ITER = "f16s"
 DAMP_NONE, DAMP_JACKSON = 0, 1
 LAP_NORMALIZED, LAP_COMBINATORIAL = 0, 1
 
@@ -27,13 +28,17 @@ _TORCH_DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
 _DT_TORCH = {F32: torch.float32, BF16: torch.bfloat16, F64: torch.float64}
 
 
+_ITER_MODES = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16,
+               BF16S_ITER: BF16S, F16S_ITER: F16S}
+
+
 def _it(iter_dtype) -> int:
-    """Iterate-mode code of a torch dtype or of "bf16s"."""
-    if isinstance(iter_dtype, str):
-        if iter_dtype.lower() == BF16S_ITER:
-            return BF16S
-        raise ValueError(f"unknown iterate mode {iter_dtype!r}")
-    return _TORCH_DT[iter_dtype]
+    """Iterate-mode code of a torch dtype or of "bf16s" / "f16s"."""
+    key = iter_dtype.lower() if isinstance(iter_dtype, str) else iter_dtype
+    try:
+        return _ITER_MODES[key]
+    except KeyError:
+        raise ValueError(f"unknown iterate mode {iter_dtype!r}") from None
 
 STATUS = {0: "CSC_OK", 1: "CSC_E_ARG", 2: "CSC_E_GRAPH", 3: "CSC_E_DTYPE", 4: "CSC_E_NOMEM",
           5: "CSC_E_HIP", 6: "CSC_E_STATE"}

@@ -49,6 +49,16 @@ struct csc_dyn_s {
   double exec_lmax[2][8] = {};
   void* aux = nullptr;
   size_t aux_bytes = 0;
+  // one-pass batches (batch > 1 without kept iterates), two buffers of `batch` slots each:
+  // every slot has a filter workspace, a staged n x qd output block, its coefficients and
+  // its moments on the device
+  bool onepass = false;
+  void* owork = nullptr;
+  size_t owork_bytes = 0;     // per slot
+  void* ostage = nullptr;
+  double* ocoef = nullptr;    // 2 batch (m + 1)
+  double* omom = nullptr;     // 2 batch (m + 1)
+  std::vector<double> ocoef_h;  // host sources of the coefficient uploads, one row per slot
   int variant = 0;
   int t = 0;
   double lam = 0.0;
@@ -79,6 +89,7 @@ void free_dyn(csc_dyn st) {
   if (!st) return;
   for (void* p : {st->theta, st->sig, static_cast<void*>(st->C), static_cast<void*>(st->prev),
                   static_cast<void*>(st->scal), st->fwork, st->kwork, st->dwork, st->basis, st->aux,
+                  st->owork, st->ostage, static_cast<void*>(st->ocoef), static_cast<void*>(st->omom),
                   st->wrap, static_cast<void*>(st->simbuf), static_cast<void*>(st->simd),
                   st->simwork, static_cast<void*>(st->pg.rowptr), static_cast<void*>(st->pg.colidx),
                   st->pg.vals, static_cast<void*>(st->pg.diag), static_cast<void*>(st->pg.deg)})
@@ -152,7 +163,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     return fail(CSC_E_ARG, "variant must be -1 or in [0, " + std::to_string(num_variants()) + ")");
   }
   const size_t es = dtype_size(feat_dt);
-  st->fwork_bytes = filter_workspace(n, d, st->iter_dt);
+  st->fwork_bytes = filter_workspace(n, d, st->iter_dt, m);  // moments up to degree m
   st->kwork_bytes = kmeans_workspace(n, d, k);
   st->dwork_bytes = dot_workspace(n);
   bool ok = hipMalloc(&st->theta, es * n * d) == hipSuccess &&
@@ -214,14 +225,31 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     }
   }
   if (st->batch > 1 && !st->basis) {
-    free_dyn(st);
-    return fail(CSC_E_NOMEM, "a batch of snapshots needs their iterates kept on the device");
+    // one-pass batches: the fresh blocks of a batch are filtered together at the cut-off in
+    // force when the batch starts, with their moments; a snapshot whose cut-off ends up
+    // different is filtered again (all such snapshots of a batch together)
+    st->onepass = true;
+    st->variant = (opts && opts->variant >= 0) ? opts->variant : [&] {
+      Graph probe{};
+      probe.variant_f32 = probe.variant_bf16 = -1;
+      return default_variant(&probe, qd, st->iter_dt);
+    }();
+    st->owork_bytes = align_up(make_plan(n, qd, st->iter_dt, st->variant, m).total);
+    const size_t slots = 2 * static_cast<size_t>(st->batch);
+    st->ocoef_h.assign(slots * (m + 1), 0.0);
+    if (hipMalloc(&st->owork, slots * st->owork_bytes) != hipSuccess ||
+        hipMalloc(&st->ostage, slots * es * n * qd) != hipSuccess ||
+        hipMalloc(&st->ocoef, slots * (m + 1) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&st->omom, slots * (m + 1) * sizeof(double)) != hipSuccess) {
+      free_dyn(st);
+      return fail(CSC_E_NOMEM, "cannot allocate the one-pass batch buffers");
+    }
   }
   if (st->use_graph && hipStreamCreate(&st->cap) != hipSuccess) {
     free_dyn(st);
     return fail(CSC_E_HIP, "cannot create the capture stream");
   }
-  if (st->nbuf == 2 || (st->basis && st->batch == 1)) {
+  if (st->nbuf == 2 || (st->basis && st->batch == 1) || st->onepass) {
     // non-blocking: callers often work on the null stream, which would otherwise serialise
     // with it; the order between the two streams comes only from the events below
     bool ev_ok = hipStreamCreateWithFlags(&st->fs, hipStreamNonBlocking) == hipSuccess &&
@@ -378,6 +406,8 @@ csc_status static_pass(csc_dyn st, const Graph* g, double lm, int t, double* cnt
   return CSC_OK;
 }
 
+csc_status cluster(csc_dyn st, int t, int32_t* labels, hipStream_t s);
+
 // One snapshot of Algorithm 1.  For t >= 2 the fresh signals and (when kept) their iterates
 // live in slot `slot`; with pre_basis the signals are drawn and the iterates computed already
 // (batched recurrence).
@@ -507,8 +537,15 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
   // the kept iterates and signals of this snapshot are no longer needed: a caller may start
   // the next snapshot's recurrence here, beside the k-means
   if (before_kmeans) CSC_TRY(before_kmeans());
+  CSC_TRY(cluster(st, t, labels, s));
+  if (lambda_t) *lambda_t = st->lam;
+  if (refined) *refined = ref;
+  if (count) *count = cnt;
+  return CSC_OK;
+}
 
-  // Step 8: k-means on Theta_t.
+// Step 8 of Algorithm 1: k-means on Theta_t (synchronising).
+csc_status cluster(csc_dyn st, int t, int32_t* labels, hipStream_t s) {
   int init = 0;
   if (st->init == 1 && t > 1) {
     const int64_t kd = static_cast<int64_t>(st->k) * st->d;
@@ -523,12 +560,206 @@ csc_status step_impl(csc_dyn st, const Graph* g, int slot, bool pre_basis, int32
                      st->kwork_bytes, s));
   CSC_HIP(hipMemcpyAsync(st->prev, labels, sizeof(int32_t) * st->n, hipMemcpyDeviceToDevice, s));
   CSC_HIP(hipStreamSynchronize(s));
-  if (lambda_t) *lambda_t = st->lam;
-  if (refined) *refined = ref;
-  if (count) *count = cnt;
   return CSC_OK;
 }
 
+
+// ---- one-pass batches ------------------------------------------------------------------
+
+void* stage_slot(csc_dyn st, int slot) {
+  return static_cast<char*>(st->ostage) + dtype_size(st->feat_dt) * static_cast<size_t>(slot) * st->n * st->qd;
+}
+void* owork_slot(csc_dyn st, int slot) { return static_cast<char*>(st->owork) + st->owork_bytes * static_cast<size_t>(slot); }
+double* ocoef_slot(csc_dyn st, int slot) { return st->ocoef + static_cast<size_t>(slot) * (st->m + 1); }
+double* omom_slot(csc_dyn st, int slot) { return st->omom + static_cast<size_t>(slot) * (st->m + 1); }
+
+// Uploads the coefficients of the step at lam for slot `slot` (graph g's spectrum bound).
+csc_status upload_coefs(csc_dyn st, const Graph* g, int slot, double lam, hipStream_t s) {
+  double* h = st->ocoef_h.data() + static_cast<size_t>(slot) * (st->m + 1);
+  cheb_coeffs(st->m, lmax_for(st, g), lam, st->damp, h);
+  CSC_HIP(hipMemcpyAsync(ocoef_slot(st, slot), h, sizeof(double) * (st->m + 1), hipMemcpyHostToDevice, s));
+  return CSC_OK;
+}
+
+// The one-pass recurrences of the given slots (graphs gs), with moments when asked; replayed
+// from a captured graph when enabled and `cached` (the launches read their coefficients
+// from the device, so a replay stays valid after new uploads).
+csc_status onepass_batch(csc_dyn st, const Graph* const* gs, const int* slots, int S, bool moments,
+                         hipStream_t s, int buf, bool cached) {
+  const void* X[8];
+  void* Y[8];
+  void* W[8];
+  const double* A[8];
+  double* M[8];
+  for (int i = 0; i < S; ++i) {
+    X[i] = sig_slot(st, slots[i]);
+    Y[i] = stage_slot(st, slots[i]);
+    W[i] = owork_slot(st, slots[i]);
+    A[i] = ocoef_slot(st, slots[i]);
+    M[i] = moments ? omom_slot(st, slots[i]) : nullptr;
+  }
+  auto run = [&](hipStream_t q, bool timed) {
+    return run_filter_batch(gs, S, st->lmax, st->m, A, X, st->feat_dt, st->qd, Y, st->feat_dt,
+                            st->qd, st->qd, st->iter_dt, st->variant, moments ? M : nullptr, W,
+                            st->owork_bytes, q, timed);
+  };
+  if (!st->use_graph || !cached) return run(s, true);
+  const void* key[10] = {};
+  double lms[8] = {};
+  key[0] = reinterpret_cast<const void*>(static_cast<intptr_t>(S));
+  for (int i = 0; i < S; ++i) {
+    key[1 + i] = gs[i];
+    lms[i] = lmax_for(st, gs[i]);
+  }
+  hipGraphExec_t& exec = st->exec[buf];
+  bool same = exec != nullptr;
+  for (int i = 0; i < 10 && same; ++i) same = key[i] == st->exec_key[buf][i];
+  for (int i = 0; i < 8 && same; ++i) same = lms[i] == st->exec_lmax[buf][i];
+  if (!same) {
+    if (exec) {
+      (void)hipGraphExecDestroy(exec);
+      exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    CSC_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeRelaxed));
+    const csc_status cs = run(st->cap, false);
+    const hipError_t e = hipStreamEndCapture(st->cap, &graph);
+    if (cs != CSC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cs;
+    }
+    if (e != hipSuccess) return fail(CSC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      exec = nullptr;
+      return fail(CSC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    for (int i = 0; i < 10; ++i) st->exec_key[buf][i] = key[i];
+    for (int i = 0; i < 8; ++i) st->exec_lmax[buf][i] = lms[i];
+  }
+  timing_begin(s);
+  CSC_HIP(hipGraphLaunch(exec, s));
+  timing_end(s, st->m, filter_batch_bytes(gs, S, st->m, st->qd, st->iter_dt, true, st->feat_dt));
+  return CSC_OK;
+}
+
+// Copies a staged n x qd block into Theta at the ring's cursor (two parts when it wraps past
+// column d) and advances the cursor.
+csc_status place_block(csc_dyn st, const void* blk, hipStream_t s) {
+  const size_t es = dtype_size(st->feat_dt);
+  const int c0 = st->cursor;
+  const int first = std::min(st->qd, st->d - c0);
+  char* th = static_cast<char*>(st->theta);
+  const char* b = static_cast<const char*>(blk);
+  CSC_HIP(hipMemcpy2DAsync(th + es * static_cast<size_t>(c0), es * st->d, b, es * st->qd, es * first,
+                           st->n, hipMemcpyDeviceToDevice, s));
+  if (first < st->qd)
+    CSC_HIP(hipMemcpy2DAsync(th, es * st->d, b + es * static_cast<size_t>(first), es * st->qd,
+                             es * (st->qd - first), st->n, hipMemcpyDeviceToDevice, s));
+  st->cursor = (c0 + st->qd) % st->d;
+  return CSC_OK;
+}
+
+// Snapshots i0 .. S-1 (all after the first) in one-pass batches.  Batch b's fresh blocks are
+// filtered together at the cut-off in force when it is issued, with their moments.  Its
+// snapshots are then decided in order on the host from their moments (Algorithm 1 steps
+// 6-7: the count at the current cut-off, and when it misses k by more than tau the one-sided
+// dichotomy), which needs no further filtering; the snapshots whose cut-off differs from the
+// one they were filtered at are filtered again, together.  The next batch's recurrence is
+// then issued on the state's stream, at the updated cut-off, and runs beside this batch's
+// k-means.
+csc_status steps_onepass(csc_dyn st, const csc_graph* graphs, int i0, int S, int32_t* const* labels,
+                         double* lambdas, int* refined, double* counts, hipStream_t s) {
+  const int t0 = st->t;
+  const int nbatch = (S - i0 + st->batch - 1) / st->batch;
+  const double sigma2 = 1.0 / static_cast<double>(st->d);
+  hipStream_t fs = st->fs;
+  CSC_HIP(hipEventRecord(st->ev_start, s));
+  CSC_HIP(hipStreamWaitEvent(fs, st->ev_start, 0));
+  double lam_issued[2] = {0.0, 0.0};
+  auto range = [&](int b, int* j, int* nb) {
+    *j = i0 + b * st->batch;
+    *nb = std::min(st->batch, S - *j);
+  };
+  auto issue = [&](int b) -> csc_status {
+    int j, nb;
+    range(b, &j, &nb);
+    const int buf = b & 1;
+    if (b >= 2) CSC_HIP(hipStreamWaitEvent(fs, st->ev_free[buf], 0));
+    const Graph* gs[8];
+    int slots[8];
+    for (int q = 0; q < nb; ++q) {
+      gs[q] = &graphs[j + q]->g;
+      slots[q] = buf * st->batch + q;
+      CSC_TRY(draw_signals(st, t0 + 1 + (j - i0) + q, slots[q], fs));
+      CSC_TRY(upload_coefs(st, gs[q], slots[q], st->lam, fs));
+    }
+    lam_issued[buf] = st->lam;
+    CSC_TRY(onepass_batch(st, gs, slots, nb, true, fs, buf, true));
+    CSC_HIP(hipEventRecord(st->ev_basis[buf], fs));
+    return CSC_OK;
+  };
+  std::vector<double> mu(static_cast<size_t>(st->batch) * (st->m + 1)), a(st->m + 1);
+  CSC_TRY(issue(0));
+  for (int b = 0; b < nbatch; ++b) {
+    int j, nb;
+    range(b, &j, &nb);
+    const int buf = b & 1;
+    CSC_HIP(hipStreamWaitEvent(s, st->ev_basis[buf], 0));
+    CSC_HIP(hipMemcpyAsync(mu.data(), omom_slot(st, buf * st->batch), sizeof(double) * nb * (st->m + 1),
+                           hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    // decisions, snapshot by snapshot
+    double lam_q[8], cnt_q[8];
+    int ref_q[8];
+    const Graph* again[8];
+    int again_slots[8], n_again = 0;
+    for (int q = 0; q < nb; ++q) {
+      const Graph* g = &graphs[j + q]->g;
+      const double lm = lmax_for(st, g);
+      const double* m_q = mu.data() + static_cast<size_t>(q) * (st->m + 1);
+      cheb_coeffs(st->m, lm, st->lam, st->damp, a.data());
+      double c = 0.0;
+      for (int i = 0; i <= st->m; ++i) c += a[i] * m_q[i];
+      c /= sigma2 * st->qd;
+      int ref = 0;
+      if (std::fabs(c - st->k) > st->tau) {
+        const double prev = std::min(st->lam, lm);
+        const double lo = c < st->k ? prev : 0.0;
+        const double hi = c < st->k ? lm : prev;
+        bisect_moments(m_q, st->m, lm, st->damp, sigma2, st->qd, st->k, st->n_cand, lo, hi,
+                       &st->lam, &c, nullptr);
+        ref = 1;
+      }
+      lam_q[q] = st->lam;
+      cnt_q[q] = c;
+      ref_q[q] = ref;
+      if (st->lam != lam_issued[buf]) {
+        again[n_again] = g;
+        again_slots[n_again] = buf * st->batch + q;
+        CSC_TRY(upload_coefs(st, g, again_slots[n_again], st->lam, s));
+        ++n_again;
+      }
+    }
+    if (n_again > 0) CSC_TRY(onepass_batch(st, again, again_slots, n_again, false, s, buf, false));
+    if (b + 1 < nbatch) {
+      // the next batch may start once this batch's filtering is enqueued (its buffer is the
+      // other one; that buffer's last use is fenced by ev_free)
+      CSC_TRY(issue(b + 1));
+    }
+    for (int q = 0; q < nb; ++q) {
+      const int t = ++st->t;
+      CSC_TRY(place_block(st, stage_slot(st, buf * st->batch + q), s));
+      CSC_TRY(cluster(st, t, labels[j + q], s));
+      if (lambdas) lambdas[j + q] = lam_q[q];
+      if (refined) refined[j + q] = ref_q[q];
+      if (counts) counts[j + q] = cnt_q[q];
+    }
+    CSC_HIP(hipEventRecord(st->ev_free[buf], s));
+  }
+  return CSC_OK;
+}
 }  // namespace
 
 csc_status dyn_step(csc_dyn st, csc_graph gh, int32_t* labels, double* lambda_t, int* refined,
@@ -558,13 +789,19 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
     return std::make_tuple(lambdas ? lambdas + j : nullptr, refined ? refined + j : nullptr,
                            counts ? counts + j : nullptr);
   };
-  // the first snapshot, no kept iterates, or similarity tracking: one at a time
-  while (i < S && (st->t == 0 || !st->basis || st->track)) {
+  // the first snapshot, no kept iterates and no one-pass batches, or similarity tracking:
+  // one at a time
+  while (i < S && (st->t == 0 || (!st->basis && !st->onepass) || st->track)) {
     auto [l, r, c] = out(i);
     CSC_TRY(step_impl(st, &graphs[i]->g, 0, false, labels[i], l, r, c, s));
     ++i;
   }
   if (i >= S) return CSC_OK;
+  if (st->onepass) {
+    const csc_status rc = steps_onepass(st, graphs, i, S, labels, lambdas, refined, counts, s);
+    if (rc != CSC_OK) (void)hipStreamSynchronize(st->fs);
+    return rc;
+  }
   const int i0 = i;
   const int t0 = st->t;  // snapshot i has index t0 + 1 + (i - i0)
   const int nbatch = (S - i0 + st->batch - 1) / st->batch;

@@ -31,20 +31,29 @@ csc_status fail(csc_status st, const std::string& msg);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Element size; for the iterate mode CSC_BF16S, the size of the stored (gathered) copy.
+// Element size; for the split iterate modes (CSC_BF16S, CSC_F16S), the size of the stored
+// (gathered) copy.
 inline size_t dtype_size(csc_dtype t) {
   switch (t) {
     case CSC_F32: return 4;
     case CSC_BF16: return 2;
     case CSC_F64: return 8;
     case CSC_BF16S: return 2;
+    case CSC_F16: return 2;
+    case CSC_F16S: return 2;
   }
   return 0;
 }
 
-inline bool iter_type_ok(csc_dtype t) { return t == CSC_F32 || t == CSC_BF16 || t == CSC_BF16S; }
-// bytes per element of the separate FP32 recurrence state (CSC_BF16S only)
-inline size_t state_size(csc_dtype t) { return t == CSC_BF16S ? 4 : 0; }
+inline bool iter_type_ok(csc_dtype t) {
+  return t == CSC_F32 || t == CSC_BF16 || t == CSC_BF16S || t == CSC_F16 || t == CSC_F16S;
+}
+// split modes: 16-bit copies for the gathers and the kept basis, FP32 recurrence state
+inline bool iter_split(csc_dtype t) { return t == CSC_BF16S || t == CSC_F16S; }
+// binary16 copies (CSC_F16, CSC_F16S)
+inline bool iter_half(csc_dtype t) { return t == CSC_F16 || t == CSC_F16S; }
+// bytes per element of the separate FP32 recurrence state (split modes only)
+inline size_t state_size(csc_dtype t) { return iter_split(t) ? 4 : 0; }
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -134,7 +143,8 @@ struct FilterPlan {
 };
 
 FilterPlan make_plan(int64_t n, int w, csc_dtype iter_dt, int variant, int m_for_moments);
-size_t filter_workspace(int64_t n, int w, csc_dtype iter_dt);
+// every variant, moments up to degree m_max (the ABI's filter calls accept m <= 4096)
+size_t filter_workspace(int64_t n, int w, csc_dtype iter_dt, int m_max = 4096);
 
 // Runs the whole recurrence.  mode_acc: accumulate Y; moments: device double[m+1] or null.
 csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const void* X,
@@ -160,6 +170,15 @@ csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m
                            csc_dtype iter_dt, int variant, void* const* bases, size_t bytes,
                            hipStream_t s, bool timed);
 double basis_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dtype iter_dt);
+// S (<= 8) one-pass filters with per-snapshot device coefficients (and moments), one launch
+// per step; work[i] holds make_plan(n, w, iter_dt, variant, m).total bytes.
+csc_status run_filter_batch(const Graph* const* graphs, int S, double lmax, int m,
+                            const double* const* coefs, const void* const* X, csc_dtype x_dt,
+                            int64_t ldx, void* const* Y, csc_dtype y_dt, int64_t ldy, int w,
+                            csc_dtype iter_dt, int variant, double* const* moments,
+                            void* const* work, size_t work_bytes, hipStream_t s, bool timed);
+double filter_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dtype iter_dt,
+                          bool moments, csc_dtype y_dt);
 
 // ------------------------------------------------------------------------------------
 // reductions, RNG

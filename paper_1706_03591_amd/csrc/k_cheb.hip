@@ -19,9 +19,10 @@
 // served by `LPR` lanes that each own 16 bytes of the row (4 FP32 or 8 BF16 columns), so a
 // gather is one 16-byte load per lane and one contiguous segment per row group.
 //
-// Iterate modes: FP32; BF16 (iterates rounded to BF16 at every step); BF16S (BF16 copies of
-// the iterates for the gathers and the kept basis, while the recurrence state Z_{j-1}, Z_j,
-// Z_{j+1} of each row stays in a separate FP32 tiled array with the same element offsets).
+// Iterate modes: FP32; BF16 or F16 (iterates rounded to BF16 / IEEE binary16 at every step);
+// BF16S or F16S (16-bit copies of the iterates for the gathers and the kept basis, while the
+// recurrence state Z_{j-1}, Z_j, Z_{j+1} of each row stays in a separate FP32 tiled array
+// with the same element offsets).
 #include <type_traits>
 
 #include "csc_internal.h"
@@ -35,10 +36,35 @@ constexpr int kStageCap = 2048;  // CSR entries staged in LDS per block
 
 enum : int { F_FIRST = 1, F_ACC = 2, F_LAST = 4, F_MOM = 8, F_STORE = 16, F_OWN = 32 };
 
-// Tag type of the BF16S iterate mode (BF16 gathered copies, FP32 state).
+// Tag types of the split iterate modes (16-bit gathered copies, FP32 state).  The 16-bit
+// storage types are uint16_t (BF16 bits) and _Float16 (IEEE binary16).
 struct Bf16S {};
+struct F16S {};
 template <typename TZ>
-using GatherT = typename std::conditional<std::is_same<TZ, Bf16S>::value, uint16_t, TZ>::type;
+constexpr bool kSplit = std::is_same<TZ, Bf16S>::value || std::is_same<TZ, F16S>::value;
+template <typename TZ>
+using GatherT = typename std::conditional<
+    std::is_same<TZ, Bf16S>::value, uint16_t,
+    typename std::conditional<std::is_same<TZ, F16S>::value, _Float16, TZ>::type>::type;
+
+// Conversions of a 16-bit storage type: to(f) rounds to nearest even and returns the bits,
+// from(bits) widens exactly.
+template <typename T16>
+struct Cvt16;
+template <>
+struct Cvt16<uint16_t> {
+  __device__ static inline uint16_t to(float f) { return f32_to_bf16(f); }
+  __device__ static inline float from(uint16_t h) { return bf16_to_f32(h); }
+};
+template <>
+struct Cvt16<_Float16> {
+  __device__ static inline uint16_t to(float f) {
+    return __builtin_bit_cast(uint16_t, static_cast<_Float16>(f));
+  }
+  __device__ static inline float from(uint16_t h) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, h));
+  }
+};
 
 template <typename TZ>
 struct Pack;
@@ -59,30 +85,36 @@ struct Pack<float> {
   }
 };
 
-template <>
-struct Pack<uint16_t> {
+// eight 16-bit values per 16 bytes, element 2i in the low half of word i
+template <typename T16>
+struct Pack16 {
   static constexpr int VEC = 8;
   __device__ static inline void unpack(const uint4& u, float* f) {
     const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      f[2 * i] = __uint_as_float(w[i] << 16);
-      f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+      f[2 * i] = Cvt16<T16>::from(static_cast<uint16_t>(w[i] & 0xffffu));
+      f[2 * i + 1] = Cvt16<T16>::from(static_cast<uint16_t>(w[i] >> 16));
     }
   }
+  // round to storage and return the stored values in f
   __device__ static inline uint4 pack(float* f) {
     uint32_t w[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      uint16_t lo = f32_to_bf16(f[2 * i]);
-      uint16_t hi = f32_to_bf16(f[2 * i + 1]);
-      f[2 * i] = bf16_to_f32(lo);
-      f[2 * i + 1] = bf16_to_f32(hi);
+      const uint16_t lo = Cvt16<T16>::to(f[2 * i]);
+      const uint16_t hi = Cvt16<T16>::to(f[2 * i + 1]);
+      f[2 * i] = Cvt16<T16>::from(lo);
+      f[2 * i + 1] = Cvt16<T16>::from(hi);
       w[i] = static_cast<uint32_t>(lo) | (static_cast<uint32_t>(hi) << 16);
     }
     return make_uint4(w[0], w[1], w[2], w[3]);
   }
 };
+template <>
+struct Pack<uint16_t> : Pack16<uint16_t> {};
+template <>
+struct Pack<_Float16> : Pack16<_Float16> {};
 
 template <typename TV>
 __device__ inline float val_f(TV v);
@@ -128,6 +160,8 @@ struct StepParams {
   int64_t n;
   int64_t row_blocks;
   float alpha, beta, coef;
+  const double* coef_dev;  // device FP64 coefficient; when set it replaces `coef` (graph replay
+                           // with coefficients that change between replays)
   float gam;           // combinatorial: own-row factor alpha + gam d_r
   const float* diag;   // combinatorial: d_r; null for the normalized Laplacian
   int flags;
@@ -181,7 +215,7 @@ __device__ inline void block_reduce2(double& a, double& b) {
 // several snapshots' steps, each with its own parameters and block range).
 template <typename TZ, typename TV, int LPR>
 __device__ inline void step_body(const StepParams& p, const int64_t bid, const int64_t nblocks) {
-  constexpr bool MIX = std::is_same<TZ, Bf16S>::value;
+  constexpr bool MIX = kSplit<TZ>;
   using TG = GatherT<TZ>;
   using P = Pack<TG>;
   constexpr int VEC = P::VEC;
@@ -374,14 +408,15 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
     if (p.flags & F_ACC) {
       const int64_t col0 = tile * WT + lane * VEC;
       float* ap = p.acc + row * p.ld_acc + col0;
+      const float cf = p.coef_dev ? static_cast<float>(*p.coef_dev) : p.coef;
       float y[VEC];
 #pragma unroll
       for (int i = 0; i < VEC; i += 4) {
         float4 t4 = *reinterpret_cast<const float4*>(ap + i);
-        y[i] = fmaf(p.coef, zn[i], t4.x);
-        y[i + 1] = fmaf(p.coef, zn[i + 1], t4.y);
-        y[i + 2] = fmaf(p.coef, zn[i + 2], t4.z);
-        y[i + 3] = fmaf(p.coef, zn[i + 3], t4.w);
+        y[i] = fmaf(cf, zn[i], t4.x);
+        y[i + 1] = fmaf(cf, zn[i + 1], t4.y);
+        y[i + 2] = fmaf(cf, zn[i + 2], t4.z);
+        y[i + 3] = fmaf(cf, zn[i + 3], t4.w);
       }
       if (p.yout) {
 #pragma unroll
@@ -425,9 +460,10 @@ __global__ __launch_bounds__(kThreads) void k_step_batch(StepBatch b) {
 // Z_0 (tiled, iter type) from X (row-major, x_dt); acc = a0 * Z_0 when acc != null.
 template <typename TZ>
 __global__ void k_init(const void* X, int x_dt, int64_t ldx, int64_t n, int w, int wpad, int wt,
-                       TZ* z0, float* acc, float a0, float* s0) {
+                       TZ* z0, float* acc, float a0, float* s0, const double* a0_dev) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n * wpad) return;
+  if (a0_dev) a0 = static_cast<float>(*a0_dev);
   const int64_t row = idx / wpad;
   const int col = static_cast<int>(idx - row * wpad);
   float x = 0.f;
@@ -444,9 +480,9 @@ __global__ void k_init(const void* X, int x_dt, int64_t ldx, int64_t n, int w, i
     stored = x;
     z0[e] = stored;
   } else {
-    const uint16_t h = f32_to_bf16(x);
-    z0[e] = h;
-    stored = s0 ? x : bf16_to_f32(h);  // BF16S: the state keeps the FP32 value
+    const uint16_t h = Cvt16<TZ>::to(x);
+    reinterpret_cast<uint16_t*>(z0)[e] = h;
+    stored = s0 ? x : Cvt16<TZ>::from(h);  // split modes: the state keeps the FP32 value
     if (s0) s0[e] = x;
   }
   if (acc) acc[row * wpad + col] = a0 * stored;
@@ -457,10 +493,11 @@ __global__ void k_init(const void* X, int x_dt, int64_t ldx, int64_t n, int w, i
 // or wholly past w, and inside one tile (wt is a multiple of 8).  Same values as k_init.
 template <typename TZ>
 __global__ void k_init8(const void* X, int x_dt, int64_t ldx, int64_t n, int w, int wpad, int wt,
-                        TZ* z0, float* acc, float a0, float* s0) {
+                        TZ* z0, float* acc, float a0, float* s0, const double* a0_dev) {
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int gpr = wpad / 8;
   if (g >= n * gpr) return;
+  if (a0_dev) a0 = static_cast<float>(*a0_dev);
   const int64_t row = g / gpr;
   const int col = static_cast<int>(g - row * gpr) * 8;
   float x[8];
@@ -495,10 +532,10 @@ __global__ void k_init8(const void* X, int x_dt, int64_t ldx, int64_t n, int w, 
     uint32_t wd[4];
 #pragma unroll
     for (int k2 = 0; k2 < 4; ++k2) {
-      const uint16_t lo = f32_to_bf16(x[2 * k2]), hi = f32_to_bf16(x[2 * k2 + 1]);
+      const uint16_t lo = Cvt16<TZ>::to(x[2 * k2]), hi = Cvt16<TZ>::to(x[2 * k2 + 1]);
       wd[k2] = static_cast<uint32_t>(lo) | (static_cast<uint32_t>(hi) << 16);
-      stored[2 * k2] = s0 ? x[2 * k2] : bf16_to_f32(lo);  // BF16S: the state keeps FP32
-      stored[2 * k2 + 1] = s0 ? x[2 * k2 + 1] : bf16_to_f32(hi);
+      stored[2 * k2] = s0 ? x[2 * k2] : Cvt16<TZ>::from(lo);  // split modes keep FP32
+      stored[2 * k2 + 1] = s0 ? x[2 * k2 + 1] : Cvt16<TZ>::from(hi);
     }
     st16(z0 + e, make_uint4(wd[0], wd[1], wd[2], wd[3]));
     if (s0) st8f(s0 + e, x);
@@ -571,21 +608,30 @@ BatchFn pick_batch(int lpr, csc_dtype val_dt) {
 }
 
 StepFn step_fn(csc_dtype iter_dt, int lpr, csc_dtype val_dt) {
-  if (iter_dt == CSC_F32) return pick_step<float>(lpr, val_dt);
-  if (iter_dt == CSC_BF16S) return pick_step<Bf16S>(lpr, val_dt);
-  return pick_step<uint16_t>(lpr, val_dt);
+  switch (iter_dt) {
+    case CSC_F32: return pick_step<float>(lpr, val_dt);
+    case CSC_BF16S: return pick_step<Bf16S>(lpr, val_dt);
+    case CSC_F16: return pick_step<_Float16>(lpr, val_dt);
+    case CSC_F16S: return pick_step<F16S>(lpr, val_dt);
+    default: return pick_step<uint16_t>(lpr, val_dt);
+  }
 }
 
 BatchFn batch_fn(csc_dtype iter_dt, int lpr, csc_dtype val_dt) {
-  if (iter_dt == CSC_F32) return pick_batch<float>(lpr, val_dt);
-  if (iter_dt == CSC_BF16S) return pick_batch<Bf16S>(lpr, val_dt);
-  return pick_batch<uint16_t>(lpr, val_dt);
+  switch (iter_dt) {
+    case CSC_F32: return pick_batch<float>(lpr, val_dt);
+    case CSC_BF16S: return pick_batch<Bf16S>(lpr, val_dt);
+    case CSC_F16: return pick_batch<_Float16>(lpr, val_dt);
+    case CSC_F16S: return pick_batch<F16S>(lpr, val_dt);
+    default: return pick_batch<uint16_t>(lpr, val_dt);
+  }
 }
 
 // Z_0 of the tiled iterates (and of the FP32 state in BF16S mode) from X; acc = a0 Z_0 when
 // acc is given.
 void launch_init(csc_dtype iter_dt, const void* X, csc_dtype x_dt, int64_t ldx, int64_t n, int w,
-                 int wpad, int wt, void* z0, float* acc, float a0, float* s0, hipStream_t s) {
+                 int wpad, int wt, void* z0, float* acc, float a0, float* s0, hipStream_t s,
+                 const double* a0_dev = nullptr) {
   const size_t xs = dtype_size(x_dt);
   if ((x_dt == CSC_F32 || x_dt == CSC_BF16) && w % 8 == 0 && wpad % 8 == 0 && wt % 8 == 0 &&
       reinterpret_cast<uintptr_t>(X) % 16 == 0 && (static_cast<size_t>(ldx) * xs) % 16 == 0) {
@@ -593,22 +639,30 @@ void launch_init(csc_dtype iter_dt, const void* X, csc_dtype x_dt, int64_t ldx, 
     const unsigned gb = static_cast<unsigned>((groups + 255) / 256);
     if (iter_dt == CSC_F32)
       hipLaunchKernelGGL(k_init8<float>, dim3(gb), dim3(256), 0, s, X, int(x_dt), ldx, n, w, wpad,
-                         wt, static_cast<float*>(z0), acc, a0, static_cast<float*>(nullptr));
+                         wt, static_cast<float*>(z0), acc, a0, static_cast<float*>(nullptr), a0_dev);
+    else if (iter_half(iter_dt))
+      hipLaunchKernelGGL(k_init8<_Float16>, dim3(gb), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
+                         wpad, wt, static_cast<_Float16*>(z0), acc, a0,
+                         iter_split(iter_dt) ? s0 : static_cast<float*>(nullptr), a0_dev);
     else
       hipLaunchKernelGGL(k_init8<uint16_t>, dim3(gb), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
                          wpad, wt, static_cast<uint16_t*>(z0), acc, a0,
-                         iter_dt == CSC_BF16S ? s0 : static_cast<float*>(nullptr));
+                         iter_split(iter_dt) ? s0 : static_cast<float*>(nullptr), a0_dev);
     return;
   }
   const int64_t total = n * wpad;
   const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
   if (iter_dt == CSC_F32)
     hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w, wpad,
-                       wt, static_cast<float*>(z0), acc, a0, static_cast<float*>(nullptr));
+                       wt, static_cast<float*>(z0), acc, a0, static_cast<float*>(nullptr), a0_dev);
+  else if (iter_half(iter_dt))
+    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
+                       wpad, wt, static_cast<_Float16*>(z0), acc, a0,
+                       iter_split(iter_dt) ? s0 : static_cast<float*>(nullptr), a0_dev);
   else
     hipLaunchKernelGGL(k_init<uint16_t>, dim3(blocks), dim3(256), 0, s, X, int(x_dt), ldx, n, w,
                        wpad, wt, static_cast<uint16_t*>(z0), acc, a0,
-                       iter_dt == CSC_BF16S ? s0 : static_cast<float*>(nullptr));
+                       iter_split(iter_dt) ? s0 : static_cast<float*>(nullptr), a0_dev);
 }
 
 }  // namespace
@@ -660,25 +714,25 @@ FilterPlan make_plan(int64_t n, int w, csc_dtype iter_dt, int variant, int m_for
   return pl;
 }
 
-// Workspace large enough for every variant and for moments up to degree 4096.
-size_t filter_workspace(int64_t n, int w, csc_dtype iter_dt) {
+// Workspace large enough for every variant and for moments up to degree m_max.
+size_t filter_workspace(int64_t n, int w, csc_dtype iter_dt, int m_max) {
   size_t best = 0;
   for (int v = 0; v < num_variants(); ++v)
-    best = std::max(best, make_plan(n, w, iter_dt, v, 4096).total);
+    best = std::max(best, make_plan(n, w, iter_dt, v, m_max).total);
   return best;
 }
 
 static double step_bytes(const Graph* g, int64_t n, int w, csc_dtype iter_dt, int flags,
                          csc_dtype y_dt) {
   const double sz = static_cast<double>(dtype_size(iter_dt));
-  const double ss = iter_dt == CSC_BF16S ? 4.0 : sz;  // state element (own-row streams)
+  const double ss = iter_split(iter_dt) ? 4.0 : sz;  // state element (own-row streams)
   double b = static_cast<double>(g->nnz) * (4.0 + dtype_size(g->val_dt)) + 4.0 * (n + 1);
   if (g->diag) b += 4.0 * n;                      // degrees (combinatorial)
   const double nw = static_cast<double>(n) * w;
   b += nw * sz;                                   // gather Z_j (each row counted once)
-  if ((flags & F_OWN) && iter_dt == CSC_BF16S) b += nw * ss;  // own Z_j from the state
+  if ((flags & F_OWN) && iter_split(iter_dt)) b += nw * ss;  // own Z_j from the state
   if (!(flags & F_FIRST)) b += nw * ss;           // Z_{j-1}
-  if (flags & F_STORE) b += nw * (iter_dt == CSC_BF16S ? ss + sz : sz);  // Z_{j+1}
+  if (flags & F_STORE) b += nw * (iter_split(iter_dt) ? ss + sz : sz);  // Z_{j+1}
   if (flags & F_ACC) b += nw * 4.0 + ((flags & F_LAST) ? nw * dtype_size(y_dt) : nw * 4.0);
   return b;
 }
@@ -691,7 +745,7 @@ csc_status run_filter(const Graph* g, double lmax, int m, const double* a, const
   if (m < 0) return fail(CSC_E_ARG, "m must be >= 0");
   if (w < 1) return fail(CSC_E_ARG, "w must be >= 1");
   if (!(lmax > 0.0)) return fail(CSC_E_ARG, "lmax must be > 0");
-  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16 or BF16S");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16, F16, BF16S or F16S");
   if (moments && m < 1) return fail(CSC_E_ARG, "moments need m >= 1");
   if (!moments_only && (ldy < w || !Y)) return fail(CSC_E_ARG, "bad Y / ldy");
   if (ldx < w || !X) return fail(CSC_E_ARG, "bad X / ldx");
@@ -1059,7 +1113,7 @@ csc_status run_backward(const Graph* g, double lmax, int m, const double* a, con
   };
   hipLaunchKernelGGL(k_init<float>, dim3(eblocks), dim3(256), 0, s, static_cast<const void*>(X),
                      int(CSC_F32), ldx, n, w, pl.wpad, wt, pp[0], static_cast<float*>(nullptr), 0.f,
-                     static_cast<float*>(nullptr));
+                     static_cast<float*>(nullptr), static_cast<const double*>(nullptr));
   gdot(pp[0], 0);
   CSC_TRY(keep(0, pp[0]));
   for (int j = 0; j < m; ++j) {
@@ -1352,7 +1406,7 @@ csc_status run_basis(const Graph* g, double lmax, int m, const void* X, csc_dtyp
                      int w, csc_dtype iter_dt, int variant, void* basis, size_t bytes, hipStream_t s) {
   const int64_t n = g->n;
   if (m < 1 || w < 1 || ldx < w || !X) return fail(CSC_E_ARG, "bad basis arguments");
-  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16 or BF16S");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16, F16, BF16S or F16S");
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
   const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
   const size_t state_bytes = align_up(static_cast<size_t>(n) * pl.wpad * state_size(iter_dt));
@@ -1400,7 +1454,7 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
   if (m + 1 > kMaxCombine) return fail(CSC_E_ARG, "combine supports m < 256");
   if (!Y || ldy < w) return fail(CSC_E_ARG, "bad Y");
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
-  const int VEC = iter_dt == CSC_F32 ? 4 : 8;  // BF16 and BF16S keep BF16 copies
+  const int VEC = iter_dt == CSC_F32 ? 4 : 8;  // the 16-bit modes keep 16-bit copies
   const int64_t threads = n * (pl.wpad / VEC);
   const unsigned blocks = static_cast<unsigned>((threads + kThreads - 1) / kThreads);
   if (dot && aux_bytes < align_up((blocks + 1) * sizeof(double))) return fail(CSC_E_ARG, "aux too small");
@@ -1430,6 +1484,8 @@ csc_status run_combine(const void* basis, int64_t n, int w, int m, csc_dtype ite
   for (int j = 0; j <= m; ++j) p.coef[j] = a[j];
   if (iter_dt == CSC_F32)
     hipLaunchKernelGGL(k_combine<float>, dim3(blocks), dim3(kThreads), 0, s, p);
+  else if (iter_half(iter_dt))
+    hipLaunchKernelGGL(k_combine<_Float16>, dim3(blocks), dim3(kThreads), 0, s, p);
   else
     hipLaunchKernelGGL(k_combine<uint16_t>, dim3(blocks), dim3(kThreads), 0, s, p);
   if (dot) hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kThreads), 0, s, static_cast<double*>(aux),
@@ -1452,6 +1508,9 @@ csc_status run_basis_moments(const void* basis, int64_t n, int w, int m, csc_dty
   if (iter_dt == CSC_F32)
     hipLaunchKernelGGL(k_dir_moments<float>, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s,
                        static_cast<const float*>(basis), slot, nvec, m, part);
+  else if (iter_half(iter_dt))
+    hipLaunchKernelGGL(k_dir_moments<_Float16>, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s,
+                       static_cast<const _Float16*>(basis), slot, nvec, m, part);
   else
     hipLaunchKernelGGL(k_dir_moments<uint16_t>, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s,
                        static_cast<const uint16_t*>(basis), slot, nvec, m, part);
@@ -1478,7 +1537,7 @@ csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m
     if (graphs[i]->val_dt != graphs[0]->val_dt) return fail(CSC_E_DTYPE, "batched graphs must share the value type");
   }
   if (m < 1 || w < 1 || ldx < w) return fail(CSC_E_ARG, "bad basis arguments");
-  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16 or BF16S");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16, F16, BF16S or F16S");
   const FilterPlan pl = make_plan(n, w, iter_dt, variant, 0);
   const size_t slot_bytes = align_up(static_cast<size_t>(n) * pl.wpad * dtype_size(iter_dt));
   const size_t state_bytes = align_up(static_cast<size_t>(n) * pl.wpad * state_size(iter_dt));
@@ -1523,6 +1582,110 @@ csc_status run_basis_batch(const Graph* const* graphs, int S, double lmax, int m
   if (timed) timing_end(s, m, bytes_alg);
   CSC_HIP(hipGetLastError());
   return CSC_OK;
+}
+
+// S (<= 8) one-pass filters advanced together, one launch per step (the dynamic step's
+// fresh blocks of several snapshots without kept iterates): snapshot i filters X[i] on
+// graphs[i] with its own coefficients coefs[i][0..m] (device FP64, read by the kernels, so a
+// captured sequence of launches stays valid when they change), accumulates in FP32 and
+// stores Y[i] (y_dt) at the last step; with moments[i] != null it also returns the doubled
+// moments mu_0..mu_m of X[i] (device).  work[i]: a filter workspace for (n, w, iter_dt) of
+// least make_plan(n, w, iter_dt, variant, m).total bytes.
+csc_status run_filter_batch(const Graph* const* graphs, int S, double lmax, int m,
+                            const double* const* coefs, const void* const* X, csc_dtype x_dt,
+                            int64_t ldx, void* const* Y, csc_dtype y_dt, int64_t ldy, int w,
+                            csc_dtype iter_dt, int variant, double* const* moments,
+                            void* const* work, size_t work_bytes, hipStream_t s, bool timed) {
+  if (S < 1 || S > kMaxBatch) return fail(CSC_E_ARG, "batch size must be in [1, 8]");
+  const int64_t n = graphs[0]->n;
+  for (int i = 0; i < S; ++i) {
+    if (graphs[i]->n != n) return fail(CSC_E_ARG, "batched graphs must have the same n");
+    if (graphs[i]->val_dt != graphs[0]->val_dt) return fail(CSC_E_DTYPE, "batched graphs must share the value type");
+  }
+  if (m < 1 || w < 1 || ldx < w || ldy < w) return fail(CSC_E_ARG, "bad batched filter arguments");
+  if (!iter_type_ok(iter_dt)) return fail(CSC_E_DTYPE, "iterates must be F32, BF16, F16, BF16S or F16S");
+  const bool mom = moments != nullptr && moments[0] != nullptr;
+  const FilterPlan pl = make_plan(n, w, iter_dt, variant, mom ? m : 0);
+  if (work_bytes < pl.total) return fail(CSC_E_ARG, "batched filter workspace too small");
+  const int wt = pl.shape.wt();
+  auto at = [&](int i, size_t off) { return static_cast<char*>(work[i]) + off; };
+  for (int i = 0; i < S; ++i)
+    launch_init(iter_dt, X[i], x_dt, ldx, n, w, pl.wpad, wt, at(i, pl.off_z0),
+                reinterpret_cast<float*>(at(i, pl.off_acc)), 0.f,
+                reinterpret_cast<float*>(at(i, pl.off_s0)), s, coefs[i]);
+  const BatchFn fn = batch_fn(iter_dt, pl.shape.lpr, graphs[0]->val_dt);
+  const int64_t per = pl.row_blocks * pl.ntiles;
+  const int J = m / 2;
+  double bytes_alg = 0.0;
+  if (timed) timing_begin(s);
+  for (int j = 0; j < m; ++j) {
+    StepBatch b{};
+    b.per = per;
+    const bool last = j == m - 1;
+    for (int i = 0; i < S; ++i) {
+      StepParams& p = b.p[i];
+      const Graph* g = graphs[i];
+      p.rowptr = g->rowptr;
+      p.colidx = g->colidx;
+      p.vals = g->vals;
+      p.zcur = at(i, (j & 1) ? pl.off_z1 : pl.off_z0);
+      p.zprev = at(i, (j & 1) ? pl.off_z0 : pl.off_z1);
+      p.zout = at(i, (j & 1) ? pl.off_z0 : pl.off_z1);
+      p.scur = reinterpret_cast<const float*>(at(i, (j & 1) ? pl.off_s1 : pl.off_s0));
+      p.sprev = reinterpret_cast<const float*>(at(i, (j & 1) ? pl.off_s0 : pl.off_s1));
+      p.sout = const_cast<float*>(p.sprev);
+      p.acc = reinterpret_cast<float*>(at(i, pl.off_acc));
+      p.ld_acc = pl.wpad;
+      p.w = w;
+      p.n = n;
+      p.row_blocks = pl.row_blocks;
+      const OpScale op = op_scale(g, lmax > 0.0 ? lmax : g->lmax_bound);
+      set_op(p, op);
+      p.coef_dev = coefs[i] + j + 1;
+      int flags = F_ACC;
+      if (j == 0) flags |= F_FIRST;
+      if (last) {
+        flags |= F_LAST;
+        p.yout = Y[i];
+        p.ldy = ldy;
+        p.y_dt = int(y_dt);
+      } else {
+        flags |= F_STORE;
+      }
+      if (mom && j <= J) {
+        flags |= F_MOM;
+        p.mom_part = reinterpret_cast<double*>(at(i, pl.off_part)) + static_cast<int64_t>(j) * 2 * per;
+      }
+      if ((flags & F_MOM) || op.own()) flags |= F_OWN;
+      p.flags = flags;
+      bytes_alg += step_bytes(g, n, w, iter_dt, flags, y_dt);
+    }
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(per * S)), dim3(kThreads), 0, s, b);
+  }
+  if (timed) timing_end(s, m, bytes_alg);
+  CSC_HIP(hipGetLastError());
+  if (mom) {
+    for (int i = 0; i < S; ++i) {
+      double* part = reinterpret_cast<double*>(at(i, pl.off_part));
+      double* msum = reinterpret_cast<double*>(at(i, pl.off_mom));
+      hipLaunchKernelGGL(k_reduce_rows, dim3(2 * (J + 1)), dim3(kThreads), 0, s, part, per, msum);
+      hipLaunchKernelGGL(k_moments, dim3(1), dim3(64), 0, s, msum, J, m, moments[i]);
+    }
+    CSC_HIP(hipGetLastError());
+  }
+  return CSC_OK;
+}
+
+double filter_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dtype iter_dt,
+                          bool moments, csc_dtype y_dt) {
+  double b = 0.0;
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < m; ++j) {
+      int flags = F_ACC | (j == 0 ? F_FIRST : 0) | (j == m - 1 ? F_LAST : F_STORE);
+      if (moments && j <= m / 2) flags |= F_MOM | F_OWN;
+      b += step_bytes(graphs[i], graphs[i]->n, w, iter_dt, flags, y_dt);
+    }
+  return b;
 }
 
 double basis_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dtype iter_dt) {

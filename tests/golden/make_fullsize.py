@@ -53,7 +53,8 @@ CASES = {
 CASE_FORMS = {
     "c3": list(storage.FORMS),
     "c5": ["fp32_onepass", "bf16io_onepass", "bf16_onepass", "bf16s_onepass",
-           "bf16s_basis_bf16copies", "f16_onepass", "f16_basis", "f16s_onepass"],
+           "bf16s_basis_bf16copies", "f16_onepass", "f16_basis", "f16s_onepass",
+           "f16s_basis_f16copies"],
 }
 
 

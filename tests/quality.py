@@ -13,8 +13,12 @@ signals R, three checks:
     equality ||Psi - Phi I Q||_F = ||Sigma - I||_F (Sigma the singular values of U_k^T R):
     C <= C_Phi + 2 (||Psi~ - Psi||_F + ||Sigma - I||_F).
   * the assignment is as good as the oracle's static CSC on the same signals: C <= C_oracle +
-    0.05 (features of another precision can lead Lloyd to another local optimum of nearly the
-    same cost; the wrong assignments below cost at least 0.35 more than SC's 0.67 on C1).
+    0.05.  Thm 3.1 speaks of optimal k-means; both sides approximate it by the best of
+    RESTARTS seeded k-means++ + 20 Lloyd runs (lowest k-means objective on the features),
+    because a single run can stop in a local optimum that merges two clusters (C near 1.1
+    instead of 0.67 on C1) on features of either precision.  Features of another precision
+    can still reach another optimum of nearly the same cost, hence the slack; the wrong
+    assignments below cost at least 0.35 more than SC's 0.67 on C1.
 A random labelling, two clusters merged, or half of a cluster moved fails at least one.
 """
 
@@ -27,6 +31,7 @@ from workloads import sbm, seed_for
 
 K = 5
 M = 50
+RESTARTS = 8
 
 
 def c1_graph():
@@ -54,13 +59,23 @@ def signals(n: int, d: int, store: str) -> np.ndarray:
                       dtype=np.float64)
 
 
+def kmeans_stream(r: int) -> int:
+    """Philox stream of the k-means++ uniforms of restart r (both sides)."""
+    return 2 + 16 * r
+
+
 def oracle_csc(A, lam_c: float, R: np.ndarray):
-    """Static CSC in the oracle: filter at lam_c, k-means++ (Philox stream 2) + 20 Lloyd."""
+    """Static CSC in the oracle: filter at lam_c, then the best (lowest objective) of RESTARTS
+    runs of k-means++ (Philox streams kmeans_stream(r)) + 20 Lloyd rounds."""
     a = chebyshev.step_coefficients(M, 2.0, lam_c, "jackson")
     Y = chebyshev.filter_recurrence(A, 2.0, a, R)
-    u = philox.uniforms(K, seed_for(1, "kmeans"), 2)
-    lab, _, _ = kmeans.lloyd(Y, Y[kmeans.kmeanspp(Y, K, u)], 20)
-    return Y, lab
+    best, best_obj = None, np.inf
+    for r in range(RESTARTS):
+        u = philox.uniforms(K, seed_for(1, "kmeans"), kmeans_stream(r))
+        lab, _, obj = kmeans.lloyd(Y, Y[kmeans.kmeanspp(Y, K, u)], 20)
+        if obj[-1] < best_obj:
+            best, best_obj = lab, obj[-1]
+    return Y, best
 
 
 def bounds(U, C_phi: float, R: np.ndarray, features: np.ndarray):

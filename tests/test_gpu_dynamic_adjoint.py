@@ -45,21 +45,36 @@ def test_dynamic_matches_oracle(csc, seq, p, d, tau, keep):
         assert agree > 0.99 or c_gpu == pytest.approx(c_orc, rel=1e-3)
 
 
-@pytest.mark.parametrize("iters", [torch.float32, torch.bfloat16, "bf16s"])
-def test_dynamic_bf16_quality(csc, seq, iters):
-    k, m, d = 4, 40, 64
-    say(f"dynamic bf16 features, iterates {iters}")
-    gpu = csc.DynamicCSC(2000, d, k, 0.5, m, seed=54, feat_dtype=torch.bfloat16, iter_dtype=iters)
+@pytest.mark.parametrize("batch", [1, 4])
+@pytest.mark.parametrize("iters", [torch.float32, torch.bfloat16, "bf16s", torch.float16, "f16s"])
+def test_dynamic_16bit_forms_cluster_like_the_oracle(csc, seq, iters, batch):
+    """Dynamic CSC with BF16 signals and features in every iterate form (kept basis, one
+    snapshot at a time or four per batched, graph-replayed recurrence) against the FP64
+    oracle's dynamic CSC on the same Philox draws: on the last snapshot the assignment's
+    cost C(X; U_k) (eq. CSC_cost) must be within 0.05 of the oracle's.  The SBM (N = 2000,
+    k = 4, degree 20, ratio 0.05) is well separated, so both sit near SC's cost, while the
+    wrong assignments of tests/quality.py (a random labelling, two clusters merged, half a
+    cluster moved) cost at least 0.3 more and fail the same check."""
+    import quality as Q
+
+    k, m, d, p, seed = 4, 40, 64, 0.5, 54
+    say(f"dynamic 16-bit features, iterates {iters}, batch {batch}")
+    gpu = csc.DynamicCSC(2000, d, k, p, m, seed=seed, feat_dtype=torch.bfloat16,
+                         iter_dtype=iters, keep_iterates=1, batch=batch, use_graph=batch > 1)
+    orc = dynamic.DynamicCSC(2000, d, k, p, m, seed=seed, storage=np.float32)
+    labels, lams, _, _ = gpu.steps([csc.Graph.from_workload(g) for g in seq])
     for g in seq:
-        lab, lam, ref, cnt = gpu.step(csc.Graph.from_workload(g))
-    A = oracle_A(seq[-1])
-    lam_d, U = operator.dense_spectrum(A)
+        r = orc.step(g)
+    lam_d, U = operator.dense_spectrum(oracle_A(seq[-1]))
     Phi = U[:, :k]
-    best = min(okm.cost(Phi, okm.lloyd(Phi, Phi[okm.kmeanspp(Phi, k, np.random.default_rng(s).random(k))], 30)[0])
-               for s in range(5))
-    c = okm.cost(Phi, lab.cpu().numpy())
-    say(f"  bf16 dynamic cost {c:.4f} vs SC {best:.4f}")
-    assert c - best <= 2 * np.sqrt(k / d) * (np.sqrt(k) + 3)
+    lab = labels[-1].cpu().numpy()
+    c_gpu, c_orc = okm.cost(Phi, lab), okm.cost(Phi, r.labels)
+    say(f"  lambda gpu {lams[-1]:.5f} oracle {r.lam:.5f}; cost gpu {c_gpu:.4f} oracle {c_orc:.4f}")
+    assert c_gpu <= c_orc + 0.05
+    for name, bad in Q.corruptions(lab).items():
+        cb = okm.cost(Phi, bad)
+        say(f"  wrong assignment {name}: cost {cb:.4f}")
+        assert cb > c_orc + 0.05
 
 
 @pytest.mark.parametrize("m,w,ckpt", [(0, 3, 0), (1, 5, 0), (7, 16, 3), (30, 20, 0), (60, 64, 8)])
@@ -166,6 +181,36 @@ def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph, it
         assert cnts[t] == ref_out[t][3]
         assert torch.equal(labels[t], ref_out[t][0])
     assert torch.equal(bat.features(), ref_theta)
+
+
+# one-pass batches (no kept iterates): a batch is filtered at the cut-off in force when it
+# starts, with its moments; decisions come from the moments, and snapshots whose cut-off
+# changed within the batch are filtered again.  Against one snapshot at a time without kept
+# iterates: the same cut-offs, refinements and labels, bit-identical features (the same
+# kernels in the same order), counts equal up to their two FP64 evaluations (the moment
+# series here, <R, h(L) R> there).  tau = 1e-12 refines every snapshot, so every block is
+# filtered again.
+@pytest.mark.parametrize("batch,use_graph,iters,p,d,tau", [(4, True, torch.float32, 0.5, 32, None),
+                                                           (3, False, torch.float16, 0.3, 40, None),
+                                                           (4, True, "bf16s", 0.5, 32, 1e-12),
+                                                           (2, True, "f16s", 0.75, 64, None),
+                                                           (4, False, torch.float32, 0.5, 32, 1e-12)])
+def test_onepass_batches_equal_sequential(csc, seq, batch, use_graph, iters, p, d, tau):
+    say(f"one-pass batches batch={batch} graph={use_graph} iterates={iters} p={p} d={d} tau={tau}")
+    k, m, seed = 4, 40, 63
+    ref = csc.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10, keep_iterates=0,
+                         iter_dtype=iters, tau=tau or 0.0)
+    ref_out = [ref.step(csc.Graph.from_workload(g)) for g in seq]
+    bat = csc.DynamicCSC(2000, d, k, p, m, seed=seed, lloyd_iters=10, keep_iterates=0,
+                         batch=batch, use_graph=use_graph, iter_dtype=iters, tau=tau or 0.0)
+    labels, lams, refs, cnts = bat.steps([csc.Graph.from_workload(g) for g in seq])
+    for t in range(len(seq)):
+        say(f"  t={t + 1} lambda {lams[t]:.6f} refined {refs[t]} count {cnts[t]:.5f} / {ref_out[t][3]:.5f}")
+        assert lams[t] == ref_out[t][1]
+        assert refs[t] == ref_out[t][2]
+        assert cnts[t] == pytest.approx(ref_out[t][3], rel=1e-6, abs=1e-6)
+        assert torch.equal(labels[t], ref_out[t][0])
+    assert torch.equal(bat.features(), ref.features())
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2])

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import quality as Q
-from oracle import eigcount, kmeans
+from oracle import chebyshev, eigcount, kmeans
 from helpers import say
 
 pytestmark = pytest.mark.gpu
@@ -23,6 +23,8 @@ FORMS = {  # features, iterates, operator values
     "bf16io": (torch.bfloat16, torch.float32, torch.bfloat16),
     "bf16s": (torch.bfloat16, "bf16s", torch.bfloat16),
     "bf16": (torch.bfloat16, torch.bfloat16, torch.bfloat16),
+    "f16": (torch.bfloat16, torch.float16, torch.bfloat16),
+    "f16s": (torch.bfloat16, "f16s", torch.bfloat16),
 }
 
 
@@ -53,12 +55,23 @@ def test_static_csc_quality(csc, c1, form, d, cut):
         lam_c, cnt, _, _ = csc.eigcount(G, Q.M, R, sigma2=1.0 / d, k=Q.K, n_cand=16, iter_dtype=iters)
         mu = eigcount.moments_direct(A, 2.0, Q.M, Rn)
         lam_o, cnt_o, _ = eigcount.eigcount_bisect(mu, Q.M, 2.0, "jackson", 1.0 / d, d, Q.K, 16, 0.0, 2.0)
-        say(f"  dichotomy: GPU {lam_c:.6f} (count {cnt:.3f}), oracle {lam_o:.6f} (count {cnt_o:.3f})")
-        assert abs(lam_c - lam_o) <= 2.0 ** -15
+        # the oracle's count at the GPU's cut-off: the two dichotomies take the same decisions
+        # unless the count at a midpoint is within the form's rounding of k, which happens on
+        # the plateau between lambda_5 and lambda_6 where the count stays within 1e-3 of k; a
+        # cut-off found there is as valid as the oracle's
+        a_g = chebyshev.step_coefficients(Q.M, 2.0, lam_c, "jackson")
+        c_at = eigcount.count_from_moments(a_g, mu, 1.0 / d, d)
+        say(f"  dichotomy: GPU {lam_c:.6f} (count {cnt:.3f}, oracle's count there {c_at:.4f}), "
+            f"oracle {lam_o:.6f} (count {cnt_o:.3f})")
+        assert abs(lam_c - lam_o) <= 2.0 ** -15 or (abs(c_at - Q.K) <= 1e-2 and abs(cnt_o - Q.K) <= 1e-2)
     a = csc.cheb_coeffs(Q.M, 2.0, lam_c)
     Y = csc.cheb_filter(G, a, R, out_dtype=feat, iter_dtype=iters)
-    labels, _ = csc.kmeans(Y, Q.K, iters=20, seed=Q.seed_for(1, "kmeans"), stream_id=2)
-    lab = labels.cpu().numpy()
+    lab, best = None, np.inf
+    for r in range(Q.RESTARTS):
+        labels, _, obj = csc.kmeans(Y, Q.K, iters=20, seed=Q.seed_for(1, "kmeans"),
+                                    stream_id=Q.kmeans_stream(r), objective=True)
+        if obj[-1] < best:
+            lab, best = labels.cpu().numpy(), obj[-1]
     F = Y.double().cpu().numpy()
     _, lab_o = Q.oracle_csc(A, lam_c, Rn)
     Phi = U[:, :Q.K]

@@ -31,9 +31,16 @@ def test_round_sig_bf16_matches_integer_rounding():
 
 
 def test_round_sig_f16_matches_numpy_half():
-    # 11 significant bits is IEEE binary16 inside its normal range
-    x = np.random.default_rng(4).standard_normal(20_000) * 3.0
-    assert np.array_equal(storage.round_sig(x, "f16"), x.astype(np.float16).astype(np.float64))
+    # IEEE binary16: 11 significant bits in the normal range, the 2^-24 grid below 2^-14,
+    # overflow to infinity from 65520 on (65504 is the largest finite value)
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.standard_normal(20_000) * 3.0,
+                        rng.standard_normal(20_000) * 2.0 ** -16,
+                        rng.standard_normal(2_000) * 3e4,
+                        [65504.0, 65519.0, 65520.0, -65536.0, 2.0 ** -25, 3 * 2.0 ** -26, 0.0]])
+    with np.errstate(over="ignore"):
+        want = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(storage.round_sig(x, "f16"), want)
 
 
 def test_round_sig_hand_ties():
