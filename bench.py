@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--init", choices=["pp", "warm"], default="pp",
                     help="k-means start per snapshot: k-means++ (pp) or the previous labels' means")
     ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ckm", "psweep"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ckm", "psweep", "kassign", "gather"],
+                    default="c3")
     ap.add_argument("--ps", default="0,0.25,0.5,0.75", help="psweep: reused fractions p")
     ap.add_argument("--n-sample", type=int, default=0,
                     help="ckm: sampled nodes (0: ceil(4 k ln k))")
@@ -71,6 +72,8 @@ def parse():
         args.n, args.k, args.d, args.m = 200_000, 20, 64, 100
     if args.workload == "c4" and "--n" not in sys.argv:
         args.n, args.k, args.d, args.m = 200_000, 20, 64, 60
+    if args.workload == "kassign" and "--n" not in sys.argv:
+        args.n, args.k, args.d = 8_000_000, 200, 256
     return args
 
 
@@ -105,7 +108,15 @@ FORMS = {
               "the f16s form with the fresh blocks of --batch snapshots filtered in one batched "
               "recurrence replayed from a HIP graph"),
 }
+for _f in ("fp32", "f16", "f16s", "bf16s"):
+    _b = FORMS[_f]
+    FORMS[_f + "b1p"] = (_b[0], _b[1], _b[2], True, True,
+                         f"the {_f} form with the fresh blocks of --batch snapshots filtered in one "
+                         f"batched one-pass recurrence (FP32 running sum, no kept iterates) replayed "
+                         f"from a HIP graph; snapshots whose cut-off changed are filtered again")
 SPLIT_MODES = ("bf16s", "f16s")
+# forms that keep no iterates (one-pass recurrences)
+ONEPASS = {f for f in FORMS if f.endswith("b1p")}
 
 
 def torch_types(form):
@@ -180,7 +191,8 @@ def main():
     if args.probe:
         return run_probe(args)
     {"c3": run_dynamic, "c5": run_dynamic, "c2": run_static, "c4": run_adjoint,
-     "ckm": run_compressive, "psweep": run_psweep}[args.workload](args)
+     "ckm": run_compressive, "psweep": run_psweep, "kassign": run_kassign,
+     "gather": run_gather}[args.workload](args)
 
 
 def run_probe(args):
@@ -288,7 +300,8 @@ def _time_form(args, form, p, resident, cap, cid):
     variant = G.autotune(qd, iter_dtype=iters)
     dyn = csc.DynamicCSC(args.n, args.d, args.k, p, args.m, seed=seed_for(cid, "signals"),
                          feat_dtype=feat, iter_dtype=iters, batch=args.batch if batched else 1,
-                         use_graph=graph, keep_iterates=1 if batched else -1, variant=variant,
+                         use_graph=graph, variant=variant,
+                         keep_iterates=0 if form in ONEPASS else (1 if batched else -1),
                          init=1 if args.init == "warm" else 0)
     labels = torch.empty(args.n, dtype=torch.int32, device=dev)
     _, lam, ref, cnt = dyn.step(G, labels)
@@ -429,6 +442,58 @@ def timed_path_errors(args, gl, T, cid, forms):
     return errors, cpu
 
 
+def golden_errors(args, resident, cap, forms):
+    """Per form: snapshot 2's fresh block (4 columns, 10k rows) filtered by a dynamic state in
+    the form's configuration with the cut-off fixed through an imported state, against the
+    committed FP64 expected values and storage floors of the C5 case."""
+    import numpy as np
+    import torch
+
+    import paper_1706_03591_amd as csc
+    from workloads import seed_for
+
+    gdir = os.path.join(ROOT, "tests", "golden")
+    with open(os.path.join(gdir, "c5_floors.json")) as f:
+        meta = json.load(f)
+    gold = np.load(os.path.join(gdir, "c5_fullsize.npz"))
+    lam = meta["cutoffs"][0]
+    rows, cols = gold["rows"], gold["cols"]
+    seed = seed_for(5, "signals")
+    qd = int(round((1 - args.p) * args.d))
+    floor_of = {"fp32": "fp32_onepass", "bf16s": "bf16s_basis_bf16copies", "f16": "f16_basis",
+                "f16s": "f16s_basis_f16copies", "f16b1p": "f16_onepass", "f16sb1p": "f16s_onepass",
+                "bf16sb1p": "bf16s_onepass", "fp32b1p": "fp32_onepass", "bf16": "bf16_basis",
+                "bf16io": "bf16io_onepass"}
+    errors = {}
+    for form in forms:
+        feat, iters, vals = torch_types(form)
+        batched = FORMS[form][3]
+        keep = 0 if form in ONEPASS else (1 if batched else -1)
+        G = csc.Graph(args.n, *resident[1], val_dtype=vals, validate=False, nnz_capacity=cap)
+        st = csc.DynamicCSC(args.n, args.d, args.k, args.p, args.m, seed=seed, feat_dtype=feat,
+                            iter_dtype=iters, tau=1e9, keep_iterates=keep,
+                            batch=args.batch if batched else 1, use_graph=FORMS[form][4],
+                            lloyd_iters=1)
+        buf = bytearray(csc.lib.csc_dyn_state_bytes(st.h))
+        h = csc.DynamicCSC.header(buf)
+        h.magic, h.n, h.d, h.k, h.m, h.qd = 0x31304E5944435343, args.n, args.d, args.k, args.m, qd
+        h.feat_dt, h.t, h.cursor, h.seed, h.lam = (0 if feat == torch.float32 else 1), 1, 0, seed, lam
+        st.import_state(buf)
+        _, lams, _, _ = st.steps([G])
+        th = st.features()
+        got = th.index_select(0, torch.from_numpy(rows).cuda()).index_select(
+            1, torch.from_numpy(cols).cuda()).double().cpu().numpy()
+        del th, st, G
+        torch.cuda.empty_cache()
+        ref = gold[f"ref_{lam}_{'f32' if feat == torch.float32 else 'bf16'}"]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        fl = meta["floors"].get(f"{floor_of.get(form, '')}@{lam}")
+        errors[form] = dict(rel_fro_vs_fp64=err, cut_off=lam, snapshot=2, storage_floor=fl,
+                            source="tests/golden/c5_fullsize.npz (10k rows x 4 columns)")
+        log(f"[bench] {form}: error {err:.3e} of the output at cut-off {lam} (snapshot 2; floor {fl})")
+    return errors
+
+
 def run_dynamic(args):
     import numpy as np
     import torch
@@ -464,7 +529,13 @@ def run_dynamic(args):
     # oracle runs double as the CPU baseline
     errors, cpu = {}, None
     if not args.no_error:
-        errors, cpu = timed_path_errors(args, seq[-1], T, cid, forms)
+        if args.workload == "c5":
+            # the oracle over 8M nodes and 160M entries takes minutes per cut-off even on all
+            # host cores, so at C5 each form filters snapshot 2's fresh block at the fixed
+            # cut-off of the committed expected values (tests/golden/make_fullsize.py)
+            errors = golden_errors(args, resident, cap, forms)
+        else:
+            errors, cpu = timed_path_errors(args, seq[-1], T, cid, forms)
     head = forms[args.headline]
     traffic = load_traffic(digest, args.headline, args.workload)
     achieved = head["step_kernel_gbps"]
@@ -736,6 +807,149 @@ def run_compressive(args):
            "agreement_with_full": round(float(conf.max(axis=1).sum() / args.n), 5),
            "nmi_vs_planted": {"full": round(float(normalized_mutual_info_score(g.labels, lf)), 5),
                               "compressive": round(float(normalized_mutual_info_score(g.labels, lc)), 5)}})
+
+
+def run_kassign(args):
+    """The k-means assignment at C5's shape (Sec. 2.1, eq. SC_cost): N = 8M BF16 rows of
+    d = 256 columns against k = 200 FP32 centroids.  The rows are a seeded synthetic mixture
+    (k centres of N(0, 1) entries, each row its centre plus N(0, 1) noise, rounded to BF16);
+    the centroids are k rows of it.  A step is one assignment call; the whole k-means
+    (k-means++ and 20 Lloyd rounds) is timed too.  The roofline compares the rows' bytes per
+    call with HBM peak and the split-precision cross products with BF16 matrix-core peak."""
+    import torch
+
+    import paper_1706_03591_amd as csc
+
+    n, d, k = args.n, args.d, args.k
+    gen = torch.Generator(device="cuda").manual_seed(20171105)
+    centers = torch.randn((k, d), generator=gen, device="cuda")
+    lab = torch.randint(0, k, (n,), generator=gen, device="cuda")
+    F = torch.empty((n, d), dtype=torch.bfloat16, device="cuda")
+    for r0 in range(0, n, 1 << 20):
+        r1 = min(n, r0 + (1 << 20))
+        F[r0:r1] = (centers[lab[r0:r1]] + torch.randn((r1 - r0, d), generator=gen, device="cuda")).to(torch.bfloat16)
+    del lab
+    Cc = F[torch.randperm(n, generator=gen, device="cuda")[:k]].float().contiguous()
+    # as k-means calls it: labels only (no per-row distances)
+    for _ in range(args.warmup):
+        csc.kmeans_assign(F, Cc, best_d2=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        csc.kmeans_assign(F, Cc, best_d2=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    t0 = time.perf_counter()
+    csc.kmeans(F, k, 20, seed=7, stream_id=2)
+    torch.cuda.synchronize()
+    km_ms = (time.perf_counter() - t0) * 1e3
+    kp = (k + 15) // 16 * 16
+    flops = 2.0 * n * kp * d * 3  # hi x hi plus the two small cross products per 32-column step
+    gbps = n * d * 2 / (ms * 1e-3) / 1e9
+    log(f"[bench] assignment {ms:.3f} ms ({gbps:.0f} GB/s of rows, {flops / (ms * 1e-3) / 1e12:.0f} "
+        f"TFLOP/s of split products); k-means++ + 20 Lloyd rounds {km_ms:.1f} ms")
+    _line(args, "k-means assignment at C5 shape: ms per call", ms, "ms", ms,
+          {"higher_is_better": False, "dtype": "bf16 rows, fp32 centroids (split bf16 products)",
+           "config": {"workload": f"synthetic BF16 mixture N={n}, d={d}, k={k}; one assignment call",
+                      "n": n, "d": d, "k": k},
+           "roofline": {"bound": "hbm", "kernel": "k_assign_mf (BF16 rows, two row tiles)",
+                        "achieved": round(gbps, 1), "peak": PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(gbps / PEAK_GBPS, 4), "traffic": None,
+                        "mfma_tflops": round(flops / (ms * 1e-3) / 1e12, 1),
+                        "mfma_frac_bf16_dense": round(flops / (ms * 1e-3) / 2.5e15, 4)},
+           "kmeans_20_lloyd_ms": round(km_ms, 2)})
+
+
+def run_gather(args):
+    """Ceiling of the recurrence step's neighbour gathers (csc_gather_probe: the step kernel's
+    gather loop with nothing else).  On the CSR of C3's first snapshot (N = 1M, 16M entries)
+    with 128-byte rows (64 binary16 or BF16 columns, the f16 step's tile), and on random
+    patterns of degree 16 over 1M rows whose columns address tables of 1M or 4M rows of 64 to
+    512 bytes (64 MB to 2 GB: inside and beyond the 256 MB MALL).  Rates count the requested
+    bytes, nnz x row bytes.  The f16 step kernel on the same C3 CSR is timed beside it."""
+    import numpy as np
+    import torch
+
+    import paper_1706_03591_amd as csc
+
+    dev = torch.device("cuda")
+    seq, _ = build_sequence(args, 1)
+    g = seq[0]
+
+    def timed(fn, reps=None):
+        reps = reps or args.steps
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    def probe(rowptr, colidx, n_table, row_bytes):
+        # host-side checks of what the kernel assumes before it runs
+        assert rowptr[0] == 0 and np.all(np.diff(rowptr) >= 0) and rowptr[-1] == len(colidx)
+        assert colidx.min() >= 0 and colidx.max() < n_table
+        rp = torch.from_numpy(rowptr.astype(np.int32)).to(dev)
+        ci = torch.from_numpy(colidx.astype(np.int32)).to(dev)
+        table = torch.randint(0, 1 << 30, (n_table * row_bytes // 4,), dtype=torch.int32, device=dev)
+        out = torch.empty((len(rowptr) - 1) * (row_bytes // 16), dtype=torch.int32, device=dev)
+        t = timed(lambda: csc.gather_probe(rp, ci, table, row_bytes, out))
+        req = len(colidx) * row_bytes
+        del table, out
+        torch.cuda.empty_cache()
+        return t, req / t / 1e12
+
+    rows = []
+    t_c3, tb_c3 = probe(g.rowptr, g.colidx, g.n, 128)
+    rows.append(dict(pattern="C3 snapshot 1", n_rows=g.n, nnz=g.nnz, n_table=g.n, row_bytes=128,
+                     table_mb=g.n * 128 / 2**20, us=round(t_c3 * 1e6, 1), tb_s=round(tb_c3, 3)))
+    log(f"[bench] gather probe, C3 CSR, 128-byte rows: {t_c3 * 1e6:.1f} us, {tb_c3:.2f} TB/s requested")
+    rng = np.random.default_rng(20171106)
+    n_rows, deg = 1_000_000, 16
+    rowptr = np.arange(n_rows + 1, dtype=np.int64) * deg
+    for n_table in (1_000_000, 4_000_000):
+        colidx = np.sort(rng.integers(0, n_table, size=(n_rows, deg)), axis=1).ravel()
+        for rb in (64, 128, 256, 512):
+            t, tb = probe(rowptr, colidx, n_table, rb)
+            rows.append(dict(pattern="uniform random, degree 16", n_rows=n_rows, nnz=n_rows * deg,
+                             n_table=n_table, row_bytes=rb, table_mb=n_table * rb / 2**20,
+                             us=round(t * 1e6, 1), tb_s=round(tb, 3)))
+            log(f"[bench] gather probe, random, table {n_table} x {rb} B ({n_table * rb / 2**20:.0f} MB): "
+                f"{t * 1e6:.1f} us, {tb:.2f} TB/s requested")
+    # the f16 step kernel on the C3 CSR (64 columns, m steps, timed by the library's events)
+    G = csc.Graph.from_workload(g, val_dtype=torch.bfloat16)
+    X = csc.randn(g.n, 64, 7, 1, sigma=0.125, dtype=torch.bfloat16)
+    a = csc.cheb_coeffs(args.m, 2.0, 0.4)
+    G.set_variant(1, torch.float16)  # one 64-column tile: 128-byte rows
+    csc.cheb_filter(G, a, X, out_dtype=torch.bfloat16, iter_dtype=torch.float16)
+    torch.cuda.synchronize()
+    csc.timing_reset()
+    csc.timing_enable(True)
+    for _ in range(3):
+        csc.cheb_filter(G, a, X, out_dtype=torch.bfloat16, iter_dtype=torch.float16)
+    torch.cuda.synchronize()
+    kms, launches, kbytes = csc.timing_read()
+    csc.timing_enable(False)
+    step_us = kms / launches * 1e3
+    gather_req = g.nnz * 128
+    step_tb = gather_req / (step_us * 1e-6) / 1e12
+    log(f"[bench] f16 one-pass step on the same CSR: {step_us:.1f} us per step; its gathers alone "
+        f"would take {t_c3 * 1e6:.1f} us at the probe's rate")
+    _line(args, "random-gather ceiling: requested TB/s of 128-byte neighbour rows on the C3 CSR",
+          tb_c3, "TB/s", t_c3 * 1e3,
+          {"config": {"workload": "csc_gather_probe on C3 snapshot 1 (N=1M, 16M entries) and random "
+                                  "degree-16 patterns; tables of 64-512-byte rows",
+                      "n": g.n, "nnz": g.nnz},
+           "sweep": rows,
+           "f16_step": {"us_per_step": round(step_us, 1), "gather_requested_tb_s": round(step_tb, 3),
+                        "algorithmic_bytes_per_step": round(kbytes / launches),
+                        "gather_share_of_probe_time": round(t_c3 * 1e6 / step_us, 3)}})
 
 
 if __name__ == "__main__":

@@ -231,16 +231,19 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  * float[k * d], row-major).  For d <= 256 and 16-byte aligned rows the scores
  * ||C_c||^2 - 2 F_i.C_c are formed on the matrix cores from exact BF16 splits of C (three
  * parts) and of FP32 rows (three parts; BF16 rows are exact): each 32-column step's leading
- * product goes to a fresh FP32 accumulator that is added in FP64, and the small cross
- * products to an FP32 sum, so each score is within 2 * 40 * 2^-24 ||F_i|| ||C_c|| (plus FP64
- * rounding) of its exact value.  A row with one centroid whose interval can hold the
+ * product goes to a fresh FP32 accumulator, the steps are summed in FP32, and the small cross
+ * products to a second FP32 sum, so each score is within 2 * 48 * 2^-24 ||F_i|| ||C_c|| (plus
+ * FP64 rounding) of its exact value.  A row with one centroid whose interval can hold the
  * minimum is decided; with two, both are re-scored in the FP64 direct form; with more, every
  * centroid is.  Otherwise (d > 256 or unaligned rows) candidates are ranked in FP32 and the
  * two best re-scored in FP64.  Exact ties go to the lowest index.  labels: device
  * int32[n]; best_d2: device float[n] (the FP64 squared distance to the chosen centroid,
- * rounded) or NULL.  The split centroids live in a library-owned buffer of the current
- * device, grown on demand (the growth allocates, and waits for the device), so concurrent
- * calls on one device race.  Asynchronous.
+ * rounded) or NULL.  sums (device float[k * d]) and counts (device int32[k]), each
+ * optional: the Lloyd partial sums of the new assignment, sums[c] = the sum of the rows
+ * labelled c (accumulated in 64-bit fixed point, exact up to the fixed-point scale, then
+ * rounded once to FP32) and counts[c] their number; they take a second pass over F.  work:
+ * csc_kmeans_workspace_bytes(n, d, k) bytes (the split centroids and the sums live there).
+ * Asynchronous.
  *
  * csc_kmeans_update: C[c] = mean of the rows labelled c; an empty cluster keeps its
  * previous centroid (C is read and overwritten); rows whose label is outside [0, k) are
@@ -261,6 +264,7 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
 size_t csc_kmeans_workspace_bytes(int64_t n, int d, int k);
 csc_status csc_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                              const float* C, int k, int32_t* labels, float* best_d2,
+                             float* sums, int32_t* counts, void* work, size_t work_bytes,
                              void* stream);
 csc_status csc_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                              const int32_t* labels, int k, float* C, int32_t* counts,
@@ -413,6 +417,19 @@ csc_status csc_dyn_destroy(csc_dyn st);
  * ckpt_every).  Asynchronous.  Defined for the normalized Laplacian; a combinatorial
  * graph returns CSC_E_ARG.
  */
+/* Chain of the adjoint from A's entries to the edge weights (Sec. 2.1: A = D^{-1/2} W
+ * D^{-1/2} with d = W 1; normalized Laplacian only, CSC_E_ARG otherwise).  dA: device
+ * float[nnz], dl/dA_e per stored entry as csc_cheb_filter_backward returns it.  dW: device
+ * double[nnz], the derivative with respect to the symmetric weight of each entry's edge
+ * (the same value on (i, j) and (j, i)): with s = D^{-1/2}, q_i = sum over the entries e of
+ * row i of dA_e A_e + dA_m(e) A_m(e) (m(e) the mirror entry) and
+ * g_ij = dA_ij s_i s_j - q_i s_i^2 / 2, dW_ij = g_ij + g_ji.  FP64 arithmetic on the stored
+ * values of A (BF16 values carry their rounding into q).  work: device scratch of
+ * csc_weight_grad_workspace_bytes(n) bytes.  Builds the mirror index on first use.
+ * Asynchronous. */
+size_t csc_weight_grad_workspace_bytes(int64_t n);
+csc_status csc_weight_grad(csc_graph g, const float* dA, double* dW, void* work,
+                           size_t work_bytes, void* stream);
 size_t csc_cheb_backward_workspace_bytes(int64_t n, int w, int m, int ckpt_every);
 csc_status csc_cheb_filter_backward(csc_graph g, double lmax, int m, const double* a,
                                     const float* X, int64_t ldx, const float* G, int64_t ldg,
@@ -431,6 +448,17 @@ csc_status csc_cheb_filter_backward(csc_graph g, double lmax, int m, const doubl
 csc_status csc_timing_enable(int on);
 csc_status csc_timing_reset(void);
 csc_status csc_timing_read(double* ms, int64_t* launches, double* bytes);
+
+/* Random-gather probe (a measurement aid, not a step of the method): the ceiling of the
+ * recurrence step's neighbour gathers on this memory system.  For the n_rows rows of a CSR
+ * pattern (rowptr: device int32[n_rows + 1], colidx: device int32[nnz]) and a table of rows
+ * of row_bytes bytes (64, 128, 256 or 512; device, 16-byte aligned), every row's group of
+ * row_bytes / 16 lanes reads the table rows its column indices name, 16 bytes per lane and
+ * eight loads in flight, as the step kernel does, and writes the XOR of what it read:
+ * out[r * (row_bytes / 16) + q] (device uint32).  The caller guarantees that every column
+ * index addresses a row of the table (nothing is checked on the device).  Asynchronous. */
+csc_status csc_gather_probe(const int32_t* rowptr, const int32_t* colidx, int64_t n_rows,
+                            const void* table, int row_bytes, uint32_t* out, void* stream);
 
 /* Kernel-shape selection for the recurrence step of graph g at width w: candidate row
  * groups and column tiles are timed on the device and the fastest is kept in the handle

@@ -12,9 +12,19 @@ and
     dl/dA   = -beta dl/dL~, read on A's stored entries (each directed entry its own
               parameter; lmax and the cut-off are held fixed).
 
+The chain to the edge weights (normalized Laplacian, Sec. 2.1: A = D^{-1/2} W D^{-1/2},
+d = W 1).  With s = d^{-1/2}, G_e = dl/dA_e and, for every node i,
+    q_i = sum over the stored entries e of row i of  G_e A_e + G_m(e) A_m(e)
+(m(e) the mirror entry (j, i) of e = (i, j)), an entry W_ij taken as its own parameter has
+    dl/dW_ij = G_ij s_i s_j - q_i s_i^2 / 2,
+because A_ab depends on W_ij directly (a = i, b = j) and through d_i (row i and column i of
+A).  The weight of an undirected edge {i, j} is one parameter stored twice, so its gradient
+is the sum over the pair: dl/dw_ij = dl/dW_ij + dl/dW_ji.
+
 Parity pins (tests/test_oracle_adjoint.py): central finite differences in FP64, the
 Daleckii-Krein divided-difference formula for the derivative of a matrix function, and
-dl/dX = h(L~)^T G.
+dl/dX = h(L~)^T G; for the weight chain, central finite differences of the loss through
+A(W) with both stored copies of an edge weight moved together.
 """
 
 from __future__ import annotations
@@ -52,3 +62,32 @@ def filter_backward(A: sp.csr_matrix, lmax: float, a: np.ndarray, X: np.ndarray,
         for j in range(1, m):
             dLt += 2.0 * np.einsum("ij,ij->i", Zb[j + 1][rows], Z[j][cols])
     return Zb[0], da, -beta * dLt
+
+
+def mirror_index(n, rowptr, colidx) -> np.ndarray:
+    """For every stored entry e = (i, j) of a structurally symmetric CSR pattern, the index of
+    the entry (j, i)."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colidx = np.asarray(colidx, dtype=np.int64)
+    nnz = int(rowptr[-1])
+    idx = sp.csr_matrix((np.arange(nnz, dtype=np.float64) + 1.0, colidx, rowptr), shape=(n, n))
+    T = idx.T.tocsr()  # entry (i, j) of T holds 1 + the index of (j, i)
+    T.sort_indices()
+    return (T.data - 1.0).astype(np.int64)
+
+
+def weight_gradient(n, rowptr, colidx, w, dA: np.ndarray) -> np.ndarray:
+    """dl/dw per stored entry of W (the same value on (i, j) and (j, i)) from dl/dA_e, for
+    the normalized Laplacian (module header)."""
+    from .operator import normalized_adjacency
+
+    A, s = normalized_adjacency(n, rowptr, colidx, w)
+    dA = np.asarray(dA, dtype=np.float64)
+    rows = np.repeat(np.arange(n), np.diff(np.asarray(rowptr, dtype=np.int64)))
+    cols = np.asarray(colidx, dtype=np.int64)
+    mir = mirror_index(n, rowptr, colidx)
+    ga = dA * A.data
+    q = np.zeros(n)
+    np.add.at(q, rows, ga + ga[mir])
+    g = dA * s[rows] * s[cols] - 0.5 * q[rows] * s[rows] ** 2
+    return g + g[mir]

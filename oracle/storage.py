@@ -80,13 +80,20 @@ def round_values(A: sp.csr_matrix, fmt) -> sp.csr_matrix:
     return sp.csr_matrix((round_sig(A.data, fmt), A.indices.copy(), A.indptr.copy()), shape=A.shape)
 
 
+def stored_operator(A: sp.csr_matrix, lmax: float, val="f64") -> sp.csr_matrix:
+    """L~ built from A's values rounded to `val` (what filter_stored multiplies by)."""
+    return scaled_laplacian(round_values(A, val), lmax)
+
+
 def filter_stored(A: sp.csr_matrix, lmax: float, a: np.ndarray, X: np.ndarray, *, val="f64",
                   state="f64", gather=None, combine="acc", acc="f64", basis="f64",
-                  out="f64") -> np.ndarray:
-    """Y = sum_j a_j T_j(L~) X with the roundings of one storage form (module header)."""
+                  out="f64", Lt=None) -> np.ndarray:
+    """Y = sum_j a_j T_j(L~) X with the roundings of one storage form (module header).
+    Lt: stored_operator(A, lmax, val), when the caller has it already (large graphs)."""
     if combine not in ("acc", "basis"):
         raise ValueError(combine)
-    Lt = scaled_laplacian(round_values(A, val), lmax)
+    if Lt is None:
+        Lt = stored_operator(A, lmax, val)
     dg = Lt.diagonal()[:, None]
     X = np.asarray(X, dtype=np.float64)
     gfmt = state if gather is None else gather

@@ -100,7 +100,7 @@ _SIGS = {
     "csc_randn": ([vp, i32, i64, i32, i64, i64, u64, u64, dbl, vp], i32),
     "csc_uniforms": ([vp, i32, u64, u64, vp], i32),
     "csc_kmeans_workspace_bytes": ([i64, i32, i32], sz),
-    "csc_kmeans_assign": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp], i32),
+    "csc_kmeans_assign": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp, vp, vp, sz, vp], i32),
     "csc_kmeans_update": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp, sz, vp], i32),
     "csc_kmeans_seed": ([vp, i32, i64, i64, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "csc_compressive_workspace_bytes": ([i64, i32, i32, i32], sz),
@@ -121,6 +121,9 @@ _SIGS = {
     "csc_cheb_backward_workspace_bytes": ([i64, i32, i32, i32], sz),
     "csc_cheb_filter_backward": ([vp, dbl, i32, pdbl, vp, i64, vp, i64, i32, vp, i64, vp, vp, i32,
                                   vp, sz, vp], i32),
+    "csc_weight_grad_workspace_bytes": ([i64], sz),
+    "csc_weight_grad": ([vp, vp, vp, vp, sz, vp], i32),
+    "csc_gather_probe": ([vp, vp, i64, vp, i32, vp, vp], i32),
     "csc_timing_enable": ([i32], i32),
     "csc_timing_reset": ([], i32),
     "csc_timing_read": ([pdbl, pi64, pdbl], i32),
@@ -437,13 +440,22 @@ def uniforms(count: int, seed: int, stream_id: int, stream=None) -> torch.Tensor
 # k-means
 
 
-def kmeans_assign(F: torch.Tensor, Cc: torch.Tensor, stream=None):
+def kmeans_assign(F: torch.Tensor, Cc: torch.Tensor, sums: bool = False, best_d2: bool = True,
+                  stream=None):
+    """(labels, best squared distances or None) and, with sums=True, also the Lloyd partial
+    sums (k x d float32) and counts (k int32) of the new assignment."""
     n, d = F.shape
     k = Cc.shape[0]
     labels = torch.empty(n, dtype=torch.int32, device=F.device)
-    best = torch.empty(n, dtype=torch.float32, device=F.device)
+    best = torch.empty(n, dtype=torch.float32, device=F.device) if best_d2 else None
+    S = torch.empty((k, d), dtype=torch.float32, device=F.device) if sums else None
+    cnt = torch.empty(k, dtype=torch.int32, device=F.device) if sums else None
+    ws = workspace(lib.csc_kmeans_workspace_bytes(n, d, k), F.device)
     _check(lib.csc_kmeans_assign(_ptr(F), _dt(F), _ld(F), n, d, _ptr(Cc.contiguous()), k,
-                                 _ptr(labels), _ptr(best), _stream(stream)))
+                                 _ptr(labels), _ptr(best), _ptr(S), _ptr(cnt), _ptr(ws),
+                                 ws.numel(), _stream(stream)))
+    if sums:
+        return labels, best, S, cnt
     return labels, best
 
 
@@ -647,3 +659,25 @@ def timing_read():
     ms, n, b = C.c_double(), C.c_int64(), C.c_double()
     _check(lib.csc_timing_read(C.byref(ms), C.byref(n), C.byref(b)))
     return ms.value, n.value, b.value
+
+
+def weight_gradient(g: "Graph", dA: torch.Tensor, stream=None) -> torch.Tensor:
+    """dl/dw per stored entry (float64, the symmetric edge weight's derivative, equal on both
+    copies of an edge) from dl/dA_e (float32, one per stored entry)."""
+    dW = torch.empty(dA.numel(), dtype=torch.float64, device=dA.device)
+    ws = workspace(lib.csc_weight_grad_workspace_bytes(g.n), dA.device)
+    _check(lib.csc_weight_grad(g.h, _ptr(dA.contiguous()), _ptr(dW), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+    return dW
+
+
+def gather_probe(rowptr: torch.Tensor, colidx: torch.Tensor, table: torch.Tensor, row_bytes: int,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The random-gather probe over a CSR pattern (int32 device tensors) and a table of rows
+    of row_bytes bytes; returns the per-lane XORs (uint32 as int32)."""
+    n = rowptr.numel() - 1
+    if out is None:
+        out = torch.empty(n * (row_bytes // 16), dtype=torch.int32, device=rowptr.device)
+    _check(lib.csc_gather_probe(_ptr(rowptr), _ptr(colidx), n, _ptr(table), int(row_bytes),
+                                _ptr(out), _stream(stream)))
+    return out

@@ -240,6 +240,15 @@ csc_status csc_graph_arrays(csc_graph h, const int32_t** rowptr, const int32_t**
   return CSC_OK;
 }
 
+size_t csc_weight_grad_workspace_bytes(int64_t n) { return align_up(static_cast<size_t>(std::max<int64_t>(n, 1)) * 8); }
+
+csc_status csc_weight_grad(csc_graph g, const float* dA, double* dW, void* work, size_t work_bytes,
+                           void* stream) {
+  if (!g || !dA || !dW) return fail(CSC_E_ARG, "null argument");
+  if (!work || work_bytes < csc_weight_grad_workspace_bytes(g->g.n)) return fail(CSC_E_ARG, "workspace too small");
+  return graph_weight_grad(&g->g, dA, dW, static_cast<double*>(work), as_stream(stream));
+}
+
 csc_status csc_graph_distance(csc_graph g1, csc_graph g2, double* rho, void* stream) {
   if (!g1 || !g2 || !rho) return fail(CSC_E_ARG, "null argument");
   hipStream_t s = as_stream(stream);
@@ -436,10 +445,12 @@ size_t csc_kmeans_workspace_bytes(int64_t n, int d, int k) { return kmeans_works
 
 csc_status csc_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                              const float* C, int k, int32_t* labels, float* best_d2,
+                             float* sums, int32_t* counts, void* work, size_t work_bytes,
                              void* stream) {
-  return launch_kmeans_assign(F, f_dt, ldf, n, d, C, k, labels, best_d2, nullptr,
-                              as_stream(stream));
+  return launch_kmeans_assign(F, f_dt, ldf, n, d, C, k, labels, best_d2, sums, counts, work,
+                              work_bytes, as_stream(stream));
 }
+
 
 csc_status csc_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                              const int32_t* labels, int k, float* C, int32_t* counts, void* work,
@@ -559,6 +570,11 @@ csc_status csc_timing_read(double* ms, int64_t* launches, double* bytes) {
   if (launches) *launches = g_timing.launches;
   if (bytes) *bytes = g_timing.bytes;
   return CSC_OK;
+}
+
+csc_status csc_gather_probe(const int32_t* rowptr, const int32_t* colidx, int64_t n_rows,
+                            const void* table, int row_bytes, uint32_t* out, void* stream) {
+  return run_gather_probe(rowptr, colidx, n_rows, table, row_bytes, out, as_stream(stream));
 }
 
 csc_status csc_autotune(csc_graph h, int w, csc_dtype iter_dt, void* work, size_t work_bytes,

@@ -100,6 +100,8 @@ struct Graph {
 csc_status graph_build(Graph* g, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
                        const double* w, int validate, hipStream_t s);
 csc_status graph_ensure_mirror(Graph* g, hipStream_t s);
+// dW (device double[nnz]) from dA (device float[nnz]); q: device double[n] scratch
+csc_status graph_weight_grad(Graph* g, const float* dA, double* dW, double* q, hipStream_t s);
 // compressive k-means (k_compress.hip)
 size_t compressive_workspace(int64_t n, int d, int k, int ns);
 csc_status run_compressive(const Graph* g, const void* F, csc_dtype f_dt, int64_t ldf, int d, int k,
@@ -177,6 +179,8 @@ csc_status run_filter_batch(const Graph* const* graphs, int S, double lmax, int 
                             int64_t ldx, void* const* Y, csc_dtype y_dt, int64_t ldy, int w,
                             csc_dtype iter_dt, int variant, double* const* moments,
                             void* const* work, size_t work_bytes, hipStream_t s, bool timed);
+csc_status run_gather_probe(const int32_t* rowptr, const int32_t* colidx, int64_t n,
+                            const void* table, int row_bytes, uint32_t* out, hipStream_t s);
 double filter_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dtype iter_dt,
                           bool moments, csc_dtype y_dt);
 
@@ -199,7 +203,9 @@ csc_status launch_uniforms(double* u, int count, uint64_t seed, uint64_t stream_
 size_t kmeans_workspace(int64_t n, int d, int k);
 csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                                 const float* C, int k, int32_t* labels, float* best_d2,
-                                double* obj_partial, hipStream_t s);
+                                float* sums, int32_t* counts, void* work, size_t work_bytes,
+                                hipStream_t s);
+
 csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                                 const int32_t* labels, int k, float* C, int32_t* counts,
                                 void* work, size_t work_bytes, hipStream_t s);

@@ -1697,3 +1697,72 @@ double basis_batch_bytes(const Graph* const* graphs, int S, int m, int w, csc_dt
 }
 
 }  // namespace csc
+
+// =====================================================================================
+// Random-gather probe: the memory system's ceiling for the recurrence step's neighbour
+// gathers.  For every row r of a CSR pattern, lane q of the row's group XORs the q-th 16-byte
+// piece of the table rows named by the row's column indices, exactly the access pattern of
+// the step kernel (CSR range staged in LDS, eight 16-byte loads in flight per lane, one row
+// group of row_bytes / 16 lanes per row) with no arithmetic and no other stream.
+namespace csc {
+
+namespace {
+
+template <int LPR>
+__global__ __launch_bounds__(kThreads) void k_gather_probe(const int32_t* rowptr,
+                                                           const int32_t* colidx, int64_t n,
+                                                           const uint4* table, uint32_t* out) {
+  constexpr int RPB = kThreads / LPR;
+  __shared__ int32_t s_col[kStageCap];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RPB;
+  const int64_t r1 = min(r0 + RPB, n);
+  const int32_t e0 = rowptr[r0], e1 = rowptr[r1];
+  const bool staged = e1 - e0 <= kStageCap;
+  if (staged)
+    for (int32_t i = threadIdx.x; i < e1 - e0; i += kThreads) s_col[i] = colidx[e0 + i];
+  __syncthreads();
+  const int64_t row = r0 + threadIdx.x / LPR;
+  const int lane = threadIdx.x % LPR;
+  if (row >= n) return;
+  const int32_t rs = rowptr[row], re = rowptr[row + 1];
+  const uint4* tb = table + lane;
+  uint32_t acc = 0;
+  int32_t e = rs;
+  for (; e + 8 <= re; e += 8) {
+    uint4 g[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t c = staged ? s_col[e + q - e0] : colidx[e + q];
+      g[q] = tb[static_cast<int64_t>(c) * LPR];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc ^= g[q].x ^ g[q].y ^ g[q].z ^ g[q].w;
+  }
+  for (; e < re; ++e) {
+    const int32_t c = staged ? s_col[e - e0] : colidx[e];
+    const uint4 g = tb[static_cast<int64_t>(c) * LPR];
+    acc ^= g.x ^ g.y ^ g.z ^ g.w;
+  }
+  out[row * LPR + lane] = acc;
+}
+
+}  // namespace
+
+csc_status run_gather_probe(const int32_t* rowptr, const int32_t* colidx, int64_t n,
+                            const void* table, int row_bytes, uint32_t* out, hipStream_t s) {
+  if (n < 1 || !rowptr || !colidx || !table || !out) return fail(CSC_E_ARG, "bad probe arguments");
+  const int64_t rpb = kThreads / (row_bytes / 16);
+  const unsigned blocks = static_cast<unsigned>((n + rpb - 1) / rpb);
+  const uint4* t = static_cast<const uint4*>(table);
+  switch (row_bytes) {
+    case 64: hipLaunchKernelGGL(k_gather_probe<4>, dim3(blocks), dim3(kThreads), 0, s, rowptr, colidx, n, t, out); break;
+    case 128: hipLaunchKernelGGL(k_gather_probe<8>, dim3(blocks), dim3(kThreads), 0, s, rowptr, colidx, n, t, out); break;
+    case 256: hipLaunchKernelGGL(k_gather_probe<16>, dim3(blocks), dim3(kThreads), 0, s, rowptr, colidx, n, t, out); break;
+    case 512: hipLaunchKernelGGL(k_gather_probe<32>, dim3(blocks), dim3(kThreads), 0, s, rowptr, colidx, n, t, out); break;
+    default: return fail(CSC_E_ARG, "row_bytes must be 64, 128, 256 or 512");
+  }
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+}  // namespace csc

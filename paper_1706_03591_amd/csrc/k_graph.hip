@@ -157,6 +157,40 @@ __device__ inline float load_val(const void* v, int dt, int64_t i) {
   return bf16_to_f32(static_cast<const uint16_t*>(v)[i]);
 }
 
+// Chain of the adjoint from A to the edge weights (normalized Laplacian, Sec. 2.1:
+// A = D^{-1/2} W D^{-1/2}, d = W 1; s = D^{-1/2}).  With G_e = dl/dA_e per stored entry:
+//   q_r = sum over the entries e of row r of G_e A_e + G_m(e) A_m(e)   (m(e) the mirror)
+//   g_e = G_e s_r s_c - q_r s_r^2 / 2                                  (W_rc as a parameter)
+//   dW_e = g_e + g_m(e)                    (the undirected weight, stored twice)
+// FP64 throughout, each sum in entry order; one thread per row.
+__global__ void k_wgrad_q(const int32_t* rowptr, const int32_t* mirror, const void* vals, int dt,
+                          const float* dA, int64_t n, double* q) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double acc = 0.0;
+  for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+    const int32_t me = mirror[e];
+    acc += static_cast<double>(dA[e]) * static_cast<double>(load_val(vals, dt, e));
+    acc += static_cast<double>(dA[me]) * static_cast<double>(load_val(vals, dt, me));
+  }
+  q[r] = acc;
+}
+
+__global__ void k_wgrad(const int32_t* rowptr, const int32_t* colidx, const int32_t* mirror,
+                        const double* dinv, const float* dA, const double* q, int64_t n,
+                        double* dW) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double sr = dinv[r];
+  for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+    const int32_t c = colidx[e];
+    const double sc = dinv[c];
+    const double g = static_cast<double>(dA[e]) * sr * sc - 0.5 * q[r] * sr * sr;
+    const double gm = static_cast<double>(dA[mirror[e]]) * sc * sr - 0.5 * q[c] * sc * sc;
+    dW[e] = g + gm;
+  }
+}
+
 // Edge distance (Sec. 4): per row, the two sorted column lists are merged and the squared
 // differences of the stored off-diagonal values summed in FP64 (an entry present in one
 // graph only counts with the other's value 0); for L = D - W the squared difference of the
@@ -320,6 +354,18 @@ csc_status graph_distance2(const Graph* a, const Graph* b, double* out, void* wo
 
 // The mirror index is needed only by the adjoint and by csc_graph_arrays; it is built on
 // first use after each (re)build.
+csc_status graph_weight_grad(Graph* g, const float* dA, double* dW, double* q, hipStream_t s) {
+  if (g->lap != CSC_LAP_NORMALIZED) return fail(CSC_E_ARG, "the weight chain is for the normalized Laplacian");
+  if (g->n == 0) return CSC_OK;
+  CSC_TRY(graph_ensure_mirror(g, s));
+  hipLaunchKernelGGL(k_wgrad_q, dim3(blocks_for(g->n)), dim3(256), 0, s, g->rowptr, g->mirror,
+                     static_cast<const void*>(g->vals), int(g->val_dt), dA, g->n, q);
+  hipLaunchKernelGGL(k_wgrad, dim3(blocks_for(g->n)), dim3(256), 0, s, g->rowptr, g->colidx,
+                     g->mirror, g->dinv, dA, static_cast<const double*>(q), g->n, dW);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
 csc_status graph_ensure_mirror(Graph* g, hipStream_t s) {
   if (g->mirror_valid) return CSC_OK;
   hipLaunchKernelGGL(k_mirror, dim3(blocks_for(g->n)), dim3(256), 0, s, g->rowptr, g->colidx, g->n,

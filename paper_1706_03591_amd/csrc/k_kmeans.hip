@@ -169,11 +169,12 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
 // runs on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16) in split precision: each FP32
 // centroid value is the sum of three BF16 parts (hi, mid, lo; residual below 2^-26 of the
 // value), and each FP32 feature likewise, so every partial product is exact in FP32.  Each
-// 32-column step of the dominant hi x hi product goes into a fresh FP32 accumulator and is
-// added to an FP64 sum, and the small cross products (weights 2^-8 and below) of each step
-// are summed in FP32 and added to a second, running FP32 accumulator; the rounding of a dot
-// product is then at most
-// E ||f|| ||c|| with E = 40 2^-24, so the exact score s*_c = ||c||^2 - 2 f.c lies in
+// 32-column step of the dominant hi x hi product goes into a fresh FP32 accumulator (at
+// most 32 u of rounding, u = 2^-24, relative to the sum of its absolute products), the at
+// most eight steps are summed in FP32 (at most 7 u more), and the small cross products
+// (weights 2^-8 and below) of each step are summed in FP32 into a second accumulator; the
+// two sums meet in FP64.  The rounding of a dot product is then at most
+// E ||f|| ||c|| with E = 48 2^-24, so the exact score s*_c = ||c||^2 - 2 f.c lies in
 // [s_c - e_c, s_c + e_c] with e_c = 2 E ||f|| ||c|| (+ FP64 rounding).  The argmin is then
 // among the centroids whose lower end is below the smallest upper end.  Each lane keeps its
 // three smallest lower ends and the smallest upper end; after the merge across lanes a row
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
   constexpr int SB = mf_sb<DP>();
   constexpr int NS = DP / 32;                      // 32-column MFMA steps
   constexpr int NP = sizeof(TF) == 4 ? 3 : 1;      // BF16 parts of a feature value
-  constexpr double E2 = 2.0 * 40.0 * 0x1p-24 * (1.0 + 0x1p-16);
+  constexpr double E2 = 2.0 * 48.0 * 0x1p-24 * (1.0 + 0x1p-16);
   extern __shared__ __align__(16) unsigned char s_raw[];
   uint16_t* s_cb = reinterpret_cast<uint16_t*>(s_raw);
   double* s_cn = reinterpret_cast<double*>(s_raw + static_cast<size_t>(3) * kc_max * SB * 2);
@@ -462,18 +463,28 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         // A operand: centroid ct*16 + li; output register r of lane (li, lq) is centroid
         // ct*16 + 4 lq + r against row li of the tile
         const uint16_t* cb = s_cb + (ct * 16 + li) * SB + lq * 8;
+        // every step starts its own accumulators, so the matrix-core chains are at most
+        // three long and the steps overlap in the pipeline; the small parts of a step are
+        // then added to the running FP32 sum.  A step's three centroid fragments are read
+        // from LDS once for all T row tiles, and the next step's are requested before this
+        // step's products, so the reads' latency hides behind them.
+        f32x4 dot[T], small[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-          double dot[4] = {0.0, 0.0, 0.0, 0.0};
-          f32x4 small = zero4;
-          // every step starts its own accumulators, so the matrix-core chains are at most
-          // three long and the steps overlap in the pipeline; the small parts of a step are
-          // then added to the running FP32 sum
+          small[t] = zero4;
+          dot[t] = zero4;
+        }
+        bf16x8 ch = lds_bf8(cb), cm = lds_bf8(cb + kc_max * SB), cl = lds_bf8(cb + 2 * kc_max * SB);
 #pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            const bf16x8 ch = lds_bf8(cb + s * 32);
-            const bf16x8 cm = lds_bf8(cb + kc_max * SB + s * 32);
-            const bf16x8 cl = lds_bf8(cb + 2 * kc_max * SB + s * 32);
+        for (int s = 0; s < NS; ++s) {
+          bf16x8 nh = ch, nm = cm, nl = cl;
+          if (s + 1 < NS) {
+            nh = lds_bf8(cb + (s + 1) * 32);
+            nm = lds_bf8(cb + kc_max * SB + (s + 1) * 32);
+            nl = lds_bf8(cb + 2 * kc_max * SB + (s + 1) * 32);
+          }
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
             const f32x4 main = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][0][s], zero4, 0, 0, 0);
             f32x4 sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][0][s], zero4, 0, 0, 0);
             sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[t][0][s], sm, 0, 0, 0);
@@ -483,10 +494,15 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
               sm2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][2][s], sm2, 0, 0, 0);
               sm += sm2;
             }
-            small += sm;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dot[r] += static_cast<double>(main[r]);
+            small[t] += sm;
+            dot[t] += main;
           }
+          ch = nh;
+          cm = nm;
+          cl = nl;
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int lc = ct * 16 + mf_drow(r, lq);
@@ -500,7 +516,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
               // index
               const double cnv = s_cn[lc];
               const double crv = s_cr[lc];
-              const double sc = cnv - 2.0 * (dot[r] + static_cast<double>(small[r]));
+              const double sc = cnv - 2.0 * (static_cast<double>(dot[t][r]) + static_cast<double>(small[t][r]));
               const double e = E2 * fnl[t] * crv + 1e-13 * (cnv + fnl[t] * crv);
               const bool real = cent < k;
               um[t] = real ? fmin(um[t], sc + e) : um[t];
@@ -517,7 +533,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
               // extra live registers would cost occupancy or spill)
               const double cnv = s_cn[lc];
               const double crv = s_cr[lc];
-              const double sc = cnv - 2.0 * (dot[r] + static_cast<double>(small[r]));
+              const double sc = cnv - 2.0 * (static_cast<double>(dot[t][r]) + static_cast<double>(small[t][r]));
               const double e = E2 * fnl[t] * crv + 1e-13 * (cnv + fnl[t] * crv);
               um[t] = fmin(um[t], sc + e);
               const double lo = sc - e;
@@ -848,18 +864,19 @@ __global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, 
       if (s_tot[t]) atomicAdd(&gcnt[t], s_tot[t]);
 }
 
+// C[c] = sums / count (C may be null), sums_out = the sums rounded once to FP32 (or null),
+// counts = the cluster sizes (or null).
 __global__ void k_upd_final(const unsigned long long* gsums, const int32_t* gcnt,
                             const uint32_t* maxabs, int64_t n, int k, int d, float* C,
-                            int32_t* counts) {
+                            int32_t* counts, float* sums_out) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<int64_t>(k) * d) return;
   const int c = static_cast<int>(t / d);
   const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
   const int32_t cnt = gcnt[c];
-  if (cnt > 0) {
-    const double sum = ldexp(static_cast<double>(static_cast<long long>(gsums[t])), -S);
-    C[t] = static_cast<float>(sum / static_cast<double>(cnt));
-  }
+  const double sum = ldexp(static_cast<double>(static_cast<long long>(gsums[t])), -S);
+  if (C && cnt > 0) C[t] = static_cast<float>(sum / static_cast<double>(cnt));
+  if (sums_out) sums_out[t] = static_cast<float>(sum);
   if (counts && (t % d) == 0) counts[c] = cnt;
 }
 
@@ -1193,7 +1210,7 @@ csc_status check_f(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
 
 csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                        const int32_t* labels, int k, float* C, int32_t* counts, void* work,
-                       bool max_ready, hipStream_t s) {
+                       bool max_ready, hipStream_t s, float* sums_out = nullptr) {
   const KmLayout L = km_layout(n, d, k);
   char* base = static_cast<char*>(work);
   auto* sums = reinterpret_cast<unsigned long long*>(base + L.off_sums);
@@ -1229,7 +1246,7 @@ csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, in
   }
 #undef CSC_UPD
   hipLaunchKernelGGL(k_upd_final, dim3(static_cast<unsigned>((kd + 255) / 256)), dim3(256), 0, s,
-                     sums, cnt, mx, n, k, d, C, counts);
+                     sums, cnt, mx, n, k, d, C, counts, sums_out);
   CSC_HIP(hipGetLastError());
   return CSC_OK;
 }
@@ -1349,42 +1366,20 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   return CSC_OK;
 }
 
-namespace {
-// scratch of the workspace-free assignment call, one per device
-constexpr int kMaxDevices = 64;
-struct CpBuf {
-  float* p = nullptr;
-  size_t bytes = 0;
-};
-std::mutex g_cp_mutex;
-CpBuf g_cp[kMaxDevices];
-}  // namespace
-
 csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                                 const float* C, int k, int32_t* labels, float* best_d2,
-                                double* obj_part, hipStream_t s) {
+                                float* sums, int32_t* counts, void* work, size_t work_bytes,
+                                hipStream_t s) {
   CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
   if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
-  // the ABI call has no workspace: the padded centroids live in a small buffer per device
-  // (the current one), owned by the library, grown on demand and kept until exit
-  int dev = 0;
-  CSC_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= kMaxDevices) return fail(CSC_E_ARG, "device index out of range");
-  const size_t need = assign_scratch_bytes(k, d);
-  float* buf = nullptr;
-  {
-    std::lock_guard<std::mutex> lock(g_cp_mutex);
-    CpBuf& b = g_cp[dev];
-    if (need > b.bytes) {
-      if (b.p) (void)hipFree(b.p);  // waits for the device's work that may still use it
-      b.p = nullptr;
-      b.bytes = 0;
-      CSC_HIP(hipMalloc(&b.p, need));
-      b.bytes = need;
-    }
-    buf = b.p;
-  }
-  return assign_impl(F, f_dt, ldf, n, d, C, k, labels, best_d2, obj_part, buf, s);
+  const KmLayout L = km_layout(n, d, k);
+  if (!work || work_bytes < L.total) return fail(CSC_E_ARG, "k-means workspace too small");
+  auto* Cp = reinterpret_cast<float*>(static_cast<char*>(work) + L.off_cp);
+  CSC_TRY(assign_impl(F, f_dt, ldf, n, d, C, k, labels, best_d2, nullptr, Cp, s));
+  // the Lloyd partial sums of the new assignment: the update's fixed-point accumulation
+  // (a second pass over F), without the division by the counts
+  if (sums || counts) CSC_TRY(update_impl(F, f_dt, ldf, n, d, labels, k, nullptr, counts, work, false, s, sums));
+  return CSC_OK;
 }
 
 csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,

@@ -1,7 +1,7 @@
 """Writes the expected values of the full-size parity tests (tests/test_gpu_fullsize.py).
 
     python tests/golden/make_fullsize.py c3      (about 10 minutes on 4 cores)
-    python tests/golden/make_fullsize.py c5      (about 40 minutes on 4 cores, 30 GB of RAM)
+    python tests/golden/make_fullsize.py c5 3    (about 50 minutes on 3 workers, 40 GB of RAM)
 
 Calls only the FP64 oracle (oracle/) and the seeded input generators (workloads/).  For
 each case it stores, on 10,000 sampled rows of 4 sampled columns of one snapshot's fresh
@@ -37,7 +37,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from oracle import chebyshev, operator, philox, storage  # noqa: E402
+from oracle import cfilter, chebyshev, operator, philox, storage  # noqa: E402
 from workloads import DynamicSBM, block_sizes_zipf, chung_lu, sbm, seed_for  # noqa: E402
 from workloads.graphs import rewire_model_free  # noqa: E402
 
@@ -92,10 +92,9 @@ def _job(job):
     A, X, rows, m = _W["A"], _W["X"], _W["rows"], _W["m"]
     a = chebyshev.step_coefficients(m, 2.0, lam, "jackson")
     t0 = time.perf_counter()
-    if kind == "ref":
-        Y = chebyshev.filter_recurrence(A, 2.0, a, X[name])
-    else:
-        Y = storage.filter_stored(A, 2.0, a, X[storage.form_inputs(name)], **storage.FORMS[name])
+    form = storage.FORMS[name]
+    Y = storage.filter_stored(A, 2.0, a, X[storage.form_inputs(name)], **form,
+                              Lt=_W["Lt"][form["val"]])
     print(f"  {kind} {name} cut-off {lam}: {time.perf_counter() - t0:.0f} s", flush=True)
     return job, Y[rows]
 
@@ -108,10 +107,25 @@ def main(case: str, workers: int = 4):
     print(f"{case}: graph n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.0f} s)", flush=True)
     _W.update(A=A, X={s: case_signals(case, s) for s in ("f32", "bf16")}, rows=case_rows(case),
               m=c["m"])
-    jobs = [("ref", lam, s) for lam in c["cutoffs"] for s in ("f32", "bf16")]
-    jobs += [("form", lam, f) for lam in c["cutoffs"] for f in CASE_FORMS[case]]
+    # the exact filters: the oracle's multi-core C recurrence (the same FP64 operations as
+    # chebyshev.filter_recurrence, pinned to it)
+    res = {}
+    Lt = operator.scaled_laplacian(A, 2.0)
+    for lam in c["cutoffs"]:
+        a = chebyshev.step_coefficients(c["m"], 2.0, lam, "jackson")
+        for s in ("f32", "bf16"):
+            t1 = time.perf_counter()
+            Y, used = cfilter.filter_recurrence_c(None, 2.0, a, _W["X"][s], Lt=Lt)
+            res[("ref", lam, s)] = Y[_W["rows"]]
+            print(f"  ref {s} cut-off {lam}: {time.perf_counter() - t1:.0f} s on {used} threads", flush=True)
+    del Lt
+    # the storage forms: each worker shares the parent's operators (built once per value
+    # format, before the fork)
+    _W["Lt"] = {v: storage.stored_operator(A, 2.0, v)
+                for v in sorted({storage.FORMS[f]["val"] for f in CASE_FORMS[case]})}
+    jobs = [("form", lam, f) for lam in c["cutoffs"] for f in CASE_FORMS[case]]
     with mp.get_context("fork").Pool(workers) as pool:
-        res = dict(pool.map(_job, jobs, chunksize=1))
+        res.update(dict(pool.imap_unordered(_job, jobs, chunksize=1)))
     refs = {f"ref_{lam}_{s}": res[("ref", lam, s)] for lam in c["cutoffs"] for s in ("f32", "bf16")}
     floors = {}
     for lam in c["cutoffs"]:

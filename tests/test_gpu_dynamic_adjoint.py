@@ -97,6 +97,48 @@ def test_adjoint_matches_oracle(csc, m, w, ckpt):
         assert np.all(dA.cpu().numpy() == 0)
 
 
+def test_weight_chain_matches_oracle_and_finite_differences(csc):
+    """The chain from dl/dA to the symmetric edge weights (Sec. 2.1, A = D^{-1/2} W D^{-1/2})
+    on C4's gradient-check graph (SBM N = 2000, k = 4, degree 10) with random symmetric
+    weights: the GPU chain of the GPU's dA against the oracle chain of the oracle's dA, and
+    the oracle's chain against FP64 central differences of the loss on a few edges."""
+    from workloads import seed_for
+    say("weight chain, C4 gradient-check graph")
+    g = sbm(2000, 4, 10.0, 0.1, seed=seed_for(4, "graph") + 7)
+    rng = np.random.default_rng(71)
+    mir = adjoint.mirror_index(g.n, g.rowptr, g.colidx)
+    w = g.w * rng.uniform(0.5, 2.0, size=g.w.shape)
+    w = 0.5 * (w + w[mir])
+    g.w = w
+    A, _ = operator.normalized_adjacency(g.n, g.rowptr, g.colidx, w)
+    G = csc.Graph.from_workload(g)
+    X = gaussian_block(g.n, 8, 0.3, seed=72)
+    Gr = gaussian_block(g.n, 8, 1.0, seed=73)
+    a = chebyshev.step_coefficients(30, 2.0, 0.5, "jackson")
+    _, _, dA = csc.filter_backward(G, a, torch.from_numpy(X).cuda(), torch.from_numpy(Gr).cuda())
+    dW = csc.weight_gradient(G, dA).cpu().numpy()
+    _, _, rdA = adjoint.filter_backward(A, 2.0, a, X.astype(np.float64), Gr.astype(np.float64))
+    rdW = adjoint.weight_gradient(g.n, g.rowptr, g.colidx, w, rdA)
+    err = rel_fro(dW, rdW)
+    say(f"  dW relative error {err:.3e}")
+    assert err <= 1e-5
+    assert np.array_equal(dW, dW[mir])
+
+    def loss(wv):
+        Av, _ = operator.normalized_adjacency(g.n, g.rowptr, g.colidx, wv)
+        return float(np.sum(Gr * chebyshev.filter_recurrence(Av, 2.0, a, X.astype(np.float64))))
+
+    h = 1e-6
+    for e in rng.integers(0, len(w), size=4):
+        wp, wm = w.copy(), w.copy()
+        for q in {int(e), int(mir[e])}:
+            wp[q] += h
+            wm[q] -= h
+        fd = (loss(wp) - loss(wm)) / (2 * h)
+        assert rdW[e] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+        assert dW[e] == pytest.approx(fd, rel=1e-4, abs=1e-6)
+
+
 def test_adjoint_c4_full_size_sampled_columns(csc):
     """C4 at full size (SBM N=200k, degree 20, w=64, m=60, checkpoints every 8 iterates):
     the adjoint is column-separable, so the 64-column run is checked on two sampled columns
@@ -187,9 +229,11 @@ def test_batched_and_graph_forms_equal_sequential(csc, seq, batch, use_graph, it
 # starts, with its moments; decisions come from the moments, and snapshots whose cut-off
 # changed within the batch are filtered again.  Against one snapshot at a time without kept
 # iterates: the same cut-offs, refinements and labels, bit-identical features (the same
-# kernels in the same order), counts equal up to their two FP64 evaluations (the moment
-# series here, <R, h(L) R> there).  tau = 1e-12 refines every snapshot, so every block is
-# filtered again.
+# kernels in the same order).  The accepted counts are two estimates of the same quantity,
+# the moment series here and <R, Y> with the stored output Y there, so they differ by the
+# rounding of Y and of the iterates: up to 1e-5 relative with FP32 iterates, 5e-3 with
+# 16-bit ones (the acceptance half-width is at least 0.5).  tau = 1e-12 refines every
+# snapshot, so every block is filtered again.
 @pytest.mark.parametrize("batch,use_graph,iters,p,d,tau", [(4, True, torch.float32, 0.5, 32, None),
                                                            (3, False, torch.float16, 0.3, 40, None),
                                                            (4, True, "bf16s", 0.5, 32, 1e-12),
@@ -208,8 +252,15 @@ def test_onepass_batches_equal_sequential(csc, seq, batch, use_graph, iters, p, 
         say(f"  t={t + 1} lambda {lams[t]:.6f} refined {refs[t]} count {cnts[t]:.5f} / {ref_out[t][3]:.5f}")
         assert lams[t] == ref_out[t][1]
         assert refs[t] == ref_out[t][2]
-        assert cnts[t] == pytest.approx(ref_out[t][3], rel=1e-6, abs=1e-6)
         assert torch.equal(labels[t], ref_out[t][0])
+        if refs[t]:
+            # both the count at the refined cut-off from the same doubled moments (computed by
+            # the batched and by the single step kernel)
+            assert cnts[t] == pytest.approx(ref_out[t][3], rel=1e-12)
+        elif iters == torch.float32:
+            assert cnts[t] == pytest.approx(ref_out[t][3], rel=1e-5)
+        else:
+            assert cnts[t] == pytest.approx(ref_out[t][3], abs=5e-3)
     assert torch.equal(bat.features(), ref.features())
 
 

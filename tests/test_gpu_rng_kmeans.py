@@ -56,6 +56,32 @@ def test_assign_matches_oracle(csc, n, d, k):
     assert np.allclose(best.cpu().numpy(), d2, rtol=1e-6)
 
 
+@pytest.mark.parametrize("n,d,k,bf", [(5000, 32, 5, False), (20011, 128, 50, True), (3000, 256, 200, False),
+                                      (777, 17, 3, False)])
+def test_assign_fused_sums_and_counts(csc, n, d, k, bf):
+    """The optional Lloyd partial sums of the assignment call: for the labels it returns,
+    sums[c] = sum of the rows labelled c and counts[c] their number (Sec. 2.1, the update
+    step of k-means); FP64 sums in the oracle, one FP32 rounding on the GPU."""
+    say(f"kmeans assign with sums n={n} d={d} k={k} bf16={bf}")
+    F = _mixture(n, d, max(k, 2), seed=n + 1)
+    Ft = torch.from_numpy(F).cuda()
+    if bf:
+        Ft = Ft.to(torch.bfloat16)
+    C = F[np.random.default_rng(2).choice(n, size=k, replace=False)] + 0.01
+    lab, _, S, cnt = csc.kmeans_assign(Ft, torch.from_numpy(C).cuda(), sums=True)
+    lab = lab.cpu().numpy()
+    F64 = Ft.double().cpu().numpy()
+    ref = np.zeros((k, d))
+    np.add.at(ref, lab, F64)
+    assert np.array_equal(cnt.cpu().numpy(), np.bincount(lab, minlength=k))
+    scale = np.abs(F64).max() * n * 2.0 ** -40  # fixed-point resolution of the sums
+    err = np.abs(S.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= 2.0 ** -24 * np.abs(ref) + 2 * scale)
+    # the same labels as the call without sums
+    lab2, _ = csc.kmeans_assign(Ft, torch.from_numpy(C).cuda())
+    assert np.array_equal(lab2.cpu().numpy(), lab)
+
+
 def test_assign_exact_ties_lowest_index(csc):
     F = np.array([[0.0, 0.0], [1.0, 1.0], [0.5, 0.5]], dtype=np.float32)
     C = np.array([[1.0, 1.0], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0]], dtype=np.float32)

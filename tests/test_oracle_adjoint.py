@@ -96,3 +96,41 @@ def test_input_gradient_is_filter_transpose(tiny):
     lam, U = operator.dense_spectrum(A)
     expect = chebyshev.filter_dense(lam, U, a, 2.0, G)
     assert np.allclose(dX, expect, atol=1e-12)
+
+
+def test_weight_chain_finite_differences():
+    """dl/dw of an undirected edge weight (both stored copies moved together), through
+    A = D^{-1/2} W D^{-1/2} and the degrees, against central differences of the loss."""
+    g = sbm(60, 3, 6.0, 0.2, seed=31)
+    rng = np.random.default_rng(34)
+    w = g.w * rng.uniform(0.5, 2.0, size=g.w.shape)
+    mir = adjoint.mirror_index(g.n, g.rowptr, g.colidx)
+    w = 0.5 * (w + w[mir])  # symmetric weights
+    X = rng.standard_normal((g.n, 3))
+    G = rng.standard_normal((g.n, 3))
+    a = chebyshev.step_coefficients(9, 2.0, 0.7, "jackson")
+    A, _ = operator.normalized_adjacency(g.n, g.rowptr, g.colidx, w)
+    _, _, dA = adjoint.filter_backward(A, 2.0, a, X, G)
+    dw = adjoint.weight_gradient(g.n, g.rowptr, g.colidx, w, dA)
+    assert np.array_equal(dw, dw[mir])
+    h = 1e-6
+
+    def loss(wv):
+        Av, _ = operator.normalized_adjacency(g.n, g.rowptr, g.colidx, wv)
+        return _loss(Av, a, X, G)
+
+    for e in rng.integers(0, len(w), size=10):
+        wp, wm = w.copy(), w.copy()
+        for q in {int(e), int(mir[e])}:
+            wp[q] += h
+            wm[q] -= h
+        fd = (loss(wp) - loss(wm)) / (2 * h)
+        assert dw[e] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_mirror_index_is_an_involution():
+    g = sbm(200, 4, 8.0, 0.2, seed=35)
+    mir = adjoint.mirror_index(g.n, g.rowptr, g.colidx)
+    assert np.array_equal(mir[mir], np.arange(len(mir)))
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    assert np.array_equal(rows[mir], g.colidx) and np.array_equal(g.colidx[mir], rows)
