@@ -266,6 +266,16 @@ csc_status csc_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t
                              const float* C, int k, int32_t* labels, float* best_d2,
                              float* sums, int32_t* counts, void* work, size_t work_bytes,
                              void* stream);
+/* csc_kmeans_assign_noalloc: for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc), the same assignment as
+ * csc_kmeans_assign without best-distance sums or workspace: labels and best_d2 as there.
+ * Its split centroids live in a static device array of the library (400 KiB per device,
+ * held until the process ends), so it takes k <= 240 and d <= 256 (CSC_E_ARG beyond) and
+ * calls no allocating routine.  Every call on a device uses that device's one array: calls
+ * that overlap on one device race.  Asynchronous. */
+csc_status csc_kmeans_assign_noalloc(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n,
+                                     int d, const float* C, int k, int32_t* labels,
+                                     float* best_d2, void* stream);
 csc_status csc_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                              const int32_t* labels, int k, float* C, int32_t* counts,
                              void* work, size_t work_bytes, void* stream);

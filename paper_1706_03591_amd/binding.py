@@ -101,6 +101,7 @@ _SIGS = {
     "csc_uniforms": ([vp, i32, u64, u64, vp], i32),
     "csc_kmeans_workspace_bytes": ([i64, i32, i32], sz),
     "csc_kmeans_assign": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp, vp, vp, sz, vp], i32),
+    "csc_kmeans_assign_noalloc": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp], i32),
     "csc_kmeans_update": ([vp, i32, i64, i64, i32, vp, i32, vp, vp, vp, sz, vp], i32),
     "csc_kmeans_seed": ([vp, i32, i64, i64, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "csc_compressive_workspace_bytes": ([i64, i32, i32, i32], sz),

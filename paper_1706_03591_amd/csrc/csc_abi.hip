@@ -451,6 +451,12 @@ csc_status csc_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t
                               work_bytes, as_stream(stream));
 }
 
+csc_status csc_kmeans_assign_noalloc(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n,
+                                     int d, const float* C, int k, int32_t* labels,
+                                     float* best_d2, void* stream) {
+  return launch_kmeans_assign_static(F, f_dt, ldf, n, d, C, k, labels, best_d2,
+                                     as_stream(stream));
+}
 
 csc_status csc_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                              const int32_t* labels, int k, float* C, int32_t* counts, void* work,

@@ -205,7 +205,12 @@ csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int6
                                 const float* C, int k, int32_t* labels, float* best_d2,
                                 float* sums, int32_t* counts, void* work, size_t work_bytes,
                                 hipStream_t s);
-
+// the same assignment with its scratch in a static device array (no workspace, allocates
+// nothing; k <= 240, d <= 256)
+csc_status launch_kmeans_assign_static(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n,
+                                       int d, const float* C, int k, int32_t* labels,
+                                       float* best_d2, hipStream_t s);
+size_t kmeans_static_scratch_bytes();
 csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                                 const int32_t* labels, int k, float* C, int32_t* counts,
                                 void* work, size_t work_bytes, hipStream_t s);

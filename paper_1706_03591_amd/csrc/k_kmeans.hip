@@ -1382,6 +1382,49 @@ csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int6
   return CSC_OK;
 }
 
+// ---- the assignment without workspace: split centroids in a static device array -------
+//
+// For callers that cannot allocate (graph capture, serving loops).  The array holds the
+// split centroids of the matrix-core path (or the padded ones of the vector path) for
+// k <= 240 and d <= 256; each device has its own copy, whose address is looked up once per
+// device with that device current.  Every call on a device uses that device's copy, so
+// calls that overlap on one device race.
+
+namespace {
+constexpr size_t kStaticScratch = 400 * 1024;
+__device__ __align__(256) unsigned char scratch[kStaticScratch];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+size_t kmeans_static_scratch_bytes() { return kStaticScratch; }
+
+csc_status launch_kmeans_assign_static(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n,
+                                       int d, const float* C, int k, int32_t* labels,
+                                       float* best_d2, hipStream_t s) {
+  CSC_TRY(check_f(F, f_dt, ldf, n, d, k));
+  if (!C || !labels) return fail(CSC_E_ARG, "null centroids or labels");
+  if (k > 240 || d > 256 || assign_scratch_bytes(k, d) > kStaticScratch)
+    return fail(CSC_E_ARG, "the allocation-free assignment takes k <= 240 and d <= 256 (its static "
+                           "scratch holds " + std::to_string(kStaticScratch) + " bytes)");
+  int dev = 0;
+  CSC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CSC_E_ARG, "device index out of range");
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+      void* p = nullptr;
+      CSC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      if (!p) return fail(CSC_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+      g_scratch[dev] = p;
+    }
+    ptr = g_scratch[dev];
+  }
+  return assign_impl(F, f_dt, ldf, n, d, C, k, labels, best_d2, nullptr, static_cast<float*>(ptr), s);
+}
+
 csc_status launch_kmeans_update(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                                 const int32_t* labels, int k, float* C, int32_t* counts,
                                 void* work, size_t work_bytes, hipStream_t s) {
