@@ -6,15 +6,18 @@ moves 0.5% of the nodes; d = 128 signals, Chebyshev degree m = 120, reuse p = 0.
 is one dynamic snapshot (Algorithm 1 steps 4-8: operator build, q d = 64 fresh signals,
 filter, eigencount, refinement when needed, k-means with 20 Lloyd rounds), with every
 snapshot's CSR already resident in HBM.  The storage forms (FORMS below) run on the same
-snapshots: FP32 everywhere; BF16 signals/features/values with FP32 iterates (bf16io); BF16
-iterates (bf16); BF16 gathered iterate copies with an FP32 recurrence state (bf16s); and
-bf16s with the fresh blocks of several snapshots in one batched, graph-replayed recurrence
-(bf16sb, the headline).
+snapshots: FP32 everywhere; BF16 signals/features/values with FP32 iterates (bf16io), BF16
+iterates (bf16), BF16 gathered copies with an FP32 recurrence state (bf16s), binary16
+iterates (f16, the headline) or binary16 copies with an FP32 state (f16s); each with a
+suffix b for the fresh blocks of several snapshots in one batched, graph-replayed recurrence,
+and b1p for batches without kept iterates.
 
 Printed: one JSON line.  `value` is the whole-job rate of the Chebyshev step kernels'
 algorithmic bytes (GB/s over the timed wall clock) of the headline form; `roofline` gives
-the step kernel's own rate from HIP events on its stream; `cpu_baseline` times the FP64
-oracle filtering a 4-column sample of a snapshot on one host core.
+the step kernel's own rate from HIP events on its stream; `errors_vs_fp64_oracle` is each
+form's error on the columns its last timed snapshot wrote; `cpu_baseline` times the FP64
+oracle (its multi-core C recurrence) filtering a 4-column sample of that snapshot on all host
+cores and on one.
 """
 
 from __future__ import annotations
@@ -41,16 +44,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--k", type=int, default=50)
-    ap.add_argument("--d", type=int, default=128)
-    ap.add_argument("--m", type=int, default=120)
-    ap.add_argument("--p", type=float, default=0.5)
+    ap.add_argument("--n", type=int, default=None, help="nodes (default: the workload's configuration)")
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--d", type=int, default=None)
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--p", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16io,bf16,bf16s,bf16b,bf16sb",
+    ap.add_argument("--forms", default="fp32,bf16io,bf16,bf16s,bf16b,bf16sb,f16,f16s,f16b,f16sb",
                     help="comma list of " + ", ".join(f"{k}: {v[5]}" for k, v in FORMS.items()))
-    ap.add_argument("--headline", default="bf16sb")
+    ap.add_argument("--headline", default="f16")
     ap.add_argument("--init", choices=["pp", "warm"], default="pp",
                     help="k-means start per snapshot: k-means++ (pp) or the previous labels' means")
     ap.add_argument("--batch", type=int, default=4, help="snapshots per batched recurrence")
@@ -66,14 +69,15 @@ def parse():
                     help="turn two rocprofv3 counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) "
                          "of --probe FORM into profiles/k_step_c3_traffic.json")
     args = ap.parse_args()
-    if args.workload == "c5" and "--n" not in sys.argv:
-        args.n, args.k, args.d, args.m, args.p = 8_000_000, 200, 256, 150, 0.75
-    if args.workload == "c2" and "--n" not in sys.argv:
-        args.n, args.k, args.d, args.m = 200_000, 20, 64, 100
-    if args.workload == "c4" and "--n" not in sys.argv:
-        args.n, args.k, args.d, args.m = 200_000, 20, 64, 60
-    if args.workload == "kassign" and "--n" not in sys.argv:
-        args.n, args.k, args.d = 8_000_000, 200, 256
+    # the configuration table (workloads/configs.py) supplies the sizes of each workload
+    from workloads import CONFIGS
+
+    cfg = {"c2": 2, "c4": 4, "c5": 5, "kassign": 5}.get(args.workload, 3)
+    c = CONFIGS[cfg]
+    for key in ("n", "k", "d", "m", "p"):
+        if getattr(args, key) is None:
+            setattr(args, key, c.get(key, 0.5))
+    args.config = c
     return args
 
 
@@ -158,24 +162,25 @@ def build_sequence(args, T):
     from workloads import DynamicSBM, block_sizes_zipf, sbm, seed_for
 
     t0 = time.perf_counter()
+    c = args.config
     if args.workload == "c5":
         from workloads import chung_lu
         from workloads.graphs import rewire_model_free
 
-        g = chung_lu(args.n, args.k, 20.0, 2.5, 0.1, seed=seed_for(5, "graph"))
+        g = chung_lu(args.n, args.k, c["degree"], c["exponent"], c["ratio"], seed=seed_for(5, "graph"))
         log(f"[bench] snapshot 1: nnz {g.nnz} ({time.perf_counter() - t0:.1f} s)")
         seq = [g]
         for t in range(2, T + 1):
-            seq.append(rewire_model_free(seq[-1], 0.005, seed_for(5, "perturb") + t, 0.1))
+            seq.append(rewire_model_free(seq[-1], c["rewire"], seed_for(5, "perturb") + t, c["ratio"]))
             log(f"[bench] snapshot {t}: nnz {seq[-1].nnz} ({time.perf_counter() - t0:.1f} s)")
         return seq, np
-    sizes = block_sizes_zipf(args.n, args.k, 1.2)
-    g = sbm(args.n, args.k, 16.0, 0.1, seed=seed_for(3, "graph"), sizes=sizes)
+    sizes = block_sizes_zipf(args.n, args.k, c["zipf_s"])
+    g = sbm(args.n, args.k, c["degree"], c["ratio"], seed=seed_for(3, "graph"), sizes=sizes)
     log(f"[bench] snapshot 1: nnz {g.nnz} ({time.perf_counter() - t0:.1f} s)")
     dyn = DynamicSBM(g, seed=seed_for(3, "perturb"))
     seq = [g]
     for t in range(2, T + 1):
-        seq.append(dyn.step(0.01, 0.005))
+        seq.append(dyn.step(c["rewire"], c["move"]))
         log(f"[bench] snapshot {t}: nnz {seq[-1].nnz} ({time.perf_counter() - t0:.1f} s)")
     return seq, np
 
@@ -565,7 +570,9 @@ def run_dynamic(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step_batch (fused Chebyshev SpMM + three-term update, iterates kept for recombination)",
+            "kernel": ("k_step_batch<%s> (fused Chebyshev SpMM + three-term update, %s)" % (
+                FORMS[args.headline][1], "one-pass: FP32 running sum" if args.headline in ONEPASS
+                else "iterates kept for recombination")),
             "achieved": round(achieved, 1),
             "peak": PEAK_GBPS,
             "unit": "GB/s",
@@ -627,7 +634,7 @@ def run_static(args):
     import paper_1706_03591_amd as csc
     from workloads import gaussian_block, sbm, seed_for
 
-    g = sbm(args.n, args.k, 20.0, 0.1, seed=seed_for(2, "graph"))
+    g = sbm(args.n, args.k, args.config["degree"], args.config["ratio"], seed=seed_for(2, "graph"))
     log(f"[bench] C2 graph nnz {g.nnz}")
     G = csc.Graph.from_workload(g)
     variant = G.autotune(args.d)
@@ -675,7 +682,7 @@ def run_adjoint(args):
     import paper_1706_03591_amd as csc
     from workloads import gaussian_block, sbm, seed_for
 
-    g = sbm(args.n, args.k, 20.0, 0.1, seed=seed_for(4, "graph"))
+    g = sbm(args.n, args.k, args.config["degree"], args.config["ratio"], seed=seed_for(4, "graph"))
     G = csc.Graph.from_workload(g)
     X = torch.from_numpy(gaussian_block(args.n, args.d, 1 / np.sqrt(args.d), seed=seed_for(4, "signals"))).cuda()
     Gr = torch.from_numpy(gaussian_block(args.n, args.d, 1.0, seed=seed_for(4, "probes"))).cuda()
@@ -941,6 +948,14 @@ def run_gather(args):
     step_tb = gather_req / (step_us * 1e-6) / 1e12
     log(f"[bench] f16 one-pass step on the same CSR: {step_us:.1f} us per step; its gathers alone "
         f"would take {t_c3 * 1e6:.1f} us at the probe's rate")
+    # a plain 1 GiB copy, whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters when
+    # this workload runs under rocprofv3 --pmc
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     _line(args, "random-gather ceiling: requested TB/s of 128-byte neighbour rows on the C3 CSR",
           tb_c3, "TB/s", t_c3 * 1e3,
           {"config": {"workload": "csc_gather_probe on C3 snapshot 1 (N=1M, 16M entries) and random "

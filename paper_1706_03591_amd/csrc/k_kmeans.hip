@@ -381,7 +381,8 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         for (int s = 0; s < NS; ++s)
           load_raw8<TF, FULL>(F, ldf, n, d, row_of(panel, t), s * 32 + lq * 8, raw[t][s]);
     }
-    double bl3[T][3], um[T], fnl[T];  // three smallest lower ends, smallest upper end, ||f||
+    double bl3[T][3], um[T], fnl[T], gfn[T];  // three smallest lower ends, smallest upper end,
+                                              // ||f||, (E2 + 1e-13) ||f||
     int bi3[T][3];
     // B operand: row li, eight consecutive columns per step from 8 lq
     bf16x8 a[T][NP][NS];
@@ -412,6 +413,9 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       fs += __shfl_xor(fs, 16, 64);
       fs += __shfl_xor(fs, 32, 64);
       fnl[t] = sqrt(static_cast<double>(fs)) * (1.0 + 0x1p-16);
+      // a score's half-width: E2 ||f|| ||c|| + 1e-13 (||c||^2 + ||f|| ||c||), the last term
+      // covering the FP64 rounding of the score and of the bound itself
+      gfn[t] = (E2 + 1e-13) * fnl[t];
     }
     if (PF && panel + gridDim.x < panels) {
 #pragma unroll
@@ -424,30 +428,29 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       if (nchunks > 1 || !staged) {
         __syncthreads();
         // 16-byte copies of the chunk's three parts, SU loads in flight per thread (the last
-        // group re-reads the final piece instead of branching), then its norms
+        // group re-reads the final piece instead of branching), then its norms.  A part's
+        // chunk is contiguous in global memory (piece q at 8 q); in LDS its rows are padded
+        // to SB, so piece q goes to row q / vpr (a shift: vpr is a power of two).
         constexpr int SU = 4;
-        const int vpr = DP / 8;
-        const int tot = 3 * kc * vpr;
-        for (int q0 = threadIdx.x; q0 < tot; q0 += SU * blockDim.x) {
-          u32x4 val[SU];
+        constexpr int vpr = DP / 8;
+        const int per = kc * vpr;
 #pragma unroll
-          for (int j = 0; j < SU; ++j) {
-            const int q = min(q0 + j * static_cast<int>(blockDim.x), tot - 1);
-            const int p = q / (kc * vpr);
-            const int rem = q - p * kc * vpr;
-            const int c = rem / vpr, v = rem - c * vpr;
-            val[j] = *reinterpret_cast<const u32x4*>(
-                parts + (static_cast<int64_t>(p) * kp + c0 + c) * DP + 8 * v);
-          }
-          __builtin_amdgcn_sched_barrier(0);
+        for (int pp = 0; pp < 3; ++pp) {
+          const uint16_t* src = parts + (static_cast<int64_t>(pp) * kp + c0) * DP;
+          uint16_t* dst = s_cb + pp * kc_max * SB;
+          for (int q0 = threadIdx.x; q0 < per; q0 += SU * blockDim.x) {
+            u32x4 val[SU];
 #pragma unroll
-          for (int j = 0; j < SU; ++j) {
-            const int q = q0 + j * static_cast<int>(blockDim.x);
-            if (q < tot) {
-              const int p = q / (kc * vpr);
-              const int rem = q - p * kc * vpr;
-              const int c = rem / vpr, v = rem - c * vpr;
-              *reinterpret_cast<u32x4*>(s_cb + (p * kc_max + c) * SB + 8 * v) = val[j];
+            for (int j = 0; j < SU; ++j) {
+              const int q = min(q0 + j * static_cast<int>(blockDim.x), per - 1);
+              val[j] = *reinterpret_cast<const u32x4*>(src + 8 * q);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < SU; ++j) {
+              const int q = q0 + j * static_cast<int>(blockDim.x);
+              if (q < per)
+                *reinterpret_cast<u32x4*>(dst + (q / vpr) * SB + 8 * (q % vpr)) = val[j];
             }
           }
         }
@@ -464,10 +467,11 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         // ct*16 + 4 lq + r against row li of the tile
         const uint16_t* cb = s_cb + (ct * 16 + li) * SB + lq * 8;
         // every step starts its own accumulators, so the matrix-core chains are at most
-        // three long and the steps overlap in the pipeline; the small parts of a step are
-        // then added to the running FP32 sum.  A step's three centroid fragments are read
-        // from LDS once for all T row tiles, and the next step's are requested before this
-        // step's products, so the reads' latency hides behind them.
+        // three long and the steps overlap in the pipeline (one chain across all steps runs
+        // slower: each product then waits for the previous one); a step's leading and small
+        // products are then added to two running FP32 sums.  A step's three centroid
+        // fragments are read from LDS once for all T row tiles, and the next step's are
+        // requested before this step's products, so the reads' latency hides behind them.
         f32x4 dot[T], small[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -517,7 +521,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
               const double cnv = s_cn[lc];
               const double crv = s_cr[lc];
               const double sc = cnv - 2.0 * (static_cast<double>(dot[t][r]) + static_cast<double>(small[t][r]));
-              const double e = E2 * fnl[t] * crv + 1e-13 * (cnv + fnl[t] * crv);
+              const double e = fma(gfn[t], crv, 1e-13 * cnv);
               const bool real = cent < k;
               um[t] = real ? fmin(um[t], sc + e) : um[t];
               const double lo = real ? sc - e : INFINITY;
@@ -534,7 +538,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
               const double cnv = s_cn[lc];
               const double crv = s_cr[lc];
               const double sc = cnv - 2.0 * (static_cast<double>(dot[t][r]) + static_cast<double>(small[t][r]));
-              const double e = E2 * fnl[t] * crv + 1e-13 * (cnv + fnl[t] * crv);
+              const double e = fma(gfn[t], crv, 1e-13 * cnv);
               um[t] = fmin(um[t], sc + e);
               const double lo = sc - e;
               if (lo < b[2]) {

@@ -15,7 +15,8 @@ test fixes through an imported state, at 0.5 (the filter keeps 9% of the signals
 at 0.4 (near the sequence's own cut-off, 0.16%).
 
 C5 (N = 8M Chung-Lu, 160M entries, d = 256, m = 150, p = 0.75): snapshot 2's fresh block at
-the cut-off 0.45 in each form's benchmark configuration.  Two properties that hold at any size
+the cut-off 0.45 in each form's benchmark configuration (kept basis of one snapshot, or a
+one-pass batch without kept iterates).  Two properties that hold at any size
 are checked on top: X^T h(L) X is symmetric, and the BF16S form stays within the BF16 bound of
 the FP32 form.
 """
@@ -48,6 +49,7 @@ C5_FORMS = {
     "fp32": (torch.float32, torch.float32, 1, 0, "fp32_onepass"),
     "bf16s": (BF16, "bf16s", 1, 1, "bf16s_basis_bf16copies"),
     "f16": (BF16, torch.float16, 1, 1, "f16_basis"),
+    "f16b1p": (BF16, torch.float16, 4, 0, "f16_onepass"),
 }
 
 
