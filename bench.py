@@ -262,7 +262,8 @@ def traffic_summary(args):
     cf = max(v for n, v in fetch if "copyBuffer" in n)
     cw = max(v for n, v in write if "copyBuffer" in n)
     sf, sw = gib_kib / cf, gib_kib / cw
-    sel = lambda rows: [v for n, v in rows if kname in n and "<" in n]  # noqa: E731
+    # (rocprofv3 leaves names with binary16 template arguments mangled)
+    sel = lambda rows: [v for n, v in rows if kname in n]  # noqa: E731
     stf, stw = sel(fetch), sel(write)
     per_launch = (statistics.mean(stf) * sf + statistics.mean(stw) * sw) * 1024.0
     path = traffic_path(args.workload)
