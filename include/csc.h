@@ -230,10 +230,11 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  * F (device, type f_dt, leading dimension ldf, d columns) and the k centroids C (device
  * float[k * d], row-major).  For d <= 256 and 16-byte aligned rows the scores
  * ||C_c||^2 - 2 F_i.C_c are formed on the matrix cores from exact BF16 splits of C (three
- * parts) and of FP32 rows (three parts; BF16 rows are exact): each 32-column step's leading
- * product goes to a fresh FP32 accumulator, the steps are summed in FP32, and the small cross
- * products to a second FP32 sum, so each score is within 2 * 48 * 2^-24 ||F_i|| ||C_c|| (plus
- * FP64 rounding) of its exact value.  A row with one centroid whose interval can hold the
+ * parts) and of FP32 rows (three parts; BF16 rows are exact): each pair of 32-column steps'
+ * leading products goes to a fresh FP32 accumulator, the pairs are summed in FP32, and the
+ * small cross products to a second FP32 sum; the score and its interval are formed in FP32,
+ * with a half-width of (2 * 72 + 16) * 2^-24 ||F_i|| ||C_c|| + 8 * 2^-24 ||C_c||^2 + 2^-110
+ * that covers every rounding.  A row with one centroid whose interval can hold the
  * minimum is decided; with two, both are re-scored in the FP64 direct form; with more, every
  * centroid is.  Otherwise (d > 256 or unaligned rows) candidates are ranked in FP32 and the
  * two best re-scored in FP64.  Exact ties go to the lowest index.  labels: device

@@ -52,6 +52,7 @@ __device__ inline double block_sum(double v) {
 // ---------------- assignment ----------------
 
 constexpr int kKG = 32;   // centroids per staged group
+constexpr int kGroup = 2; // 32-column MFMA steps per fresh FP32 accumulator in the assignment
 constexpr int kCH = 16;   // columns per streamed chunk
 constexpr int kRIT = 4;   // rows per thread per block
 
@@ -169,13 +170,16 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
 // runs on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16) in split precision: each FP32
 // centroid value is the sum of three BF16 parts (hi, mid, lo; residual below 2^-26 of the
 // value), and each FP32 feature likewise, so every partial product is exact in FP32.  Each
-// 32-column step of the dominant hi x hi product goes into a fresh FP32 accumulator (at
-// most 32 u of rounding, u = 2^-24, relative to the sum of its absolute products), the at
-// most eight steps are summed in FP32 (at most 7 u more), and the small cross products
-// (weights 2^-8 and below) of each step are summed in FP32 into a second accumulator; the
-// two sums meet in FP64.  The rounding of a dot product is then at most
-// E ||f|| ||c|| with E = 48 2^-24, so the exact score s*_c = ||c||^2 - 2 f.c lies in
-// [s_c - e_c, s_c + e_c] with e_c = 2 E ||f|| ||c|| (+ FP64 rounding).  The argmin is then
+// pair of 32-column steps of the dominant hi x hi product goes into a fresh FP32
+// accumulator (at most 64 u of rounding, u = 2^-24, relative to the sum of its absolute
+// products), the at most four pairs are summed in FP32 (at most 3 u more), and the small
+// cross products (weights 2^-8 and below) of each pair are summed in FP32 into a second
+// accumulator.  The rounding of a dot product is then at most E ||f|| ||c|| with
+// E = 72 2^-24.  The score s_c = ||c||^2 - 2 f.c and its ends are formed in FP32, so the exact
+// score lies in [s_c - e_c, s_c + e_c] with e_c = (2 E + 16 u) ||f|| ||c|| + 8 u ||c||^2 +
+// 2^-110: the u terms bound the FP32 rounding of ||c||^2, of the two sums, of the score and
+// of its ends (each at most u times ||c||^2 + 2 ||f|| ||c||), and the absolute term covers
+// products that underflow, so such rows are re-scored rather than misassigned.  The argmin is then
 // among the centroids whose lower end is below the smallest upper end.  Each lane keeps its
 // three smallest lower ends and the smallest upper end; after the merge across lanes a row
 // with one such candidate is certified, a row with two is re-scored against both in the
@@ -308,12 +312,14 @@ __device__ inline bf16x8 lds_bf8(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
 }
 
-__device__ inline bool sc_less(double va, int ia, double vb, int ib) {
+template <typename V>
+__device__ inline bool sc_less(V va, int ia, V vb, int ib) {
   return va < vb || (va == vb && ia < ib);
 }
 
 // insert (v, i) into the sorted list b[0..2]
-__device__ inline void top3_insert(double* b, int* ix, double v, int i) {
+template <typename V>
+__device__ inline void top3_insert(V* b, int* ix, V v, int i) {
   if (sc_less(v, i, b[2], ix[2])) {
     if (sc_less(v, i, b[1], ix[1])) {
       b[2] = b[1]; ix[2] = ix[1];
@@ -347,11 +353,14 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
   constexpr int SB = mf_sb<DP>();
   constexpr int NS = DP / 32;                      // 32-column MFMA steps
   constexpr int NP = sizeof(TF) == 4 ? 3 : 1;      // BF16 parts of a feature value
-  constexpr double E2 = 2.0 * 48.0 * 0x1p-24 * (1.0 + 0x1p-16);
+  // rounding of one group's FP32 sum of 32 kGroup products, of summing the at most 8 / kGroup
+  // groups, and 5 u for the small cross products and the FP64 meeting (72 u for pairs)
+  constexpr double E2 = 2.0 * (32.0 * kGroup + (8 / kGroup - 1) + 5) * 0x1p-24 * (1.0 + 0x1p-16);
   extern __shared__ __align__(16) unsigned char s_raw[];
   uint16_t* s_cb = reinterpret_cast<uint16_t*>(s_raw);
-  double* s_cn = reinterpret_cast<double*>(s_raw + static_cast<size_t>(3) * kc_max * SB * 2);
-  double* s_cr = s_cn + kc_max;
+  // per staged centroid: FP32 ||c||^2, ||c|| rounded up, and the score's centroid-only
+  // half-width term (one 16-byte LDS read per score)
+  float4* s_cq = reinterpret_cast<float4*>(s_raw + static_cast<size_t>(3) * kc_max * SB * 2);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
@@ -381,8 +390,8 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         for (int s = 0; s < NS; ++s)
           load_raw8<TF, FULL>(F, ldf, n, d, row_of(panel, t), s * 32 + lq * 8, raw[t][s]);
     }
-    double bl3[T][3], um[T], fnl[T], gfn[T];  // three smallest lower ends, smallest upper end,
-                                              // ||f||, (E2 + 1e-13) ||f||
+    float bl3[T][3], um[T], gfn[T];  // three smallest lower ends, smallest upper end, and the
+                                     // row's factor of the half-width
     int bi3[T][3];
     // B operand: row li, eight consecutive columns per step from 8 lq
     bf16x8 a[T][NP][NS];
@@ -412,10 +421,11 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       }
       fs += __shfl_xor(fs, 16, 64);
       fs += __shfl_xor(fs, 32, 64);
-      fnl[t] = sqrt(static_cast<double>(fs)) * (1.0 + 0x1p-16);
-      // a score's half-width: E2 ||f|| ||c|| + 1e-13 (||c||^2 + ||f|| ||c||), the last term
-      // covering the FP64 rounding of the score and of the bound itself
-      gfn[t] = (E2 + 1e-13) * fnl[t];
+      // ||f|| bounded above (the FP32 sum of at most 256 squares errs by at most 2^-16)
+      const double fnl = sqrt(static_cast<double>(fs)) * (1.0 + 0x1p-16);
+      // a score's half-width: (E2 + 16 u) ||f|| ||c|| + 8 u ||c||^2 + 2^-110; the u terms
+      // cover the FP32 rounding of the score and of its ends, the last any underflow
+      gfn[t] = static_cast<float>((E2 + 16.0 * 0x1p-24) * fnl * (1.0 + 0x1p-20));
     }
     if (PF && panel + gridDim.x < panels) {
 #pragma unroll
@@ -456,8 +466,8 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         }
         for (int c = threadIdx.x; c < kc; c += blockDim.x) {
           const double q = cn_g[c0 + c];
-          s_cn[c] = q;
-          s_cr[c] = sqrt(q);
+          s_cq[c] = make_float4(static_cast<float>(q), static_cast<float>(sqrt(q) * (1.0 + 0x1p-20)),
+                                static_cast<float>(8.0 * 0x1p-24 * q * (1.0 + 0x1p-20) + 0x1p-110), 0.f);
         }
         __syncthreads();
         staged = true;
@@ -466,17 +476,19 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         // A operand: centroid ct*16 + li; output register r of lane (li, lq) is centroid
         // ct*16 + 4 lq + r against row li of the tile
         const uint16_t* cb = s_cb + (ct * 16 + li) * SB + lq * 8;
-        // every step starts its own accumulators, so the matrix-core chains are at most
-        // three long and the steps overlap in the pipeline (one chain across all steps runs
-        // slower: each product then waits for the previous one); a step's leading and small
-        // products are then added to two running FP32 sums.  A step's three centroid
+        // every pair of steps starts its own accumulators, so the matrix-core chains are at
+        // most four long and the pairs overlap in the pipeline (one chain across all steps
+        // runs slower: each product then waits for the previous one); a pair's leading and
+        // small products are then added to two running FP32 sums.  A step's three centroid
         // fragments are read from LDS once for all T row tiles, and the next step's are
         // requested before this step's products, so the reads' latency hides behind them.
-        f32x4 dot[T], small[T];
+        f32x4 dot[T], small[T], pm[T], ps[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
           small[t] = zero4;
           dot[t] = zero4;
+          pm[t] = zero4;
+          ps[t] = zero4;
         }
         bf16x8 ch = lds_bf8(cb), cm = lds_bf8(cb + kc_max * SB), cl = lds_bf8(cb + 2 * kc_max * SB);
 #pragma unroll
@@ -489,17 +501,20 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
           }
 #pragma unroll
           for (int t = 0; t < T; ++t) {
-            const f32x4 main = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][0][s], zero4, 0, 0, 0);
-            f32x4 sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][0][s], zero4, 0, 0, 0);
-            sm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[t][0][s], sm, 0, 0, 0);
+            // steps after a group's first continue its accumulators; the group is then summed
+            const bool cont = (s % kGroup) != 0;
+            pm[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][0][s], cont ? pm[t] : zero4, 0, 0, 0);
+            ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][0][s], cont ? ps[t] : zero4, 0, 0, 0);
+            ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[t][0][s], ps[t], 0, 0, 0);
             if constexpr (NP == 3) {
-              f32x4 sm2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][1][s], zero4, 0, 0, 0);
-              sm2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][1][s], sm2, 0, 0, 0);
-              sm2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][2][s], sm2, 0, 0, 0);
-              sm += sm2;
+              ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][1][s], ps[t], 0, 0, 0);
+              ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][1][s], ps[t], 0, 0, 0);
+              ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][2][s], ps[t], 0, 0, 0);
             }
-            small[t] += sm;
-            dot[t] += main;
+            if (s % kGroup == kGroup - 1 || s + 1 == NS) {
+              small[t] += ps[t];
+              dot[t] += pm[t];
+            }
           }
           ch = nh;
           cm = nm;
@@ -511,20 +526,19 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
           for (int r = 0; r < 4; ++r) {
             const int lc = ct * 16 + mf_drow(r, lq);
             const int cent = c0 + lc;
-            double* b = bl3[t];
+            float* b = bl3[t];
             int* ix = bi3[t];
             if constexpr (T == 1 && NP == 1) {
               // sorted insertion of (lo, cent) into the three smallest lower ends, as selects
               // (no branches, so no register shuffling at joins); centroids arrive in
               // increasing index order within a lane, and strict < keeps ties on the lower
               // index
-              const double cnv = s_cn[lc];
-              const double crv = s_cr[lc];
-              const double sc = cnv - 2.0 * (static_cast<double>(dot[t][r]) + static_cast<double>(small[t][r]));
-              const double e = fma(gfn[t], crv, 1e-13 * cnv);
+              const float4 cq = s_cq[lc];
+              const float sc = fmaf(-2.f, dot[t][r] + small[t][r], cq.x);
+              const float e = fmaf(gfn[t], cq.y, cq.z);
               const bool real = cent < k;
-              um[t] = real ? fmin(um[t], sc + e) : um[t];
-              const double lo = real ? sc - e : INFINITY;
+              um[t] = real ? fminf(um[t], sc + e) : um[t];
+              const float lo = real ? sc - e : INFINITY;
               const bool l0 = lo < b[0], l1 = lo < b[1], l2 = lo < b[2];
               b[2] = l1 ? b[1] : (l2 ? lo : b[2]);
               ix[2] = l1 ? ix[1] : (l2 ? cent : ix[2]);
@@ -535,12 +549,11 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
             } else if (cent < k) {
               // the same insertion with branches (two row tiles or FP32 rows: the selects'
               // extra live registers would cost occupancy or spill)
-              const double cnv = s_cn[lc];
-              const double crv = s_cr[lc];
-              const double sc = cnv - 2.0 * (static_cast<double>(dot[t][r]) + static_cast<double>(small[t][r]));
-              const double e = fma(gfn[t], crv, 1e-13 * cnv);
-              um[t] = fmin(um[t], sc + e);
-              const double lo = sc - e;
+              const float4 cq = s_cq[lc];
+              const float sc = fmaf(-2.f, dot[t][r] + small[t][r], cq.x);
+              const float e = fmaf(gfn[t], cq.y, cq.z);
+              um[t] = fminf(um[t], sc + e);
+              const float lo = sc - e;
               if (lo < b[2]) {
                 if (lo < b[1]) {
                   b[2] = b[1]; ix[2] = ix[1];
@@ -559,18 +572,18 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
     for (int t = 0; t < T; ++t) {
       const int64_t row = row_of(panel, t);
       const bool valid = row < n;
-      double* b = bl3[t];
+      float* b = bl3[t];
       int* ix = bi3[t];
       // merge over the four lanes of the row (lq), in (value, index) order
 #pragma unroll
       for (int off = 16; off < 64; off <<= 1) {
-        double ob[3];
+        float ob[3];
         int oi[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) { ob[q] = __shfl_xor(b[q], off, 64); oi[q] = __shfl_xor(ix[q], off, 64); }
 #pragma unroll
         for (int q = 0; q < 3; ++q) top3_insert(b, ix, ob[q], oi[q]);
-        um[t] = fmin(um[t], __shfl_xor(um[t], off, 64));
+        um[t] = fminf(um[t], __shfl_xor(um[t], off, 64));
       }
       // candidates: lower end not above the smallest upper end (the first always is)
       const bool certain = !valid || ix[1] >= k || b[1] > um[t];
