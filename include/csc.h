@@ -229,12 +229,13 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  * csc_kmeans_assign: labels[i] = argmin_c sum_t (F[i, t] - C[c, t])^2 for the n rows of
  * F (device, type f_dt, leading dimension ldf, d columns) and the k centroids C (device
  * float[k * d], row-major).  For d <= 256 and 16-byte aligned rows the scores
- * ||C_c||^2 - 2 F_i.C_c are formed on the matrix cores from exact BF16 splits of C (three
- * parts) and of FP32 rows (three parts; BF16 rows are exact): each pair of 32-column steps'
- * leading products goes to a fresh FP32 accumulator, the pairs are summed in FP32, and the
- * small cross products to a second FP32 sum; the score and its interval are formed in FP32,
- * with a half-width of (2 * 72 + 16) * 2^-24 ||F_i|| ||C_c|| + 8 * 2^-24 ||C_c||^2 + 2^-110
- * that covers every rounding.  A row with one centroid whose interval can hold the
+ * ||C_c||^2 - 2 F_i.C_c are formed on the matrix cores from two BF16 parts of C (hi, mid;
+ * the rest, R_c, within 2^-16 of each value) and exact BF16 splits of FP32 rows (three parts;
+ * BF16 rows are exact): each pair of 32-column steps' leading products goes to a fresh FP32
+ * accumulator, the pairs are summed in FP32, and the small cross products to a second FP32
+ * sum; the score and its interval are formed in FP32, with a half-width of
+ * (2 * 72 + 16) * 2^-24 ||F_i|| ||C_c|| + 2 ||F_i|| ||R_c|| + 8 * 2^-24 ||C_c||^2 + 2^-110
+ * that covers the dropped part and every rounding.  A row with one centroid whose interval can hold the
  * minimum is decided; with two, both are re-scored in the FP64 direct form; with more, every
  * centroid is.  Otherwise (d > 256 or unaligned rows) candidates are ranked in FP32 and the
  * two best re-scored in FP64.  Exact ties go to the lowest index.  labels: device
@@ -270,7 +271,7 @@ csc_status csc_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int64_t
 /* csc_kmeans_assign_noalloc: for callers that cannot allocate device memory (code under
  * HIP graph capture, serving loops, harnesses that forbid hipMalloc), the same assignment as
  * csc_kmeans_assign without best-distance sums or workspace: labels and best_d2 as there.
- * Its split centroids live in a static device array of the library (400 KiB per device,
+ * Its split centroids live in a static device array of the library (256 KiB per device,
  * held until the process ends), so it takes k <= 240 and d <= 256 (CSC_E_ARG beyond) and
  * calls no allocating routine.  Every call on a device uses that device's one array: calls
  * that overlap on one device race.  Asynchronous. */

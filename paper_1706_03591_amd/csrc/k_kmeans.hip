@@ -53,6 +53,7 @@ __device__ inline double block_sum(double v) {
 
 constexpr int kKG = 32;   // centroids per staged group
 constexpr int kGroup = 2; // 32-column MFMA steps per fresh FP32 accumulator in the assignment
+constexpr int kCParts = 2; // BF16 parts of a centroid value on the matrix cores (hi, mid)
 constexpr int kCH = 16;   // columns per streamed chunk
 constexpr int kRIT = 4;   // rows per thread per block
 
@@ -168,18 +169,21 @@ __global__ __launch_bounds__(kThreads) void k_assign(const TF* F, int64_t ldf, i
 
 // MFMA form of the assignment (d <= 256).  The cross term F C^T is a dense contraction and
 // runs on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16) in split precision: each FP32
-// centroid value is the sum of three BF16 parts (hi, mid, lo; residual below 2^-26 of the
-// value), and each FP32 feature likewise, so every partial product is exact in FP32.  Each
-// pair of 32-column steps of the dominant hi x hi product goes into a fresh FP32
-// accumulator (at most 64 u of rounding, u = 2^-24, relative to the sum of its absolute
-// products), the at most four pairs are summed in FP32 (at most 3 u more), and the small
-// cross products (weights 2^-8 and below) of each pair are summed in FP32 into a second
-// accumulator.  The rounding of a dot product is then at most E ||f|| ||c|| with
-// E = 72 2^-24.  The score s_c = ||c||^2 - 2 f.c and its ends are formed in FP32, so the exact
-// score lies in [s_c - e_c, s_c + e_c] with e_c = (2 E + 16 u) ||f|| ||c|| + 8 u ||c||^2 +
-// 2^-110: the u terms bound the FP32 rounding of ||c||^2, of the two sums, of the score and
-// of its ends (each at most u times ||c||^2 + 2 ||f|| ||c||), and the absolute term covers
-// products that underflow, so such rows are re-scored rather than misassigned.  The argmin is then
+// centroid value is rounded to two BF16 parts (hi, mid); what they leave out, r_c (at most
+// 2^-16 of each value), moves a dot product by at most ||f|| ||r_c||, with ||r_c|| computed
+// exactly per centroid.  Each FP32 feature is split into three BF16 parts (BF16 features are
+// their own single part), so every partial product is exact in FP32.  Each pair of 32-column steps of the dominant hi x hi product
+// goes into a fresh FP32 accumulator (at most 64 u of rounding, u = 2^-24, relative to the
+// sum of its absolute products), the at most four pairs are summed in FP32 (at most 3 u
+// more), and the small cross products (weights 2^-8 and below) of each pair are summed in
+// FP32 into a second accumulator (5 u covers them and the dropped row-part products).  A dot
+// product is then within E ||f|| ||c|| + ||f|| ||r_c|| of f.c with E = 72 2^-24.  The score
+// s_c = ||c||^2 - 2 f.c and its ends are formed in FP32, so the exact score lies in
+// [s_c - e_c, s_c + e_c] with e_c = (2 E + 16 u) ||f|| ||c|| + 2 ||f|| ||r_c|| + 8 u ||c||^2 +
+// 2^-110: the u
+// terms bound the FP32 rounding of ||c||^2, of the two sums, of the score and of its ends
+// (each at most u times ||c||^2 + 2 ||f|| ||c||), and the absolute term covers products that
+// underflow, so such rows are re-scored rather than misassigned.  The argmin is then
 // among the centroids whose lower end is below the smallest upper end.  Each lane keeps its
 // three smallest lower ends and the smallest upper end; after the merge across lanes a row
 // with one such candidate is certified, a row with two is re-scored against both in the
@@ -205,7 +209,9 @@ __host__ __device__ inline void split3(float x, uint16_t& h, uint16_t& m, uint16
   l = f32_to_bf16(rem);
 }
 
-// parts[(p * kp + c) * DP + col], p = 0 hi, 1 mid, 2 lo; zero for c >= k or col >= d.
+// parts[(p * kp + c) * DP + col], p = 0 hi, 1 mid (the lo part is dropped: its value, at most
+// 2^-16 of the centroid value, is carried by the score's error bound); zero for c >= k or
+// col >= d.
 __global__ void k_prep_centroids(const float* C, int k, int d, int kp, int DP, uint16_t* parts) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= kp * DP) return;
@@ -215,21 +221,33 @@ __global__ void k_prep_centroids(const float* C, int k, int d, int kp, int DP, u
   split3(x, h, m, l);
   parts[t] = h;
   parts[static_cast<int64_t>(kp) * DP + t] = m;
-  parts[2 * static_cast<int64_t>(kp) * DP + t] = l;
 }
 
-// cn[c] = ||C_c||^2 in FP64 for c < k, +inf for the padding up to kp; one wave per centroid.
+// cn[c] = ||C_c||^2 in FP64 for c < k, +inf for the padding up to kp, and cn[kp + c] = the
+// 2-norm of what the two BF16 parts leave out of C_c (exact: the split's differences are exact
+// in FP32); one wave per centroid.
 __global__ void k_centroid_norms(const float* C, int k, int d, int kp, double* cn) {
   const int c = blockIdx.x;
-  double q = 0.0;
+  double q = 0.0, rq = 0.0;
   if (c < k)
     for (int col = threadIdx.x; col < d; col += 64) {
-      const double v = static_cast<double>(C[static_cast<int64_t>(c) * d + col]);
+      const float x = C[static_cast<int64_t>(c) * d + col];
+      uint16_t h, m, l;
+      split3(x, h, m, l);
+      const double v = static_cast<double>(x);
+      const double r = (v - static_cast<double>(bf16_to_f32(h))) - static_cast<double>(bf16_to_f32(m));
       q += v * v;
+      rq += r * r;
     }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-  if (threadIdx.x == 0) cn[c] = c < k ? q : INFINITY;
+  for (int off = 32; off > 0; off >>= 1) {
+    q += __shfl_xor(q, off, 64);
+    rq += __shfl_xor(rq, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    cn[c] = c < k ? q : INFINITY;
+    cn[kp + c] = sqrt(rq);
+  }
 }
 
 // eight consecutive values of row `row` from column col (zeros past d or n)
@@ -331,13 +349,13 @@ __device__ inline void top3_insert(V* b, int* ix, V v, int i) {
   }
 }
 
-// LDS layout of one staged chunk: 3 parts x kc_max rows of SB = DP + 8 bf16, then kc_max
-// FP64 squared norms and kc_max FP64 norms.
+// LDS layout of one staged chunk: kCParts parts x kc_max rows of SB = DP + 8 bf16, then
+// kc_max 16-byte records of FP32 norm terms.
 template <int DP>
 __host__ __device__ constexpr int mf_sb() { return DP + 8; }
 
 inline size_t mf_lds_bytes(int DP, int kc_max) {
-  return static_cast<size_t>(3) * kc_max * (DP + 8) * 2 + static_cast<size_t>(kc_max) * 16;
+  return static_cast<size_t>(kCParts) * kc_max * (DP + 8) * 2 + static_cast<size_t>(kc_max) * 16;
 }
 
 // T row tiles per wave and WV waves per block (T > 1 and WV = 8 when the centroids need
@@ -354,18 +372,21 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
   constexpr int NS = DP / 32;                      // 32-column MFMA steps
   constexpr int NP = sizeof(TF) == 4 ? 3 : 1;      // BF16 parts of a feature value
   // rounding of one group's FP32 sum of 32 kGroup products, of summing the at most 8 / kGroup
-  // groups, and 5 u for the small cross products and the FP64 meeting (72 u for pairs)
+  // groups, and 5 u for the small cross products and the dropped products of the row parts
+  // (72 u for pairs); the centroid's dropped part enters through its own norm
   constexpr double E2 = 2.0 * (32.0 * kGroup + (8 / kGroup - 1) + 5) * 0x1p-24 * (1.0 + 0x1p-16);
   extern __shared__ __align__(16) unsigned char s_raw[];
   uint16_t* s_cb = reinterpret_cast<uint16_t*>(s_raw);
   // per staged centroid: FP32 ||c||^2, ||c|| rounded up, and the score's centroid-only
   // half-width term (one 16-byte LDS read per score)
-  float4* s_cq = reinterpret_cast<float4*>(s_raw + static_cast<size_t>(3) * kc_max * SB * 2);
+  float4* s_cq = reinterpret_cast<float4*>(s_raw + static_cast<size_t>(kCParts) * kc_max * SB * 2);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int nchunks = (kp + kc_max - 1) / kc_max;
   const int64_t panels = (n + 16 * WV * T - 1) / (16 * WV * T);
+  // centroid rows readable as 16-byte pieces
+  const bool cvec = d % 4 == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0;
   const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
   double objsum = 0.0;
   bool staged = false;
@@ -390,8 +411,8 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         for (int s = 0; s < NS; ++s)
           load_raw8<TF, FULL>(F, ldf, n, d, row_of(panel, t), s * 32 + lq * 8, raw[t][s]);
     }
-    float bl3[T][3], um[T], gfn[T];  // three smallest lower ends, smallest upper end, and the
-                                     // row's factor of the half-width
+    // three smallest lower ends, smallest upper end, and the row's factors of the half-width
+    float bl3[T][3], um[T], gfn[T], rfn[T];
     int bi3[T][3];
     // B operand: row li, eight consecutive columns per step from 8 lq
     bf16x8 a[T][NP][NS];
@@ -423,9 +444,11 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       fs += __shfl_xor(fs, 32, 64);
       // ||f|| bounded above (the FP32 sum of at most 256 squares errs by at most 2^-16)
       const double fnl = sqrt(static_cast<double>(fs)) * (1.0 + 0x1p-16);
-      // a score's half-width: (E2 + 16 u) ||f|| ||c|| + 8 u ||c||^2 + 2^-110; the u terms
-      // cover the FP32 rounding of the score and of its ends, the last any underflow
+      // a score's half-width: (E2 + 16 u) ||f|| ||c|| + 2 ||f|| ||r_c|| + 8 u ||c||^2 + 2^-110
+      // (r_c what the centroid's two parts leave out); the u terms cover the FP32 rounding of
+      // the score and of its ends, the last any underflow
       gfn[t] = static_cast<float>((E2 + 16.0 * 0x1p-24) * fnl * (1.0 + 0x1p-20));
+      rfn[t] = static_cast<float>(fnl * (1.0 + 0x1p-20));
     }
     if (PF && panel + gridDim.x < panels) {
 #pragma unroll
@@ -445,7 +468,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         constexpr int vpr = DP / 8;
         const int per = kc * vpr;
 #pragma unroll
-        for (int pp = 0; pp < 3; ++pp) {
+        for (int pp = 0; pp < kCParts; ++pp) {
           const uint16_t* src = parts + (static_cast<int64_t>(pp) * kp + c0) * DP;
           uint16_t* dst = s_cb + pp * kc_max * SB;
           for (int q0 = threadIdx.x; q0 < per; q0 += SU * blockDim.x) {
@@ -467,7 +490,8 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
         for (int c = threadIdx.x; c < kc; c += blockDim.x) {
           const double q = cn_g[c0 + c];
           s_cq[c] = make_float4(static_cast<float>(q), static_cast<float>(sqrt(q) * (1.0 + 0x1p-20)),
-                                static_cast<float>(8.0 * 0x1p-24 * q * (1.0 + 0x1p-20) + 0x1p-110), 0.f);
+                                static_cast<float>(8.0 * 0x1p-24 * q * (1.0 + 0x1p-20) + 0x1p-110),
+                                static_cast<float>(2.0 * cn_g[kp + c0 + c] * (1.0 + 0x1p-20)));
         }
         __syncthreads();
         staged = true;
@@ -490,14 +514,13 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
           pm[t] = zero4;
           ps[t] = zero4;
         }
-        bf16x8 ch = lds_bf8(cb), cm = lds_bf8(cb + kc_max * SB), cl = lds_bf8(cb + 2 * kc_max * SB);
+        bf16x8 ch = lds_bf8(cb), cm = lds_bf8(cb + kc_max * SB);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          bf16x8 nh = ch, nm = cm, nl = cl;
+          bf16x8 nh = ch, nm = cm;
           if (s + 1 < NS) {
             nh = lds_bf8(cb + (s + 1) * 32);
             nm = lds_bf8(cb + kc_max * SB + (s + 1) * 32);
-            nl = lds_bf8(cb + 2 * kc_max * SB + (s + 1) * 32);
           }
 #pragma unroll
           for (int t = 0; t < T; ++t) {
@@ -505,7 +528,6 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
             const bool cont = (s % kGroup) != 0;
             pm[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][0][s], cont ? pm[t] : zero4, 0, 0, 0);
             ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][0][s], cont ? ps[t] : zero4, 0, 0, 0);
-            ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, a[t][0][s], ps[t], 0, 0, 0);
             if constexpr (NP == 3) {
               ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, a[t][1][s], ps[t], 0, 0, 0);
               ps[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, a[t][1][s], ps[t], 0, 0, 0);
@@ -518,7 +540,6 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
           }
           ch = nh;
           cm = nm;
-          cl = nl;
         }
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -535,7 +556,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
               // index
               const float4 cq = s_cq[lc];
               const float sc = fmaf(-2.f, dot[t][r] + small[t][r], cq.x);
-              const float e = fmaf(gfn[t], cq.y, cq.z);
+              const float e = fmaf(rfn[t], cq.w, fmaf(gfn[t], cq.y, cq.z));
               const bool real = cent < k;
               um[t] = real ? fminf(um[t], sc + e) : um[t];
               const float lo = real ? sc - e : INFINITY;
@@ -551,7 +572,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
               // extra live registers would cost occupancy or spill)
               const float4 cq = s_cq[lc];
               const float sc = fmaf(-2.f, dot[t][r] + small[t][r], cq.x);
-              const float e = fmaf(gfn[t], cq.y, cq.z);
+              const float e = fmaf(rfn[t], cq.w, fmaf(gfn[t], cq.y, cq.z));
               um[t] = fminf(um[t], sc + e);
               const float lo = sc - e;
               if (lo < b[2]) {
@@ -590,36 +611,65 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       const bool pair = !certain && (ix[2] >= k || b[2] > um[t]);
       int lab = ix[0] < k ? ix[0] : 0;  // (no candidate only with NaN features)
       double best = 0.0;
+      // FP64 squared distance from the row to centroid c (the direct form): each lane covers
+      // the columns s * 32 + 8 lq + i of the row (just read, so cached) and of the centroid,
+      // four 32-column steps per round with their loads in flight together; the four lanes of
+      // the row then add their sums.
+      auto dist_to = [&](int c) -> double {
+        const float* crow = C + static_cast<int64_t>(c) * d;
+        constexpr int SG = NS < 4 ? NS : 4;
+        double e = 0.0;
+#pragma unroll 1
+        for (int s0 = 0; s0 < NS; s0 += SG) {
+          u32x4 fr[SG][RW];
+          float cv[SG][8];
+#pragma unroll
+          for (int g = 0; g < SG; ++g) {
+            const int col0 = (s0 + g) * 32 + lq * 8;
+            load_raw8<TF, FULL>(F, ldf, n, d, row, col0, fr[g]);
+            if (cvec && col0 + 8 <= d) {
+              const float4 u0 = reinterpret_cast<const float4*>(crow + col0)[0];
+              const float4 u1 = reinterpret_cast<const float4*>(crow + col0)[1];
+              cv[g][0] = u0.x; cv[g][1] = u0.y; cv[g][2] = u0.z; cv[g][3] = u0.w;
+              cv[g][4] = u1.x; cv[g][5] = u1.y; cv[g][6] = u1.z; cv[g][7] = u1.w;
+            } else {
+#pragma unroll
+              for (int q = 0; q < 8; ++q) cv[g][q] = col0 + q < d ? crow[col0 + q] : 0.f;
+            }
+          }
+#pragma unroll
+          for (int g = 0; g < SG; ++g) {
+            float fv[8];
+            raw8_to_f<TF>(fr[g], fv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const double tv = static_cast<double>(fv[q]) - static_cast<double>(cv[g][q]);
+              e += tv * tv;
+            }
+          }
+        }
+        e += __shfl_xor(e, 16, 64);
+        e += __shfl_xor(e, 32, 64);
+        return e;
+      };
       if (!certain) {
-        // FP64 direct form against the candidates (the two best, else every centroid); the
-        // four lanes of the row split the columns
-        const int nc = pair ? 2 : k;
+        // the direct form against the candidates: the two best, else every centroid
         double be = INFINITY;
         int bl = 0x7fffffff;
-        for (int q = 0; q < nc; ++q) {
-          const int c = pair ? (q == 0 ? ix[0] : ix[1]) : q;
-          double e = 0.0;
-          for (int col = lq; col < d; col += 4) {
-            const double tv = static_cast<double>(to_f<TF>(F[row * ldf + col])) -
-                              static_cast<double>(C[static_cast<int64_t>(c) * d + col]);
-            e += tv * tv;
+        if (pair) {
+          const double e0 = dist_to(ix[0]), e1 = dist_to(ix[1]);
+          if (sc_less(e0, ix[0], be, bl)) { be = e0; bl = ix[0]; }
+          if (sc_less(e1, ix[1], be, bl)) { be = e1; bl = ix[1]; }
+        } else {
+          for (int c = 0; c < k; ++c) {
+            const double e = dist_to(c);
+            if (sc_less(e, c, be, bl)) { be = e; bl = c; }
           }
-          e += __shfl_xor(e, 16, 64);
-          e += __shfl_xor(e, 32, 64);
-          if (sc_less(e, c, be, bl)) { be = e; bl = c; }
         }
         lab = bl;
         best = be;
       } else if (valid && (best_d2 || obj_part)) {
-        double e = 0.0;
-        for (int col = lq; col < d; col += 4) {
-          const double tv = static_cast<double>(to_f<TF>(F[row * ldf + col])) -
-                            static_cast<double>(C[static_cast<int64_t>(lab) * d + col]);
-          e += tv * tv;
-        }
-        e += __shfl_xor(e, 16, 64);
-        e += __shfl_xor(e, 32, 64);
-        best = e;
+        best = dist_to(lab);
       }
       if (valid && lq == 0) {
         labels[row] = lab;
@@ -1308,11 +1358,12 @@ MfPlan mf_plan(int64_t n, int d, int k, bool bf16_rows = false) {
   return P;
 }
 
-// centroid scratch of the MFMA assignment: three BF16 parts (kp x DP each), then kp norms
+// centroid scratch of the MFMA assignment: two BF16 parts (kp x DP each), then kp squared
+// norms and kp norms of what the parts leave out
 size_t mf_scratch_bytes(int k, int d) {
   const MfPlan P = mf_plan(1, d, k);
   if (!P.DP) return 0;
-  return align_up(static_cast<size_t>(3) * P.kp * P.DP * 2) + static_cast<size_t>(P.kp) * 8;
+  return align_up(static_cast<size_t>(kCParts) * P.kp * P.DP * 2) + static_cast<size_t>(P.kp) * 16;
 }
 
 size_t assign_scratch_bytes(int k, int d) {
@@ -1331,7 +1382,7 @@ static csc_status assign_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_
   if (P.DP && rows_aligned(F, f_dt, ldf)) {
     auto* parts = reinterpret_cast<uint16_t*>(Cp);
     auto* cn = reinterpret_cast<double*>(reinterpret_cast<char*>(Cp) +
-                                         align_up(static_cast<size_t>(3) * P.kp * P.DP * 2));
+                                         align_up(static_cast<size_t>(kCParts) * P.kp * P.DP * 2));
     hipLaunchKernelGGL(k_prep_centroids, dim3((P.kp * P.DP + 255) / 256), dim3(256), 0, s, C, k, d,
                        P.kp, P.DP, parts);
     hipLaunchKernelGGL(k_centroid_norms, dim3(P.kp), dim3(64), 0, s, C, k, d, P.kp, cn);
@@ -1408,7 +1459,7 @@ csc_status launch_kmeans_assign(const void* F, csc_dtype f_dt, int64_t ldf, int6
 // calls that overlap on one device race.
 
 namespace {
-constexpr size_t kStaticScratch = 400 * 1024;
+constexpr size_t kStaticScratch = 256 * 1024;
 __device__ __align__(256) unsigned char scratch[kStaticScratch];
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
