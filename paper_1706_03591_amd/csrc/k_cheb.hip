@@ -33,6 +33,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kStageCap = 2048;  // CSR entries staged in LDS per block
+constexpr int kLight = 32;       // a heavy block's rows up to this many entries: one row group
 
 enum : int { F_FIRST = 1, F_ACC = 2, F_LAST = 4, F_MOM = 8, F_STORE = 16, F_OWN = 32 };
 
@@ -303,56 +304,93 @@ __device__ inline void step_body(const StepParams& p, const int64_t bid, const i
     }
   } else {
     // Heavy block (more CSR entries than the LDS stage holds, e.g. the hubs of a power-law
-    // graph): its rows are taken one at a time by all RPB row groups, group g summing the
-    // entries rs + g, rs + g + RPB, ...; the partial sums meet in LDS (the unused stage) in
-    // group order, so the result does not depend on scheduling.
+    // graph).  Its light rows (at most kLight entries) are summed by their own row group,
+    // reading the CSR from global memory.  Its other rows are taken one at a time by all RPB
+    // row groups: the row's entries pass through LDS in chunks of kChunk (a multiple of RPB),
+    // group g sums the entries rs + g, rs + g + RPB, ... eight gathers at a time, and the
+    // partial sums meet in LDS in group order, so the result does not depend on scheduling.
+    constexpr int kChunk = kStageCap / 2;
     static_assert(kThreads * VEC <= kStageCap, "reduction buffer must fit the stage");
-    float* s_red = reinterpret_cast<float*>(s_col);  // RPB x LPR x VEC = kThreads * VEC floats
+    static_assert(kChunk % RPB == 0, "chunks must keep each group's entries");
+    // reduction buffer: the upper halves of the stage (kThreads * VEC floats)
+    auto red = [&](int i) -> float& {
+      return i < kStageCap / 2 ? reinterpret_cast<float*>(s_col)[kStageCap / 2 + i] : s_val[i];
+    };
+    if (row < p.n) {
+      const int32_t rs = p.rowptr[row], re = p.rowptr[row + 1];
+      if (re - rs <= kLight) {
+        int32_t e = rs;
+        for (; e + 8 <= re; e += 8) {
+          int32_t c[8];
+          float v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) { c[q] = p.colidx[e + q]; v[q] = val_f<TV>(vals[e + q]); }
+          uint4 g[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) g[q] = ld16(zc + static_cast<int64_t>(c[q]) * WT);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            float f[VEC];
+            P::unpack(g[q], f);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v[q], f[i], acc[i]);
+          }
+        }
+        for (; e < re; ++e) {
+          const uint4 g = ld16(zc + static_cast<int64_t>(p.colidx[e]) * WT);
+          float f[VEC];
+          P::unpack(g, f);
+          const float v = val_f<TV>(vals[e]);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc[i] = fmaf(v, f[i], acc[i]);
+        }
+      }
+    }
     for (int rr = 0; rr < RPB && r0 + rr < p.n; ++rr) {
       const int64_t rw = r0 + rr;
       const int32_t rs = p.rowptr[rw], re = p.rowptr[rw + 1];
+      if (re - rs <= kLight) continue;  // (uniform over the block)
       float part[VEC];
 #pragma unroll
       for (int i = 0; i < VEC; ++i) part[i] = 0.f;
-      int32_t e = rs + grp;
-      for (; e + 3 * RPB < re; e += 4 * RPB) {
-        const int32_t c0 = p.colidx[e], c1 = p.colidx[e + RPB], c2 = p.colidx[e + 2 * RPB],
-                      c3 = p.colidx[e + 3 * RPB];
-        const float v0 = val_f<TV>(vals[e]), v1 = val_f<TV>(vals[e + RPB]),
-                    v2 = val_f<TV>(vals[e + 2 * RPB]), v3 = val_f<TV>(vals[e + 3 * RPB]);
-        const uint4 g0 = ld16(zc + static_cast<int64_t>(c0) * WT);
-        const uint4 g1 = ld16(zc + static_cast<int64_t>(c1) * WT);
-        const uint4 g2 = ld16(zc + static_cast<int64_t>(c2) * WT);
-        const uint4 g3 = ld16(zc + static_cast<int64_t>(c3) * WT);
-        float f[VEC];
-        P::unpack(g0, f);
+      for (int32_t c0 = rs; c0 < re; c0 += kChunk) {
+        const int32_t cn = min(kChunk, re - c0);
+        __syncthreads();  // the previous chunk's readers are done
+        for (int32_t i = threadIdx.x; i < cn; i += kThreads) {
+          s_col[i] = p.colidx[c0 + i];
+          s_val[i] = val_f<TV>(vals[c0 + i]);
+        }
+        __syncthreads();
+        int32_t l = grp;
+        for (; l + 7 * RPB < cn; l += 8 * RPB) {
+          uint4 g[8];
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v0, f[i], part[i]);
-        P::unpack(g1, f);
+          for (int q = 0; q < 8; ++q) g[q] = ld16(zc + static_cast<int64_t>(s_col[l + q * RPB]) * WT);
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v1, f[i], part[i]);
-        P::unpack(g2, f);
+          for (int q = 0; q < 8; ++q) {
+            float f[VEC];
+            P::unpack(g[q], f);
+            const float v = s_val[l + q * RPB];
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v2, f[i], part[i]);
-        P::unpack(g3, f);
+            for (int i = 0; i < VEC; ++i) part[i] = fmaf(v, f[i], part[i]);
+          }
+        }
+        for (; l < cn; l += RPB) {
+          const uint4 g = ld16(zc + static_cast<int64_t>(s_col[l]) * WT);
+          float f[VEC];
+          P::unpack(g, f);
+          const float v = s_val[l];
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v3, f[i], part[i]);
+          for (int i = 0; i < VEC; ++i) part[i] = fmaf(v, f[i], part[i]);
+        }
       }
-      for (; e < re; e += RPB) {
-        const uint4 g = ld16(zc + static_cast<int64_t>(p.colidx[e]) * WT);
-        float f[VEC];
-        P::unpack(g, f);
-        const float v = val_f<TV>(vals[e]);
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) part[i] = fmaf(v, f[i], part[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < VEC; ++i) s_red[(grp * LPR + lane) * VEC + i] = part[i];
+      for (int i = 0; i < VEC; ++i) red((grp * LPR + lane) * VEC + i) = part[i];
       __syncthreads();
       if (grp == rr) {
         for (int g = 0; g < RPB; ++g)
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) acc[i] += s_red[(g * LPR + lane) * VEC + i];
+          for (int i = 0; i < VEC; ++i) acc[i] += red((g * LPR + lane) * VEC + i);
       }
       __syncthreads();
     }
