@@ -854,7 +854,7 @@ def run_kassign(args):
     torch.cuda.synchronize()
     km_ms = (time.perf_counter() - t0) * 1e3
     kp = (k + 15) // 16 * 16
-    flops = 2.0 * n * kp * d * 3  # hi x hi plus the two small cross products per 32-column step
+    flops = 2.0 * n * kp * d * 2  # the rows against the centroids' hi and mid BF16 parts
     gbps = n * d * 2 / (ms * 1e-3) / 1e9
     log(f"[bench] assignment {ms:.3f} ms ({gbps:.0f} GB/s of rows, {flops / (ms * 1e-3) / 1e12:.0f} "
         f"TFLOP/s of split products); k-means++ + 20 Lloyd rounds {km_ms:.1f} ms")

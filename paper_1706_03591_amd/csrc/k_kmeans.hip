@@ -460,7 +460,7 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       const int kc = min(kc_max, kp - c0);
       if (nchunks > 1 || !staged) {
         __syncthreads();
-        // 16-byte copies of the chunk's three parts, SU loads in flight per thread (the last
+        // 16-byte copies of the chunk's kCParts parts, SU loads in flight per thread (the last
         // group re-reads the final piece instead of branching), then its norms.  A part's
         // chunk is contiguous in global memory (piece q at 8 q); in LDS its rows are padded
         // to SB, so piece q goes to row q / vpr (a shift: vpr is a power of two).

@@ -35,12 +35,14 @@ def c1():
     return g, A, lam, U, c_phi
 
 
+# the cut-off from a dense eigendecomposition for every form; from the eigencount dichotomy on
+# the signals themselves for FP32, the split BF16 form and the binary16 headline form
+CASES = [("eigh", f) for f in FORMS] + [("eigcount", f) for f in ("fp32", "bf16s", "f16")]
+
+
 @pytest.mark.parametrize("d", [32, 256])
-@pytest.mark.parametrize("form", list(FORMS))
-@pytest.mark.parametrize("cut", ["eigh", "eigcount"])
+@pytest.mark.parametrize("cut,form", CASES)
 def test_static_csc_quality(csc, c1, form, d, cut):
-    if cut == "eigcount" and form not in ("fp32", "bf16s"):
-        pytest.skip("the dichotomy is covered by the FP32 and BF16S forms")
     g, A, lam, U, c_phi = c1
     feat, iters, vals = FORMS[form]
     store = "f32" if feat == torch.float32 else "bf16"
