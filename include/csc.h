@@ -237,8 +237,10 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  * (2 * 72 + 16) * 2^-24 ||F_i|| ||C_c|| + 2 ||F_i|| ||R_c|| + 8 * 2^-24 ||C_c||^2 + 2^-110
  * that covers the dropped part and every rounding.  A row with one centroid whose interval can hold the
  * minimum is decided; with two, both are re-scored in the FP64 direct form; with more, every
- * centroid is.  Otherwise (d > 256 or unaligned rows) candidates are ranked in FP32 and the
- * two best re-scored in FP64.  Exact ties go to the lowest index.  labels: device
+ * centroid is.  Rows that are not 16-byte aligned take a vector path instead: candidates are
+ * ranked in FP32 and the two best re-scored in FP64.  Exact ties go to the lowest index.
+ * Every k-means call takes 1 <= d <= 256 columns and 1 <= k <= 240 centroids (CSC_E_ARG
+ * otherwise, before any device memory is touched).  labels: device
  * int32[n]; best_d2: device float[n] (the FP64 squared distance to the chosen centroid,
  * rounded) or NULL.  sums (device float[k * d]) and counts (device int32[k]), each
  * optional: the Lloyd partial sums of the new assignment, sums[c] = the sum of the rows

@@ -100,6 +100,13 @@ def test_host_argument_errors(pkg):
     bad = pkg.binding.DynOpts(keep_iterates=0, lloyd_iters=-1, refresh_budget=0.1)
     assert lib.csc_dyn_create(100, 8, 2, 0.5, 10, 1, 0, 1, ctypes.byref(bad), ctypes.byref(out)) == 1
     assert lib.csc_dyn_create(100, 8, 2, 0.5, 10, 1, 5, 1, ctypes.byref(opts), ctypes.byref(out)) == 3
+    # k-means sizes beyond 256 columns or 240 centroids are refused before any device access
+    assert lib.csc_kmeans_assign(fake, 0, 257, 10, 257, fake, 5, fake, None, None, None, fake,
+                                 1 << 30, None) == 1
+    assert b"d must be <= 256" in lib.csc_last_error()
+    assert lib.csc_kmeans_assign(fake, 0, 256, 1000, 256, fake, 241, fake, None, None, None, fake,
+                                 1 << 30, None) == 1
+    assert b"k must be <= 240" in lib.csc_last_error()
     # null handles
     assert lib.csc_cheb_filter(None, 2.0, 3, None, None, 0, 1, None, 0, 1, 1, 0, None, None, 0, None) == 1
     assert lib.csc_graph_destroy(None) == 0

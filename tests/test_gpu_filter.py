@@ -49,6 +49,46 @@ def test_filter_orders_and_damping(csc, c1, m, damping):
     assert rel_fro(Y, ref) <= TOL_F32
 
 
+def test_filter_max_order(csc, c1):
+    """m = 4096, the largest order the ABI accepts, against the oracle within twice the FP32
+    storage floor (the FP64 recurrence rounded where the one-pass FP32 filter stores values),
+    or 1e-5 where that is larger."""
+    from oracle import storage
+
+    g, G, A = c1
+    m, w = 4096, 8
+    say(f"filter parity at the maximum order m={m}")
+    X = gaussian_block(g.n, w, 1 / np.sqrt(w), seed=11)
+    a = chebyshev.step_coefficients(m, 2.0, 0.43, "jackson")
+    G.set_variant(-1, torch.float32)
+    Y = csc.cheb_filter(G, a, torch.from_numpy(X).cuda()).cpu().numpy()
+    ref = chebyshev.filter_recurrence(A, 2.0, a, X.astype(np.float64))
+    emu = storage.filter_stored(A, 2.0, a, X.astype(np.float64), **storage.FORMS["fp32_onepass"])
+    floor = rel_fro(emu, ref)
+    err = rel_fro(Y, ref)
+    say(f"  error {err:.3e}, storage floor {floor:.3e}")
+    assert err <= max(TOL_F32, 2.0 * floor)
+
+
+def test_edgeless_and_single_node_graphs(csc):
+    """Graphs without edges (every node isolated: A = 0, L = I) of 1 and 37 nodes.  With
+    lmax = 2 the shifted operator is 0, so the filter is the scalar sum_j a_j T_j(0) with
+    T_j(0) = cos(j pi / 2) times X (Sec. 2.2, Step 1; the Chebyshev polynomials at 0)."""
+    for n in (1, 37):
+        G = csc.Graph(n, np.zeros(n + 1, dtype=np.int64), np.zeros(0, dtype=np.int32),
+                      np.zeros(0, dtype=np.float64), validate=True)
+        assert G.info() == (n, 0, n)
+        X = gaussian_block(n, 5, 0.5, seed=3 + n)
+        for lam_c in (0.5, 1.5):
+            a = chebyshev.step_coefficients(40, 2.0, lam_c, "jackson")
+            Y = csc.cheb_filter(G, a, torch.from_numpy(X).cuda()).cpu().numpy()
+            s = sum(a[j] * np.cos(j * np.pi / 2) for j in range(len(a)))
+            say(f"  n={n} lambda_c={lam_c}: h(1) = {s:.6f}")
+            assert np.allclose(Y, s * X, rtol=1e-6, atol=1e-7 * np.abs(X).max())
+            # the damped step at 1: near 1 above the cut-off, near 0 below it
+            assert abs(s - (1.0 if lam_c > 1.0 else 0.0)) < 0.1
+
+
 def test_filter_lmax_not_two(csc, c1):
     g, G, A = c1
     say("filter parity lmax=1.9 (diagonal term)")

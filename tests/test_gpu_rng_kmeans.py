@@ -42,7 +42,10 @@ def _mixture(n, d, k, seed, spread=6.0):
     return (centers[lab] + rng.standard_normal((n, d))).astype(np.float32)
 
 
-@pytest.mark.parametrize("n,d,k", [(5000, 32, 5), (20011, 128, 50), (3000, 256, 200), (777, 17, 1)])
+# (4099, 256, 240): the largest d and k the k-means calls take (two centroid chunks per
+# 256-row panel)
+@pytest.mark.parametrize("n,d,k", [(5000, 32, 5), (20011, 128, 50), (3000, 256, 200), (777, 17, 1),
+                                   (4099, 256, 240)])
 def test_assign_matches_oracle(csc, n, d, k):
     say(f"kmeans assign n={n} d={d} k={k}")
     F = _mixture(n, d, max(k, 2), seed=n)
