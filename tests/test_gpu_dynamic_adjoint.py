@@ -18,9 +18,11 @@ def seq():
     return [g0] + [dyn.step(0.01, 0.005) for _ in range(4)]
 
 
+# (0.97, 32): one fresh column per snapshot (q d = 1); (0.5, 256): the widest feature block
 @pytest.mark.parametrize("keep", [0, 1])
 @pytest.mark.parametrize("p,d,tau", [(0.5, 32, 1e-12), (0.5, 64, None), (0.75, 64, None), (0.0, 16, None),
-                                     (0.3, 40, None), (0.3, 40, 1e-12)])
+                                     (0.3, 40, None), (0.3, 40, 1e-12), (0.97, 32, None),
+                                     (0.5, 256, None)])
 def test_dynamic_matches_oracle(csc, seq, p, d, tau, keep):
     say(f"dynamic parity p={p} d={d} tau={tau} keep_iterates={keep}")
     k, m, seed = 4, 40, 53
