@@ -170,13 +170,20 @@ def test_filter_bf16_graph_values(csc):
 
 
 def test_heavy_rows_isolated_nodes_and_ragged_tail(csc):
-    # a star of degree 3000 (exceeds the per-block LDS stage), isolated nodes and n not a
-    # multiple of any row block
+    # a star of degree 3000 (exceeds the per-block LDS stage: its entries pass through LDS in
+    # three chunks), rows 1..40 of about 200 entries each in the same row block (summed by
+    # all row groups) beside rows of one or a few entries (summed by their own group),
+    # isolated nodes and n not a multiple of any row block
+    from oracle import storage
+
     rng = np.random.default_rng(3)
     n = 5003
     keys = set()
     for j in range(1, 3001):
         keys.add(j)  # edge (0, j): key 0 * n + j
+    for i in range(1, 41):
+        for j in rng.choice(np.arange(3001, n - 10), size=200, replace=False):
+            keys.add(i * n + int(j))
     u = rng.integers(3001, n - 10, size=20000)
     v = rng.integers(3001, n - 10, size=20000)
     for a_, b_ in zip(u, v):
@@ -192,6 +199,11 @@ def test_heavy_rows_isolated_nodes_and_ragged_tail(csc):
     mu_ref = eigcount.moments_direct(A, 2.0, 30, X.astype(np.float64))
     Xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
     ref_b = chebyshev.filter_recurrence(A, 2.0, a, Xb.float().cpu().numpy().astype(np.float64))
+    # binary16 iterates: within twice the emulated storage floor of the one-pass f16 form
+    Xb64 = Xb.float().cpu().numpy().astype(np.float64)
+    # (this graph stores FP32 operator values)
+    f16_floor = rel_fro(storage.filter_stored(A, 2.0, a, Xb64, **dict(storage.FORMS["f16_onepass"],
+                                                                      val="f32", out="f32")), ref_b)
     for variant in range(4):
         G.set_variant(variant)
         Y, mu = csc.cheb_filter(G, a, torch.from_numpy(X).cuda(), moments=True)
@@ -200,8 +212,14 @@ def test_heavy_rows_isolated_nodes_and_ragged_tail(csc):
         G.set_variant(variant, "bf16s")
         Ys = csc.cheb_filter(G, a, Xb, iter_dtype="bf16s").cpu().numpy()
         assert rel_fro(Ys, ref_b) <= 2e-2
+        G.set_variant(variant, torch.float16)
+        Yh = csc.cheb_filter(G, a, Xb, iter_dtype=torch.float16).cpu().numpy()
+        err_h = rel_fro(Yh, ref_b)
+        say(f"  variant {variant}: f16 error {err_h:.3e}, floor {f16_floor:.3e}")
+        assert err_h <= max(1e-5, 2.0 * f16_floor)
     G.set_variant(-1)
     G.set_variant(-1, "bf16s")
+    G.set_variant(-1, torch.float16)
 
 
 def test_moments_match_oracle(csc, c1):
