@@ -588,6 +588,11 @@ def run_dynamic(args):
         "errors_vs_fp64_oracle": errors,
         "cpu_baseline": None if args.no_cpu_baseline else cpu,
         "kernel_sha256_16": digest,
+        "headline_note": (
+            f"value and roofline count the {args.headline} form's own algorithmic bytes; 16-bit "
+            f"iterates move half of FP32's per step, so a faster form can show fewer GB/s: "
+            + ", ".join(f"{f} {r['ms_per_snapshot']:.1f} ms" for f, r in forms.items())
+            + " per snapshot"),
     }
     if "fp32" in forms:
         out["speedup_per_snapshot_vs_fp32"] = {
