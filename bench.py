@@ -581,6 +581,13 @@ def run_dynamic(args):
             "traffic": traffic,
             "algorithmic_bytes_per_launch": round(head["bytes_per_launch"]),
             "avg_launch_us": round(head["step_kernel_us"], 2),
+            # the measured HBM-side bytes over the live launch time: the rate to compare with
+            # the random-gather ceiling of the gather workload
+            "traffic_rate_tb_s": (round(traffic / (head["step_kernel_us"] * 1e-6) / 1e12, 3)
+                                  if traffic else None),
+            "note": ("live launches run beside the previous snapshot's recombination and k-means "
+                     "on a second stream; the gathers fetch each neighbour row from beyond L2, so "
+                     "traffic exceeds the algorithmic bytes"),
         },
         "forms": {f: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
                       if k not in ("G", "theta_sample")}

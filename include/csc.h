@@ -347,10 +347,15 @@ typedef struct {
   int keep_iterates;  /* -1: keep all m + 1 iterates of the fresh block when they fit in free
                          device memory and m < 256 (a refinement then recombines them, in FP64,
                          instead of running the recurrence again); 0: never; 1: always
-                         (CSC_E_NOMEM when they do not fit, CSC_E_ARG when m >= 256) */
+                         (CSC_E_NOMEM when they do not fit, CSC_E_ARG when m >= 256).  Where
+                         two sets of kept iterates fit, csc_dynamic_steps runs the next
+                         snapshot's (or batch's) recurrence beside the current one's
+                         recombination, refinement and k-means */
   int batch;          /* csc_dynamic_steps: fresh blocks of up to `batch` (<= 8) snapshots are
-                         filtered together, one launch per recurrence step; needs the
-                         iterates kept (0 or 1 -> one snapshot at a time) */
+                         filtered together, one launch per recurrence step: from kept
+                         iterates, or, where they are not kept, as one-pass batches whose
+                         snapshots are filtered again when their cut-off moves (0 or 1 -> one
+                         snapshot at a time) */
   int use_graph;      /* non-zero: the recurrence launches are captured once in a HIP graph
                          and replayed for every snapshot (or batch) */
   int variant;        /* recurrence kernel shape (row group x column tile) for the fresh

@@ -167,7 +167,7 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
   st->kwork_bytes = kmeans_workspace(n, d, k);
   st->dwork_bytes = dot_workspace(n);
   bool ok = hipMalloc(&st->theta, es * n * d) == hipSuccess &&
-            hipMalloc(&st->sig, es * n * std::max(d, (st->batch > 1 ? 2 : 1) * st->batch * qd)) == hipSuccess &&
+            hipMalloc(&st->sig, es * n * std::max(d, 2 * st->batch * qd)) == hipSuccess &&
             hipMalloc(&st->C, sizeof(float) * k * d) == hipSuccess &&
             hipMalloc(&st->prev, sizeof(int32_t) * n) == hipSuccess &&
             hipMalloc(&st->scal, sizeof(double) * (m + 2)) == hipSuccess &&
@@ -203,8 +203,9 @@ csc_status dyn_create(int64_t n, int d, int k, double p, int m, csc_damping damp
     (void)hipMemGetInfo(&free_b, &total_b);
     const size_t margin = size_t(4) << 30;
     const size_t want = st->basis_bytes * st->batch;
-    // a second batch of slots when batching and it fits: recurrence and k-means overlap
-    if (st->batch > 1 && 2 * want + st->aux_bytes + margin <= free_b &&
+    // a second set of slots when it fits, batched or not: the next recurrence then runs
+    // beside this one's recombination, refinement and k-means
+    if (2 * want + st->aux_bytes + margin <= free_b &&
         hipMalloc(&st->basis, 2 * want) == hipSuccess) {
       st->nbuf = 2;
       if (hipMalloc(&st->aux, st->aux_bytes) != hipSuccess) {
