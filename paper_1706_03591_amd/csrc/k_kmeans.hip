@@ -981,10 +981,12 @@ __global__ void k_pp_cdist(const float* C, int d, int cj, double* cd) {
 // and writes their sum to bsum[b].  A row is skipped without reading it when
 // ||C_cj - C_owner||^2 >= 4 d2 (1 + 1e-9): by the triangle inequality the new centre is then
 // no closer, so the result equals the unpruned pass (the margin covers the FP64 rounding of
-// both sides).  Sixteen lanes share a row so that each load instruction reads whole rows; the
-// lanes' partial sums meet in a fixed shuffle tree.  The block first reads the current
-// distances and owners of all its rows (coalesced) and decides which rows to read, so the
-// feature loads that follow wait on no other global load.
+// both sides).  The block first reads the current distances and owners of all its rows
+// (coalesced), decides which rows to read and lists them in row order, so the feature loads
+// that follow wait on no other global load and a pruned row costs no instruction beyond its
+// test.  Sixteen lanes share a listed row so that each load instruction reads whole rows; the
+// lanes' partial sums meet in a fixed shuffle tree.  The block's sum of the new distances is
+// taken over all its rows in a fixed order.
 template <typename TF, bool VEC, int NPC>
 __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, int64_t n, int d,
                                                       int dp, const float* C, int cj, int first,
@@ -1040,20 +1042,45 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
       const int c = (pc * 16 + l16) * V + i;
       cjd[pc][i] = c < d ? static_cast<double>(s_cj[c]) : 0.0;
     }
-  double local = 0.0;
-  for (int q0 = 0; q0 < RB / 16; q0 += U) {
+  // the rows to read, in row order: a wave ballot per stretch of kThreads rows
+  __shared__ int16_t s_list[RB];
+  __shared__ int s_wcnt[kThreads / 64];
+  __shared__ int s_total;
+  if (threadIdx.x == 0) s_total = 0;
+  __syncthreads();
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < kRIT; ++i) {
+      const int r = threadIdx.x + i * kThreads;
+      const bool nd = s_need[r] != 0;
+      const uint64_t bal = __ballot(nd);
+      const int before = __popcll(bal & ((uint64_t(1) << lane) - 1));
+      if (lane == 0) s_wcnt[wave] = __popcll(bal);
+      __syncthreads();
+      int off = s_total;
+      for (int w = 0; w < wave; ++w) off += s_wcnt[w];
+      if (nd) s_list[off + before] = static_cast<int16_t>(r);
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / 64; ++w) s_total += s_wcnt[w];
+      __syncthreads();
+    }
+  }
+  const int cnt = s_total;
+  for (int q0 = 0; q0 < cnt; q0 += 16 * U) {
     uint4 raw[U][NPC];
     bool need[U];
-    double dold[U];
+    int rr[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int r = (q0 + u) * 16 + grp;
-      const int64_t row = base + r;
-      need[u] = s_need[r] != 0;
-      dold[u] = s_old[r];
+      const int li = q0 + u * 16 + grp;
+      need[u] = li < cnt;
+      rr[u] = need[u] ? s_list[li] : 0;
+      const int64_t row = base + rr[u];
       if constexpr (VEC) {
-        // branch-free, so that all U x NPC loads are in flight together: skipped rows read
-        // row 0 and pieces past d read column 0 (in bounds, cached, and never summed)
+        // branch-free, so that all U x NPC loads are in flight together: list slots past the
+        // end read row 0 and pieces past d read column 0 (in bounds, cached, and never used)
         const TF* rowp = F + (need[u] ? row : 0) * ldf;
 #pragma unroll
         for (int pc = 0; pc < NPC; ++pc) {
@@ -1061,7 +1088,7 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
           raw[u][pc] = *reinterpret_cast<const uint4*>(rowp + (c0 < d ? c0 : 0));
         }
       } else {
-        const TF* rowp = F + (row < n ? row : 0) * ldf;
+        const TF* rowp = F + (need[u] ? row : 0) * ldf;
 #pragma unroll
         for (int pc = 0; pc < NPC; ++pc) {
           const int c0 = (pc * 16 + l16) * V;
@@ -1076,9 +1103,7 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t row = base + (q0 + u) * 16 + grp;
-      // every row is summed (no divergent branch around the loads' uses); a skipped row's
-      // sum is then discarded
+      const int64_t row = base + rr[u];
       double s = 0.0;
 #pragma unroll
       for (int pc = 0; pc < NPC; ++pc) {
@@ -1102,24 +1127,26 @@ __global__ __launch_bounds__(kThreads) void k_pp_dist(const TF* F, int64_t ldf, 
           s += t * t;
         }
       }
-      if (!need[u]) s = 0.0;
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 16);
-      if (row < n && l16 == 0) {
-        double v = dold[u];
+      if (need[u] && l16 == 0) {
         if (first) {
-          v = s;
-          d2[row] = v;
+          s_old[rr[u]] = s;
+          d2[row] = s;
           owner[row] = 0;
-        } else if (need[u] && s < v) {
-          v = s;
-          d2[row] = v;
+        } else if (s < s_old[rr[u]]) {
+          s_old[rr[u]] = s;
+          d2[row] = s;
           owner[row] = cj;
         }
-        local += v;
       }
     }
   }
+  __syncthreads();
+  // the block's sum of the (new) distances, each thread's rows in order, then a fixed tree
+  double local = 0.0;
+#pragma unroll
+  for (int i = 0; i < kRIT; ++i) local += s_old[threadIdx.x + i * kThreads];
   const double tot = block_sum(local);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
