@@ -251,8 +251,13 @@ csc_status csc_uniforms(double* u, int count, uint64_t seed, uint64_t stream_id,
  *
  * csc_kmeans_update: C[c] = mean of the rows labelled c; an empty cluster keeps its
  * previous centroid (C is read and overwritten); rows whose label is outside [0, k) are
- * ignored; counts: device int32[k] or NULL.  Sums in 64-bit fixed point (order-independent,
- * bit-reproducible).  work: csc_kmeans_workspace_bytes(n, d, k).  Asynchronous.
+ * ignored; counts: device int32[k] or NULL.  Sums in 64-bit fixed point: each value is
+ * rounded (half to even) to an integer multiple of 2^-S, S = 62 - e - ceil(log2 n) (kept
+ * within [-60, 120]) for max |F| < 2^e, and the integers are added exactly, so the result
+ * does not depend on the order of the rows (bit-reproducible).  The rows are ordered by
+ * label (counting sort) and summed in chunks of one label.  n < 2^31 (CSC_E_ARG
+ * otherwise).  work: csc_kmeans_workspace_bytes(n, d, k) (it also holds the row order and
+ * the chunk sums).  Asynchronous.
  *
  * csc_kmeans_seed: k-means++ (Arthur and Vassilvitskii, 2007) driven by the device
  * uniforms u[0..k-1]: the first centre is row floor(u[0] n); centre j is the first row

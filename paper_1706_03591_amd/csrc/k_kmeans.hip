@@ -8,9 +8,10 @@
 // ranking and FP64 re-score of the best two.
 //
 // Update: sums of the rows of each cluster in 64-bit fixed point (scale 2^S chosen from
-// max |F| and n so that no sum can overflow), accumulated with integer atomics in LDS and
-// then in global memory.  Integer addition is associative, so the sums do not depend on
-// the order of the atomics and the update is bit-reproducible; the quantisation step
+// max |F| and n so that no sum can overflow).  The rows are ordered by label (counting
+// sort), summed in chunks of one label each, and the chunk sums added per label.  Integer
+// addition is associative, so the sums depend neither on the order of the rows within a
+// label nor on the chunking, and the update is bit-reproducible; the quantisation step
 // 2^-S is far below FP32 resolution.
 //
 // k-means++: FP64 squared distances to the newest centre (sixteen lanes per row, rows the
@@ -18,6 +19,7 @@
 // one-block pick of the first row whose running sum exceeds u_j * total.
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "csc_internal.h"
 
@@ -704,10 +706,8 @@ __device__ inline int fixed_scale(float maxabs, int64_t n) {
   return S < -60 ? -60 : (S > 120 ? 120 : S);
 }
 
-__global__ void k_upd_clear(unsigned long long* sums, int64_t kd, int32_t* cnt, int k,
-                            uint32_t* maxabs) {
+__global__ void k_upd_clear(int32_t* cnt, int k, uint32_t* maxabs) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < kd) sums[t] = 0ull;
   if (t < k) cnt[t] = 0;
   if (t == 0 && maxabs) maxabs[0] = 0u;
 }
@@ -746,205 +746,239 @@ __global__ void k_maxabs(const TF* F, int64_t ldf, int64_t n, int d, int flat, u
   if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
-// Block (b, y): rows [b * rpb, ...), columns [y * cw, y * cw + cw).  The
-// block first orders its rows by label in LDS (counting sort), then each group of cw lanes
-// walks a contiguous stretch of that order, summing runs of equal labels in registers and
-// adding each run to the LDS sums with one integer atomic per column.  The sums are 64-bit
-// fixed point, so neither the order inside a label nor the order of the atomics changes them.
-constexpr int kUpdRows = 1024;
+// The update orders the rows by label with a counting sort (label counts, their prefix sums,
+// a scatter of row indices), then sums each label's rows in chunks of kUpdChunk: one block
+// per chunk, whose rows all carry the chunk's label, so a block keeps one running sum per
+// column in registers and writes one 64-bit partial sum per column.  A last pass adds each
+// label's chunk partials in chunk order.  All sums are 64-bit fixed point, so neither the
+// order of the rows within a label nor the grouping changes them.
+constexpr int kUpdChunk = 512;       // rows per chunk (the last chunk of a label may be short)
+constexpr int kUpdScatterRows = 8192;  // rows per scatter block (one global atomic per label each)
 
-template <typename TF, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_upd_acc(const TF* F, int64_t ldf, int64_t n, int d,
-                                                      const int32_t* labels, int k, int64_t rpb,
-                                                      int nsub, int cw, int64_t nblk, int ny,
+// Label counts (out-of-range labels are ignored): an LDS histogram per block, then one global
+// atomic per label.
+__global__ __launch_bounds__(kThreads) void k_lab_hist(const int32_t* labels, int64_t n, int k,
+                                                       int32_t* cnt) {
+  __shared__ int32_t h[256];
+  for (int t = threadIdx.x; t < k; t += kThreads) h[t] = 0;
+  __syncthreads();
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+    const int32_t lb = labels[i];
+    if (lb >= 0 && lb < k) atomicAdd(&h[lb], 1);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < k; t += kThreads)
+    if (h[t]) atomicAdd(&cnt[t], h[t]);
+}
+
+// One block: off[c] = rows with a smaller label, cur[c] = off[c] (the scatter's cursor), and
+// first[c] = chunks of the smaller labels; first[k] = all chunks, off[k] = all valid rows.
+__global__ __launch_bounds__(kThreads) void k_lab_scan(const int32_t* cnt, int k, int32_t* off,
+                                                       int32_t* cur, int32_t* first) {
+  __shared__ int32_t s_w[2][kThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int c = t < k ? cnt[t] : 0;
+  const int ch = (c + kUpdChunk - 1) / kUpdChunk;
+  int x = c, y = ch;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int xa = __shfl_up(x, o, 64), ya = __shfl_up(y, o, 64);
+    if (lane >= o) { x += xa; y += ya; }
+  }
+  if (lane == 63) { s_w[0][wave] = x; s_w[1][wave] = y; }
+  __syncthreads();
+  int ax = 0, ay = 0;
+  for (int w = 0; w < wave; ++w) { ax += s_w[0][w]; ay += s_w[1][w]; }
+  if (t < k) {
+    off[t] = ax + x - c;
+    cur[t] = ax + x - c;
+    first[t] = ay + y - ch;
+  }
+  if (t == k - 1) {
+    off[k] = ax + x;
+    first[k] = ay + y;
+  }
+}
+
+// Scatter: block b takes rows [b * kUpdScatterRows, ...), reserves a range of each label's
+// slots with one global atomic per label, and writes each row's index into it.
+__global__ __launch_bounds__(kThreads) void k_lab_scatter(const int32_t* labels, int64_t n, int k,
+                                                          int32_t* cur, int32_t* perm) {
+  constexpr int PER = kUpdScatterRows / kThreads;
+  __shared__ int32_t h[256];
+  __shared__ int32_t base[256];
+  for (int t = threadIdx.x; t < k; t += kThreads) h[t] = 0;
+  __syncthreads();
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kUpdScatterRows;
+  int32_t lb[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int64_t r = r0 + i * kThreads + threadIdx.x;
+    lb[i] = r < n ? labels[r] : -1;
+    if (lb[i] < 0 || lb[i] >= k) lb[i] = -1;
+    if (lb[i] >= 0) atomicAdd(&h[lb[i]], 1);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < k; t += kThreads) {
+    base[t] = h[t] ? atomicAdd(&cur[t], h[t]) : 0;
+    h[t] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+    if (lb[i] >= 0)
+      perm[base[lb[i]] + atomicAdd(&h[lb[i]], 1)] = static_cast<int32_t>(r0 + i * kThreads + threadIdx.x);
+}
+
+// Chunk sums: block b (< first[k]) takes chunk b, whose rows all have the label c with
+// first[c] <= b < first[c + 1].  A row is covered by LR lanes of 8 columns each (LR a power
+// of two, 8 LR >= d); the kThreads / LR row groups of the block take the chunk's rows in turn
+// and their sums meet in LDS in group order.  Writes part[b * d + col] for col < d.
+template <typename TF, bool VEC, int LR>
+__global__ __launch_bounds__(kThreads) void k_lab_sum(const TF* F, int64_t ldf, int64_t n, int d,
+                                                      int k, const int32_t* off,
+                                                      const int32_t* first, const int32_t* perm,
                                                       const uint32_t* maxabs,
-                                                      unsigned long long* gsums, int32_t* gcnt) {
-  // LDS: k * cw sums, then k counts, k offsets, k block totals, rpb labels, rpb row order.
-  // The block takes nsub consecutive stretches of rpb rows; each is sorted by label on its
-  // own, and the sums of all of them meet in the same LDS accumulators before the single
-  // flush to global memory.
-  // Blocks are numbered so that the ny column groups of one row block follow each other on
-  // the same XCD (workgroups go to the eight XCDs in turn): they then share that XCD's L2
-  // copy of the rows' cache lines.  Ids past the last row block exit at once.
-  const int64_t L = blockIdx.x;
-  const int64_t bx = (L / (8 * ny)) * 8 + (L & 7);
-  const int by = static_cast<int>((L >> 3) % ny);
-  if (bx >= nblk) return;
-  extern __shared__ unsigned long long s_acc[];
-  int32_t* s_cnt = reinterpret_cast<int32_t*>(s_acc + static_cast<size_t>(k) * cw);
-  int32_t* s_off = s_cnt + k;
-  int32_t* s_tot = s_off + k;
-  int32_t* s_lab = s_tot + k;
-  int32_t* s_perm = s_lab + rpb;
-  for (int t = threadIdx.x; t < k * cw; t += kThreads) s_acc[t] = 0ull;
-  for (int t = threadIdx.x; t < k; t += kThreads) s_tot[t] = 0;
-  const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
-  __shared__ int s_nv;
-  __shared__ int s_wsum[kThreads / 64];
-  // a lane owns 8 consecutive columns; LR lanes cover the block's cw columns of one row, and
-  // the kThreads / LR row slots split the label-ordered rows into contiguous stretches
-  const int LR = cw / 8;
-  const int slots = kThreads / LR;
-  const int slot = threadIdx.x / LR;
+                                                      unsigned long long* part) {
+  constexpr int G = kThreads / LR;  // row groups
+  __shared__ int32_t s_rows[kUpdChunk];
+  __shared__ long long s_red[kThreads * 8];
+  const int32_t b = static_cast<int32_t>(blockIdx.x);
+  if (b >= first[k]) return;  // (uniform across the block)
+  int lo = 0, hi = k - 1;     // the label whose chunks include b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int32_t p0 = off[lo] + (b - first[lo]) * kUpdChunk;
+  const int nr = min(kUpdChunk, off[lo + 1] - p0);
+  for (int i = threadIdx.x; i < nr; i += kThreads) s_rows[i] = perm[p0 + i];
+  __syncthreads();
+
+  const float mxf = __uint_as_float(maxabs[0]);
+  const int S = fixed_scale(mxf, n);
+  int em = 0;
+  frexpf(mxf, &em);
+  const int hb = em + S;  // every converted value is an integer of magnitude <= 2^hb
+  const int g = threadIdx.x / LR;
   const int c8 = (threadIdx.x % LR) * 8;
-  const int col0 = by * cw + c8;
   // VEC (aligned rows, d a multiple of 8): unmasked 16-byte loads; a lane past d reads
-  // column 0 and its sums are never flushed
-  const int lcol = VEC && col0 >= d ? 0 : col0;
-  for (int sub = 0; sub < nsub; ++sub) {
-    const int64_t r0 = (bx * nsub + sub) * rpb;
-    const int nr = static_cast<int>(max<int64_t>(0, min(r0 + rpb, n) - r0));
-    if (nr == 0) break;  // uniform across the block
-    for (int t = threadIdx.x; t < k; t += kThreads) s_cnt[t] = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += kThreads) {
-      int lb = labels[r0 + i];
-      if (lb < 0 || lb >= k) lb = -1;  // out-of-range labels are ignored
-      s_lab[i] = lb;
-      if (lb >= 0) atomicAdd(&s_cnt[lb], 1);
+  // column 0 and its sums are never written
+  const int lcol = VEC && c8 >= d ? 0 : c8;
+  constexpr int RW = sizeof(TF) / 2;  // 16-byte pieces per eight values
+  auto load_raw = [&](int32_t row, uint4* raw) {
+    const TF* rp = F + static_cast<int64_t>(row) * ldf + lcol;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int w = 0; w < RW; ++w) raw[w] = reinterpret_cast<const uint4*>(rp)[w];
+    } else {
+      TF tmp[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tmp[i] = c8 + i < d ? rp[i] : TF(0);
+      __builtin_memcpy(raw, tmp, sizeof(tmp));
     }
-    __syncthreads();
-    {
-      // exclusive prefix of the k <= kThreads label counts: a scan in each wave, then the
-      // totals of the waves before
-      const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-      const int c = t < k ? s_cnt[t] : 0;
-      int x = c;
+  };
+  auto unpack = [&](const uint4* raw, float* v) {
+    if constexpr (sizeof(TF) == 4) {
+      v[0] = __uint_as_float(raw[0].x); v[1] = __uint_as_float(raw[0].y);
+      v[2] = __uint_as_float(raw[0].z); v[3] = __uint_as_float(raw[0].w);
+      v[4] = __uint_as_float(raw[1].x); v[5] = __uint_as_float(raw[1].y);
+      v[6] = __uint_as_float(raw[1].z); v[7] = __uint_as_float(raw[1].w);
+    } else {
+      const uint32_t w[4] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w};
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
+      for (int i = 0; i < 4; ++i) {
+        v[2 * i] = __uint_as_float(w[i] << 16);
+        v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
       }
-      if (lane == 63) s_wsum[wave] = x;
-      __syncthreads();
-      int add = 0;
-      for (int w = 0; w < wave; ++w) add += s_wsum[w];
-      if (t < k) {
-        s_off[t] = add + x - c;
-        s_tot[t] += c;
-      }
-      if (t == kThreads - 1) s_nv = add + x;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += kThreads)
-      if (s_lab[i] >= 0) s_perm[atomicAdd(&s_off[s_lab[i]], 1)] = i;
-    __syncthreads();
-    const int nv = s_nv;
-    const int per = (nv + slots - 1) / slots;
-    const int q0 = slot * per, q1 = min(nv, q0 + per);
-    int cur = -1;
-    long long run[8];
+  };
+  long long sum[8];
+  // A group sums at most ceil(nr / G) values per column.  When that many values of
+  // magnitude <= 2^hb stay within 2^53, every partial sum is an integer that FP64 holds
+  // exactly: each value is then rounded to an integer in FP32 (v * 2^S is exact there, and
+  // rintf rounds half to even like llrint) and summed in FP64, converted to 64 bits once at
+  // the end.  Otherwise each value is converted to 64 bits on its own.  Both give the same
+  // integers.
+  auto walk = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    using Acc = std::conditional_t<FAST, double, long long>;
+    Acc acc[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) run[i] = 0;
-    auto flush = [&]() {
-      if (cur < 0) return;
+    for (int i = 0; i < 8; ++i) acc[i] = 0;
+    auto add = [&](const float* v) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (run[i] != 0 && c8 + i < cw)
-          atomicAdd(&s_acc[cur * cw + c8 + i], static_cast<unsigned long long>(run[i]));
-    };
-    constexpr int RW = sizeof(TF) / 2;  // 16-byte pieces per eight values
-    auto load_raw = [&](int ii, uint4* raw) {
-      const TF* rp = F + (r0 + ii) * ldf + lcol;
-      if constexpr (VEC) {
-#pragma unroll
-        for (int w = 0; w < RW; ++w) raw[w] = reinterpret_cast<const uint4*>(rp)[w];
-      } else {
-        TF tmp[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) tmp[i] = col0 + i < d ? rp[i] : TF(0);
-        __builtin_memcpy(raw, tmp, sizeof(tmp));
+      for (int i = 0; i < 8; ++i) {
+        if constexpr (FAST) acc[i] += static_cast<double>(rintf(ldexpf(v[i], S)));
+        else acc[i] += llrint(ldexp(static_cast<double>(v[i]), S));
       }
-    };
-    auto unpack = [&](const uint4* raw, float* v) {
-      if constexpr (sizeof(TF) == 4) {
-        v[0] = __uint_as_float(raw[0].x); v[1] = __uint_as_float(raw[0].y);
-        v[2] = __uint_as_float(raw[0].z); v[3] = __uint_as_float(raw[0].w);
-        v[4] = __uint_as_float(raw[1].x); v[5] = __uint_as_float(raw[1].y);
-        v[6] = __uint_as_float(raw[1].z); v[7] = __uint_as_float(raw[1].w);
-      } else {
-        const uint32_t w[4] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          v[2 * i] = __uint_as_float(w[i] << 16);
-          v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-        }
-      }
-    };
-    auto load8v = [&](int ii, float* v) {
-      uint4 raw[RW];
-      load_raw(ii, raw);
-      unpack(raw, v);
     };
     // UR rows in flight per lane (eight 16-byte loads)
     constexpr int UR = 8 / RW;
-    int q = q0;
-    for (; q + UR <= q1; q += UR) {
-      int lb[UR];
+    int q = g;
+    for (; q + (UR - 1) * G < nr; q += UR * G) {
       uint4 raw[UR][RW];
 #pragma unroll
-      for (int u = 0; u < UR; ++u) {
-        const int ii = s_perm[q + u];
-        lb[u] = s_lab[ii];
-        load_raw(ii, raw[u]);
-      }
+      for (int u = 0; u < UR; ++u) load_raw(s_rows[q + u * G], raw[u]);
       // all the rows' loads ahead of the first use
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
         float v[8];
         unpack(raw[u], v);
-        if (lb[u] != cur) {
-          flush();
-          cur = lb[u];
-#pragma unroll
-          for (int i = 0; i < 8; ++i) run[i] = 0;
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[i]), S));
+        add(v);
       }
     }
-    for (; q < q1; ++q) {
-      const int ii = s_perm[q];
-      const int lb = s_lab[ii];
+    for (; q < nr; q += G) {
+      uint4 raw[RW];
+      load_raw(s_rows[q], raw);
       float v[8];
-      load8v(ii, v);
-      if (lb != cur) {
-        flush();
-        cur = lb;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) run[i] = 0;
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) run[i] += llrint(ldexp(static_cast<double>(v[i]), S));
+      unpack(raw, v);
+      add(v);
     }
-    flush();
-    __syncthreads();  // s_lab and s_perm are rewritten by the next stretch
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sum[i] = static_cast<long long>(acc[i]);
+  };
+  const int per = (nr + G - 1) / G;
+  if (hb <= 53 && (53 - hb >= 30 || per <= (1 << (53 - hb)))) walk(std::true_type{});
+  else walk(std::false_type{});
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s_red[(g * LR + threadIdx.x % LR) * 8 + i] = sum[i];
+  __syncthreads();
+  // thread t < 8 LR adds column t over the groups, in group order
+  if (threadIdx.x < LR * 8 && static_cast<int>(threadIdx.x) < d) {
+    const int lane = threadIdx.x / 8, i = threadIdx.x % 8;
+    long long t = 0;
+    for (int gg = 0; gg < G; ++gg) t += s_red[(gg * LR + lane) * 8 + i];
+    part[static_cast<int64_t>(b) * d + threadIdx.x] = static_cast<unsigned long long>(t);
   }
-  for (int t = threadIdx.x; t < k * cw; t += kThreads) {
-    const int c = t / cw, cc = t % cw;
-    const int gc = by * cw + cc;
-    if (gc < d && s_acc[t] != 0ull) atomicAdd(&gsums[static_cast<int64_t>(c) * d + gc], s_acc[t]);
-  }
-  if (by == 0)
-    for (int t = threadIdx.x; t < k; t += kThreads)
-      if (s_tot[t]) atomicAdd(&gcnt[t], s_tot[t]);
 }
 
-// C[c] = sums / count (C may be null), sums_out = the sums rounded once to FP32 (or null),
-// counts = the cluster sizes (or null).
-__global__ void k_upd_final(const unsigned long long* gsums, const int32_t* gcnt,
-                            const uint32_t* maxabs, int64_t n, int k, int d, float* C,
-                            int32_t* counts, float* sums_out) {
+// Per (c, col): the sum of label c's chunk partials (integers: any order gives the same
+// value), then C[c] = sum / count (C may be null), sums_out = the sum rounded once to FP32
+// (or null), counts = the cluster sizes (or null).
+__global__ void k_upd_final(const unsigned long long* part, const int32_t* first,
+                            const int32_t* gcnt, const uint32_t* maxabs, int64_t n, int k, int d,
+                            float* C, int32_t* counts, float* sums_out) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<int64_t>(k) * d) return;
-  const int c = static_cast<int>(t / d);
+  const int c = static_cast<int>(t / d), col = static_cast<int>(t % d);
+  const int32_t j0 = first[c], j1 = first[c + 1];
+  unsigned long long a[4] = {0ull, 0ull, 0ull, 0ull};
+  int32_t j = j0;
+  for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] += part[static_cast<int64_t>(j + q) * d + col];
+  }
+  for (; j < j1; ++j) a[0] += part[static_cast<int64_t>(j) * d + col];
+  const unsigned long long tot = a[0] + a[1] + a[2] + a[3];
   const int S = fixed_scale(__uint_as_float(maxabs[0]), n);
   const int32_t cnt = gcnt[c];
-  const double sum = ldexp(static_cast<double>(static_cast<long long>(gsums[t])), -S);
+  const double sum = ldexp(static_cast<double>(static_cast<long long>(tot)), -S);
   if (C && cnt > 0) C[t] = static_cast<float>(sum / static_cast<double>(cnt));
   if (sums_out) sums_out[t] = static_cast<float>(sum);
-  if (counts && (t % d) == 0) counts[c] = cnt;
+  if (counts && col == 0) counts[c] = cnt;
 }
 
 // ---------------- k-means++ ----------------
@@ -1265,9 +1299,12 @@ int64_t assign_blocks(int64_t n) {
 }
 
 struct KmLayout {
-  size_t off_u, off_d2, off_bsum, off_sums, off_cnt, off_max, off_obj, off_objv, off_sel, off_cp,
-      off_own, off_cd, total;
+  size_t off_u, off_d2, off_bsum, off_cnt, off_max, off_obj, off_objv, off_sel, off_cp,
+      off_own, off_cd, off_perm, off_part, off_tab, total;
 };
+
+// chunks of the update's label-ordered rows: at most one short chunk per label
+int64_t upd_chunks(int64_t n, int k) { return (n + kUpdChunk - 1) / kUpdChunk + k; }
 
 int padded_k(int k) { return (k + kKG - 1) / kKG * kKG; }
 
@@ -1278,7 +1315,6 @@ KmLayout km_layout(int64_t n, int d, int k) {
   L.off_u = off; off += align_up(static_cast<size_t>(k) * 8);
   L.off_d2 = off; off += align_up(static_cast<size_t>(n) * 8);
   L.off_bsum = off; off += align_up(static_cast<size_t>(blocks) * 8);
-  L.off_sums = off; off += align_up(static_cast<size_t>(k) * d * 8);
   L.off_cnt = off; off += align_up(static_cast<size_t>(k) * 4);
   L.off_max = off; off += 256;
   L.off_obj = off; off += align_up(static_cast<size_t>(std::max<int64_t>(blocks, 2048)) * 8);
@@ -1287,6 +1323,9 @@ KmLayout km_layout(int64_t n, int d, int k) {
   L.off_cp = off; off += align_up(assign_scratch_bytes(k, d));
   L.off_own = off; off += align_up(static_cast<size_t>(n) * 4);
   L.off_cd = off; off += align_up(static_cast<size_t>(k) * 8);
+  L.off_perm = off; off += align_up(static_cast<size_t>(n) * 4);
+  L.off_part = off; off += align_up(static_cast<size_t>(upd_chunks(n, k)) * d * 8);
+  L.off_tab = off; off += align_up(static_cast<size_t>(k + 1) * 12);
   L.total = off;
   return L;
 }
@@ -1307,42 +1346,49 @@ csc_status check_f(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
 csc_status update_impl(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
                        const int32_t* labels, int k, float* C, int32_t* counts, void* work,
                        bool max_ready, hipStream_t s, float* sums_out = nullptr) {
+  if (n > INT32_MAX) return fail(CSC_E_ARG, "the update takes fewer than 2^31 rows");
   const KmLayout L = km_layout(n, d, k);
   char* base = static_cast<char*>(work);
-  auto* sums = reinterpret_cast<unsigned long long*>(base + L.off_sums);
   auto* cnt = reinterpret_cast<int32_t*>(base + L.off_cnt);
   auto* mx = reinterpret_cast<uint32_t*>(base + L.off_max);
+  auto* perm = reinterpret_cast<int32_t*>(base + L.off_perm);
+  auto* part = reinterpret_cast<unsigned long long*>(base + L.off_part);
+  auto* off = reinterpret_cast<int32_t*>(base + L.off_tab);
+  int32_t* cur = off + (k + 1);
+  int32_t* first = cur + (k + 1);
   const int64_t kd = static_cast<int64_t>(k) * d;
-  hipLaunchKernelGGL(k_upd_clear, dim3(static_cast<unsigned>((std::max<int64_t>(kd, k) + 255) / 256)),
-                     dim3(256), 0, s, sums, kd, cnt, k, max_ready ? nullptr : mx);
+  // the counts start at zero
+  hipLaunchKernelGGL(k_upd_clear, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, s,
+                     cnt, k, max_ready ? nullptr : mx);
   if (!max_ready) CSC_TRY(launch_maxabs(F, f_dt, ldf, n, d, mx, s));
-  const int cw = k <= 112 ? 64 : 32;
-  // rows per stretch: up to kUpdRows, within 64 KiB of LDS next to the k x cw sums; each block
-  // takes up to 16 stretches (about 512 blocks across x), so the k x cw flush to global
-  // memory is amortised over more rows
-  const size_t fixed_lds = static_cast<size_t>(k) * cw * 8 + static_cast<size_t>(k) * 12;
-  const int64_t cap = std::min<int64_t>(kUpdRows, static_cast<int64_t>((64 * 1024 - fixed_lds) / 8));
-  const int64_t nstretch = std::max<int64_t>(1, (n + cap - 1) / cap);
-  const int64_t rpb = (n + nstretch - 1) / nstretch;  // <= cap
-  const int nsub = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(16, nstretch / 512)));
-  const int64_t nblk = (nstretch + nsub - 1) / nsub;
-  const size_t lds = fixed_lds + static_cast<size_t>(rpb) * 8;
-  const int ny = (d + cw - 1) / cw;
-  // row blocks in groups of eight, each group's ny column groups in turn per XCD
-  const int64_t grid = (nblk + 7) / 8 * 8 * ny;
+  // few blocks: each adds its k counts with global atomics, which serialise per label
+  hipLaunchKernelGGL(k_lab_hist, dim3(static_cast<unsigned>(std::min<int64_t>(256, (n + kThreads - 1) / kThreads))),
+                     dim3(kThreads), 0, s, labels, n, k, cnt);
+  hipLaunchKernelGGL(k_lab_scan, dim3(1), dim3(kThreads), 0, s, cnt, k, off, cur, first);
+  hipLaunchKernelGGL(k_lab_scatter, dim3(static_cast<unsigned>((n + kUpdScatterRows - 1) / kUpdScatterRows)),
+                     dim3(kThreads), 0, s, labels, n, k, cur, perm);
+  const unsigned chunks = static_cast<unsigned>(upd_chunks(n, k));
   const bool vec = rows_aligned(F, f_dt, ldf) && d % 8 == 0;
-#define CSC_UPD(TF, V)                                                                         \
-  hipLaunchKernelGGL((k_upd_acc<TF, V>), dim3(static_cast<unsigned>(grid)), dim3(kThreads), lds, s, \
-                     static_cast<const TF*>(F), ldf, n, d, labels, k, rpb, nsub, cw, nblk, ny, mx,  \
-                     sums, cnt)
-  if (f_dt == CSC_F32) {
-    if (vec) CSC_UPD(float, true); else CSC_UPD(float, false);
-  } else {
-    if (vec) CSC_UPD(uint16_t, true); else CSC_UPD(uint16_t, false);
+  const int lr = d <= 32 ? 4 : d <= 64 ? 8 : d <= 128 ? 16 : 32;
+#define CSC_SUM(TF, V, LR)                                                                      \
+  hipLaunchKernelGGL((k_lab_sum<TF, V, LR>), dim3(chunks), dim3(kThreads), 0, s,                 \
+                     static_cast<const TF*>(F), ldf, n, d, k, off, first, perm, mx, part)
+#define CSC_SUM_LR(TF, V)                                                                       \
+  switch (lr) {                                                                                 \
+    case 4: CSC_SUM(TF, V, 4); break;                                                           \
+    case 8: CSC_SUM(TF, V, 8); break;                                                           \
+    case 16: CSC_SUM(TF, V, 16); break;                                                         \
+    default: CSC_SUM(TF, V, 32); break;                                                         \
   }
-#undef CSC_UPD
+  if (f_dt == CSC_F32) {
+    if (vec) { CSC_SUM_LR(float, true) } else { CSC_SUM_LR(float, false) }
+  } else {
+    if (vec) { CSC_SUM_LR(uint16_t, true) } else { CSC_SUM_LR(uint16_t, false) }
+  }
+#undef CSC_SUM_LR
+#undef CSC_SUM
   hipLaunchKernelGGL(k_upd_final, dim3(static_cast<unsigned>((kd + 255) / 256)), dim3(256), 0, s,
-                     sums, cnt, mx, n, k, d, C, counts, sums_out);
+                     part, first, cnt, mx, n, k, d, C, counts, sums_out);
   CSC_HIP(hipGetLastError());
   return CSC_OK;
 }
@@ -1607,8 +1653,7 @@ csc_status run_kmeans(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int
     CSC_TRY(launch_kmeans_seed(F, f_dt, ldf, n, d, k, u, C, nullptr, work, work_bytes, s));
   }
   // max |F| once: the features do not change during the Lloyd rounds
-  hipLaunchKernelGGL(k_upd_clear, dim3(1), dim3(256), 0, s, static_cast<unsigned long long*>(nullptr),
-                     int64_t(0), static_cast<int32_t*>(nullptr), 0, mx);
+  hipLaunchKernelGGL(k_upd_clear, dim3(1), dim3(256), 0, s, static_cast<int32_t*>(nullptr), 0, mx);
   CSC_TRY(launch_maxabs(F, f_dt, ldf, n, d, mx, s));
   const int64_t nparts = assign_parts(n, d, k, F, f_dt, ldf);
   for (int it = 0; it <= iters; ++it) {

@@ -142,6 +142,58 @@ def test_update_matches_oracle(csc, n, d, k, dtype):
     assert torch.equal(Cg, Cg3)
 
 
+def _fixed_point_centroids(F64, lab, k, C0):
+    """The update's arithmetic written out in numpy: each value rounded half to even to a
+    multiple of 2^-S (S = 62 - e - ceil(log2 n), kept within [-60, 120], max |F| < 2^e), the
+    integers of each label added exactly, the sum scaled back in FP64, divided by the count
+    and rounded once to FP32; labels outside [0, k) ignored, empty clusters unchanged."""
+    n = F64.shape[0]
+    _, e = np.frexp(np.float32(np.abs(F64).max()))
+    S = int(np.clip(62 - int(e) - (n - 1).bit_length(), -60, 120))
+    ok = (lab >= 0) & (lab < k)
+    lv = lab[ok]
+    order = np.argsort(lv, kind="stable")
+    y = np.rint(np.ldexp(F64[ok][order], S)).astype(np.int64)
+    cnt = np.bincount(lv, minlength=k)
+    C = C0.copy()
+    nz = np.flatnonzero(cnt)
+    starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])[nz]
+    sums = np.add.reduceat(y, starts, axis=0)
+    C[nz] = (np.ldexp(sums.astype(np.float64), -S) / cnt[nz, None]).astype(np.float32)
+    return C, cnt
+
+
+@pytest.mark.parametrize("n,d,k,dtype,ld_pad", [(600000, 256, 200, torch.bfloat16, 0),
+                                                (100003, 128, 3, torch.float32, 0),
+                                                (3000, 256, 200, torch.float32, 0),
+                                                (9001, 50, 20, torch.bfloat16, 0),
+                                                (20000, 17, 5, torch.float32, 3)])
+def test_update_sums_are_exact_fixed_point(csc, n, d, k, dtype, ld_pad):
+    """The Lloyd update (Sec. 2.1, the update step of k-means) returns, bit for bit, the means
+    of the 64-bit fixed-point sums: large n with FP64 runs inside a chunk, small n with each
+    value converted on its own, labels of 30 000+ rows over many chunks, masked rows (d = 50,
+    d = 17 with a leading dimension of d + 3), out-of-range labels and an empty cluster."""
+    say(f"kmeans update exact n={n} d={d} k={k} {dtype} ld=d+{ld_pad}")
+    rng = np.random.default_rng(n + k)
+    F = torch.from_numpy(_mixture(n, d, k, seed=n + 7)).to(dtype)
+    lab = rng.integers(0, k, size=n).astype(np.int32)
+    lab[lab == k - 1] = 0  # cluster k - 1 empty: keeps its previous centroid
+    lab[rng.choice(n, size=n // 100, replace=False)] = -1
+    lab[rng.choice(n, size=n // 100, replace=False)] = k
+    C0 = rng.standard_normal((k, d)).astype(np.float32)
+    ref, rcnt = _fixed_point_centroids(F.double().numpy(), lab, k, C0)
+    if ld_pad:
+        Fg = torch.zeros((n, d + ld_pad), dtype=dtype, device="cuda")
+        Fg[:, :d] = F.cuda()
+        Fg = Fg[:, :d]
+    else:
+        Fg = F.cuda()
+    Cg = torch.from_numpy(C0.copy()).cuda()
+    counts = csc.kmeans_update(Fg, torch.from_numpy(lab).cuda(), Cg)
+    assert np.array_equal(counts.cpu().numpy(), rcnt)
+    assert np.array_equal(Cg.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
 @pytest.mark.parametrize("n,d,k,dtype", [(3000, 16, 6, torch.float32), (50000, 64, 20, torch.float32),
                                          (3000, 200, 8, torch.float32),
                                          (20011, 128, 40, torch.bfloat16),
