@@ -364,8 +364,11 @@ inline size_t mf_lds_bytes(int DP, int kc_max) {
 // several LDS chunks: each staged chunk then serves 16 WV T rows, dividing the re-staging
 // traffic; the registers of T = 2 allow one such block per CU, the same eight waves as two
 // blocks of four).
+// The one-tile kernels up to 128 columns are held to four waves per SIMD (at most 128
+// registers, no spills): the latency of their row loads and LDS reads needs the waves.
 template <typename TF, int DP, int T, int WV, bool FULL>
-__global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf, int64_t n, int d,
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(T == 1 && DP <= 128 ? 4 : 1)))
+void k_assign_mf(const TF* F, int64_t ldf, int64_t n, int d,
                                                    const uint16_t* parts, const double* cn_g,
                                                    const float* C, int k, int kp, int kc_max,
                                                    int32_t* labels, float* best_d2,
@@ -615,11 +618,13 @@ __global__ __launch_bounds__(64 * WV) void k_assign_mf(const TF* F, int64_t ldf,
       double best = 0.0;
       // FP64 squared distance from the row to centroid c (the direct form): each lane covers
       // the columns s * 32 + 8 lq + i of the row (just read, so cached) and of the centroid,
-      // four 32-column steps per round with their loads in flight together; the four lanes of
-      // the row then add their sums.
+      // SG 32-column steps per round with their loads in flight together (two in the one-tile
+      // kernels, whose registers are kept for occupancy); the four lanes of the row then add
+      // their sums.
       auto dist_to = [&](int c) -> double {
         const float* crow = C + static_cast<int64_t>(c) * d;
-        constexpr int SG = NS < 4 ? NS : 4;
+        constexpr int SG0 = T == 1 ? 2 : 4;
+        constexpr int SG = NS < SG0 ? NS : SG0;
         double e = 0.0;
 #pragma unroll 1
         for (int s0 = 0; s0 < NS; s0 += SG) {
