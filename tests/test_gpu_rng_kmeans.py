@@ -167,7 +167,9 @@ def _fixed_point_centroids(F64, lab, k, C0):
                                                 (100003, 128, 3, torch.float32, 0),
                                                 (3000, 256, 200, torch.float32, 0),
                                                 (9001, 50, 20, torch.bfloat16, 0),
-                                                (20000, 17, 5, torch.float32, 3)])
+                                                (20000, 17, 5, torch.float32, 3),
+                                                (2000, 32, 1, torch.float32, 0),
+                                                (511, 8, 3, torch.bfloat16, 0)])
 def test_update_sums_are_exact_fixed_point(csc, n, d, k, dtype, ld_pad):
     """The Lloyd update (Sec. 2.1, the update step of k-means) returns, bit for bit, the means
     of the 64-bit fixed-point sums: large n with FP64 runs inside a chunk, small n with each
@@ -177,7 +179,8 @@ def test_update_sums_are_exact_fixed_point(csc, n, d, k, dtype, ld_pad):
     rng = np.random.default_rng(n + k)
     F = torch.from_numpy(_mixture(n, d, k, seed=n + 7)).to(dtype)
     lab = rng.integers(0, k, size=n).astype(np.int32)
-    lab[lab == k - 1] = 0  # cluster k - 1 empty: keeps its previous centroid
+    if k > 1:
+        lab[lab == k - 1] = 0  # cluster k - 1 empty: keeps its previous centroid
     lab[rng.choice(n, size=n // 100, replace=False)] = -1
     lab[rng.choice(n, size=n // 100, replace=False)] = k
     C0 = rng.standard_normal((k, d)).astype(np.float32)
@@ -192,6 +195,19 @@ def test_update_sums_are_exact_fixed_point(csc, n, d, k, dtype, ld_pad):
     counts = csc.kmeans_update(Fg, torch.from_numpy(lab).cuda(), Cg)
     assert np.array_equal(counts.cpu().numpy(), rcnt)
     assert np.array_equal(Cg.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
+def test_update_without_valid_labels_keeps_centroids(csc):
+    """Every label outside [0, k): no cluster has a row, so every centroid stays as it was
+    and every count is zero (no chunk to sum)."""
+    n, d, k = 3000, 40, 7
+    F = torch.from_numpy(_mixture(n, d, k, seed=11)).cuda()
+    lab = np.where(np.arange(n) % 2 == 0, -1, k).astype(np.int32)
+    C0 = np.random.default_rng(12).standard_normal((k, d)).astype(np.float32)
+    Cg = torch.from_numpy(C0.copy()).cuda()
+    counts = csc.kmeans_update(F, torch.from_numpy(lab).cuda(), Cg)
+    assert np.array_equal(counts.cpu().numpy(), np.zeros(k, dtype=np.int32))
+    assert np.array_equal(Cg.cpu().numpy(), C0)
 
 
 @pytest.mark.parametrize("n,d,k,dtype", [(3000, 16, 6, torch.float32), (50000, 64, 20, torch.float32),
