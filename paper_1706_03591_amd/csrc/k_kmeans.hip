@@ -1342,9 +1342,10 @@ csc_status check_f(const void* F, csc_dtype f_dt, int64_t ldf, int64_t n, int d,
   if (d > 256) return fail(CSC_E_ARG, "d must be <= 256");
   if (k < 1) return fail(CSC_E_ARG, "need k >= 1");
   if (need_k_le_n && k > n) return fail(CSC_E_ARG, "seeding needs k <= n");
-  // (the Lloyd update keeps k fixed-point sums of a 32-column group and k counts in LDS)
+  // (the update's label scan takes one thread per label, and its label histograms and the
+  // allocation-free assignment's static centroid array are sized for 240 labels)
   if (k > 240) return fail(CSC_E_ARG, "k must be <= 240");
-  static_assert(240 * (32 * 8 + 4) <= 62 * 1024, "update LDS");
+  static_assert(240 <= kThreads, "one scan thread per label");
   return CSC_OK;
 }
 
