@@ -817,26 +817,16 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
     CSC_HIP(hipEventRecord(st->ev_start, s));
     CSC_HIP(hipStreamWaitEvent(fs, st->ev_start, 0));
   }
-  // fresh signals of batch b into its buffer's signal slots, on stream strm
-  auto draw = [&](int b, hipStream_t strm) -> csc_status {
-    const int j = i0 + b * st->batch;
-    const int nb = std::min(st->batch, S - j);
-    const int buf = pipe ? (b & 1) : 0;
-    for (int q = 0; q < nb; ++q)
-      CSC_TRY(draw_signals(st, t0 + 1 + (j - i0) + q, buf * st->batch + q, strm));
-    return CSC_OK;
-  };
   auto issue = [&](int b) -> csc_status {
     const int j = i0 + b * st->batch;
     const int nb = std::min(st->batch, S - j);
     const int buf = pipe ? (b & 1) : 0;
-    // two buffers, from the third batch on: the signals were drawn on the caller's stream once
-    // the batch two before had finished with this buffer, and ev_free follows that draw (so
-    // the recurrence stream goes from one recurrence straight to the next)
     if (pipe && b >= 2) CSC_HIP(hipStreamWaitEvent(fs, st->ev_free[buf], 0));
-    else CSC_TRY(draw(b, fs));
     const Graph* gs[8];
-    for (int q = 0; q < nb; ++q) gs[q] = &graphs[j + q]->g;
+    for (int q = 0; q < nb; ++q) {
+      gs[q] = &graphs[j + q]->g;
+      CSC_TRY(draw_signals(st, t0 + 1 + (j - i0) + q, buf * st->batch + q, fs));
+    }
     CSC_TRY(batch_basis(st, gs, nb, fs, buf));
     if (pipe || early) CSC_HIP(hipEventRecord(st->ev_basis[buf], fs));
     return CSC_OK;
@@ -864,11 +854,7 @@ csc_status dyn_steps(csc_dyn st, const csc_graph* graphs, int S, int32_t* const*
         CSC_TRY(step_impl(st, &graphs[j + q]->g, buf * st->batch + q, true, labels[j + q], l, r,
                           c, s, hand_over ? next : std::function<csc_status()>()));
       }
-      if (pipe) {
-        // this buffer's signal and basis slots are free: the signals of batch b + 2 go there
-        if (b + 2 < nbatch) CSC_TRY(draw(b + 2, s));
-        CSC_HIP(hipEventRecord(st->ev_free[buf], s));
-      }
+      if (pipe) CSC_HIP(hipEventRecord(st->ev_free[buf], s));
       if (!pipe && !early && b + 1 < nbatch) CSC_TRY(issue(b + 1));
     }
     return CSC_OK;
